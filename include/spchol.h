@@ -1,0 +1,212 @@
+/*
+ * spchol.h -- C ABI of an MI355X (gfx950) supernodal sparse Cholesky library.
+ *
+ * The method is the right-looking supernodal factorization of a sparse
+ * symmetric positive definite matrix A = L L^T (Sec. II of "GPU Accelerated
+ * Sparse Cholesky Factorization", Karsavuran, Ng and Peyton): for every
+ * supernode J, leaves to root, a dense Cholesky of its diagonal block, a
+ * triangular solve of its off-diagonal panel, then the update L_RJ L_RJ^T
+ * scattered through relative indices into the ancestor supernodes it touches
+ * (Sec. II-A, Fig. 2).  The triangular solves (Sec. I) and the
+ * log-determinant follow.  All numeric work runs in HIP kernels on one GPU;
+ * the factor stays resident in device memory.
+ *
+ * Conventions for every entry point
+ *  - Indices are 0-based.  A matrix is given by its lower triangle, diagonal
+ *    included, in compressed-column form: colptr[n+1], rowind[colptr[n]],
+ *    rows strictly increasing inside each column, every row >= its column,
+ *    every diagonal entry present.  vals follow rowind's order.
+ *  - perm[k] is the original index eliminated k-th (NULL = identity).  The
+ *    factor is that of C = P A P^T with C_kk' = A_{perm[k], perm[k']}.
+ *  - "host" pointers are read during the call only.  "device" pointers are
+ *    hipMalloc'ed (coarse-grained) device memory owned by the caller; they
+ *    must stay valid until the work enqueued on `stream` has completed.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued asynchronously on it; only the calls that return a
+ *    host value (spchol_factor's info, spchol_logdet) synchronize it.
+ *  - Handles are owned by the library and freed with their destroy call.
+ *    A spchol_num keeps a reference to its spchol_sym: destroy the num
+ *    first.  Handles may be used from one host thread at a time.
+ *  - On error the status is negative, outputs are unspecified, handles stay
+ *    valid and spchol_last_error() returns a message (thread-local).
+ *  - No C++ exception crosses this boundary.
+ */
+#ifndef SPCHOL_H
+#define SPCHOL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spchol_sym_s *spchol_sym; /* symbolic analysis (host + device copy) */
+typedef struct spchol_num_s *spchol_num; /* numeric factor (device memory)        */
+
+typedef enum {
+  SPCHOL_OK = 0,
+  SPCHOL_ERR_ARG = -1,     /* null or inconsistent argument               */
+  SPCHOL_ERR_PATTERN = -2, /* unsorted/duplicate/upper entry, no diagonal */
+  SPCHOL_ERR_NOT_SPD = -3, /* a pivot was not positive (see info)         */
+  SPCHOL_ERR_OOM = -4,     /* host or device allocation failed            */
+  SPCHOL_ERR_HIP = -5,     /* a HIP runtime call failed                   */
+  SPCHOL_ERR_NOCONV = -6   /* iterative refinement did not converge       */
+} spchol_status;
+
+/* Supernode partition (Sec. I: columns with the same structure form a
+ * dense submatrix).  FUNDAMENTAL: column j+1 joins j's supernode when j is
+ * its only etree child and struct(L_j) \ {j} = struct(L_{j+1}).  MAXIMAL:
+ * the only-child condition is dropped (the partition drawn in Fig. 1). */
+enum { SPCHOL_SNODE_FUNDAMENTAL = 0, SPCHOL_SNODE_MAXIMAL = 1 };
+
+typedef struct {
+  int32_t snode_mode;      /* SPCHOL_SNODE_*                                    */
+  int32_t amalg_max_zeros; /* relaxed amalgamation (Sec. IV-A merges a supernode
+                              with its parent): a supernode is merged into its
+                              parent when the parent's columns follow right after
+                              its own and the merged dense storage holds at most
+                              this many explicit zeros per column; 0 = off      */
+  int32_t panel_width;     /* columns per factorization panel (0 = default 64,
+                              must be a multiple of 16 and <= 64)              */
+  int32_t reserved;
+} spchol_options;
+
+/* Fill *opt with the defaults (fundamental, no amalgamation, panel 64). */
+spchol_status spchol_default_options(spchol_options *opt);
+
+/* Symbolic analysis (host only, no device work): elimination tree (Sec. II),
+ * column counts, supernode partition and amalgamation, supernodal elimination
+ * tree (Fig. 1), row lists, relative indices relind(J, P) (Sec. II-A), the map
+ * from A's entries to factor storage, and the leaves-to-root level schedule.
+ *   n, colptr, rowind: host, lower CSC pattern of A (see conventions).
+ *   perm: host, n entries or NULL.
+ *   opt: host or NULL (defaults).
+ *   out: receives a new handle.
+ * Errors: SPCHOL_ERR_ARG (n < 0, null pointer, perm not a permutation),
+ * SPCHOL_ERR_PATTERN (pattern violates the conventions), SPCHOL_ERR_OOM. */
+spchol_status spchol_analyze(int64_t n, const int64_t *colptr, const int64_t *rowind,
+                             const int64_t *perm, const spchol_options *opt, spchol_sym *out);
+
+/* Summary of a symbolic analysis (host output). */
+typedef struct {
+  int64_t n;
+  int64_t nnz_a;        /* stored lower entries of A                          */
+  int64_t nnz_l;        /* true nonzeros of L (sum of column counts)         */
+  int64_t storage;      /* doubles of supernodal storage (sum m_J * k_J)     */
+  int64_t nsuper;       /* supernodes after amalgamation                      */
+  int64_t nrows_total;  /* sum of supernode row-list lengths m_J              */
+  int64_t npairs;       /* (J, P) pairs: J updates ancestor P                 */
+  int64_t nrelind;      /* total relative-index entries                       */
+  int64_t nlevels;      /* height of the supernodal elimination tree          */
+  int64_t max_k, max_m; /* largest supernode width and row count              */
+  double flops_alg;     /* sum_j c_j^2 over true column counts               */
+  double flops_exec;    /* the same over the amalgamated (stored) structure  */
+} spchol_sym_info_t;
+
+spchol_status spchol_sym_info(spchol_sym sym, spchol_sym_info_t *info);
+
+/* Export the structure to caller-owned host arrays (any may be NULL):
+ *   parent[n]            column elimination tree of C (-1 = root)
+ *   count[n]             column counts c_j of L (diagonal included)
+ *   super_ptr[nsuper+1]  first column of each supernode
+ *   sparent[nsuper]      supernodal elimination tree (-1 = root)
+ *   row_ptr[nsuper+1], row_idx[nrows_total]   sorted row list of each supernode
+ *   pair_J[npairs], pair_P[npairs]            J updates ancestor P (J ascending,
+ *                                             then P ascending)
+ *   pair_a0[npairs]      index, among J's off-diagonal rows, of the first row
+ *                        lying in P's columns
+ *   relind_ptr[npairs+1], relind[nrelind]     relind(J, P) for J's off-diagonal
+ *                        rows from pair_a0 on: the distance of the row from the
+ *                        bottom of P's row list, i.e. m_P - 1 - position
+ *                        (Sec. II-A; positional reading of Fig. 1's example)
+ *   level[nsuper]        leaves-to-root level of each supernode              */
+spchol_status spchol_sym_export(spchol_sym sym, int64_t *parent, int64_t *count,
+                                int64_t *super_ptr, int64_t *sparent, int64_t *row_ptr,
+                                int64_t *row_idx, int64_t *pair_J, int64_t *pair_P,
+                                int64_t *pair_a0, int64_t *relind_ptr, int32_t *relind,
+                                int64_t *level);
+
+/* Storage layout of the factor: supernode J is a dense column-major
+ * m_J x k_J array at offset storage_off[J] (doubles) with leading dimension
+ * m_J; its rows are row_idx[row_ptr[J] ...] (Sec. II-A stores each
+ * supernode as a dense array).  The upper triangle of the diagonal block is
+ * zero.  storage_off has nsuper+1 entries (host). */
+spchol_status spchol_sym_storage(spchol_sym sym, int64_t *storage_off);
+
+/* Numeric factorization (Sec. II-A, RL): scatter A's values into zeroed
+ * supernodal storage, then per level and panel: dense Cholesky of the
+ * diagonal block, triangular solve of the panel, and the update of the
+ * remaining columns and of the ancestors through relative indices.
+ *   vals_dev: device, fp64, colptr[n] entries in rowind's order.
+ *   out: receives a new numeric handle holding L in device memory.
+ *   info: host; 0 on success, else the 1-based permuted column of the
+ *         smallest column whose pivot was not positive (or NaN); the status
+ *         is then SPCHOL_ERR_NOT_SPD and *out is still created.
+ * Synchronizes `stream` once to read the pivot status. */
+spchol_status spchol_factor(spchol_sym sym, const double *vals_dev, void *stream,
+                            spchol_num *out, int64_t *info);
+
+/* Re-run the numeric factorization into an existing handle (same pattern,
+ * new values), without reallocating.  Same semantics as spchol_factor. */
+spchol_status spchol_refactor(spchol_num num, const double *vals_dev, void *stream,
+                              int64_t *info);
+
+/* Solve A X = B in place.  B_dev: device, n x nrhs column-major, leading
+ * dimension ldb >= n, original (unpermuted) ordering.  Forward solve with L
+ * leaves to root, backward solve with L^T root to leaves. */
+spchol_status spchol_solve(spchol_num num, double *B_dev, int64_t nrhs, int64_t ldb,
+                           void *stream);
+
+/* log det(A) = 2 sum_j log L_jj, reduced on the device (pairwise tree);
+ * out_host receives the value.  Synchronizes `stream`. */
+spchol_status spchol_logdet(spchol_num num, double *out_host, void *stream);
+
+/* Copy the supernodal storage of L (storage doubles, layout as in
+ * spchol_sym_storage) to caller-owned device memory dst_dev. */
+spchol_status spchol_num_export(spchol_num num, double *dst_dev, void *stream);
+
+/* Per-kernel timing of a numeric handle (HIP events recorded around every
+ * launch on the call's stream while enabled).  Kernel kinds: */
+enum {
+  SPCHOL_KERNEL_FILL = 0,        /* zero fill of the factor storage          */
+  SPCHOL_KERNEL_SCATTER_A = 1,   /* A's values into storage                  */
+  SPCHOL_KERNEL_FACTOR = 2,      /* panel Cholesky + triangular solve        */
+  SPCHOL_KERNEL_UPDATE_INT = 3,  /* update of a supernode's own columns      */
+  SPCHOL_KERNEL_UPDATE_EXT = 4,  /* update scattered into ancestors          */
+  SPCHOL_KERNEL_FWD_TRI = 5,
+  SPCHOL_KERNEL_FWD_GEMV = 6,
+  SPCHOL_KERNEL_BWD_GEMVT = 7,
+  SPCHOL_KERNEL_BWD_TRI = 8,
+  SPCHOL_KERNEL_PERM = 9,        /* solve permutation gather/scatter         */
+  SPCHOL_KERNEL_LOGDET = 10,
+  SPCHOL_KERNEL_KINDS = 11
+};
+
+typedef struct {
+  int64_t launches; /* launches timed                                          */
+  double ms;        /* summed event time                                       */
+  double flops;     /* algorithmic flops of those launches (stored structure)  */
+  double bytes;     /* algorithmic HBM bytes of those launches                 */
+} spchol_kernel_stat;
+
+/* enable != 0 starts collecting (clearing earlier records), 0 stops. */
+spchol_status spchol_profile(spchol_num num, int32_t enable);
+
+/* Synchronize the streams the records were made on, sum the records per
+ * kind into out[SPCHOL_KERNEL_KINDS] (host) and clear them. */
+spchol_status spchol_profile_read(spchol_num num, spchol_kernel_stat *out);
+
+void spchol_sym_destroy(spchol_sym sym);
+void spchol_num_destroy(spchol_num num);
+
+/* Thread-local message for the last failing call on this thread. */
+const char *spchol_last_error(void);
+
+/* Library version string. */
+const char *spchol_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPCHOL_H */

@@ -56,12 +56,12 @@ def lib():
         L.oracle_sym_sizes.argtypes = [C.c_void_p, _i64p]
         L.oracle_sym_get.argtypes = [C.c_void_p] + [C.c_void_p] * 14
         L.oracle_factor.restype = C.c_int64
-        L.oracle_factor.argtypes = [C.c_void_p, _f64p, C.c_int32, _f64p]
+        L.oracle_factor.argtypes = [C.c_void_p, _f64p, C.c_int32, C.c_int64, _f64p]
         L.oracle_solve.argtypes = [C.c_void_p, _f64p, C.c_void_p, C.c_int64, C.c_int64]
         L.oracle_logdet.restype = C.c_double
         L.oracle_logdet.argtypes = [C.c_void_p, _f64p]
         L.oracle_flops.restype = C.c_double
-        L.oracle_flops.argtypes = [C.c_void_p]
+        L.oracle_flops.argtypes = [C.c_void_p, C.c_int64]
         _lib = L
     return _lib
 
@@ -133,17 +133,22 @@ class Symbolic:
         t = int(idx[0])
         return self.rel[self.relptr[t]:self.relptr[t + 1]]
 
-    def flops(self) -> float:
-        return float(lib().oracle_flops(self._h))
+    def flops(self, ncols: int = -1) -> float:
+        """sum_j c_j^2 over the first ncols columns (all by default)."""
+        return float(lib().oracle_flops(self._h, int(ncols)))
 
     # --- numeric -----------------------------------------------------------
-    def factor(self, vals, variant: int = 0) -> "Factor":
+    def factor(self, vals, variant: int = 0, ncols: int = -1) -> "Factor":
+        """variant 0 left-looking, 1 up-looking.  ncols >= 0 (left-looking)
+        computes only the first ncols columns, which are then final."""
         vals = np.ascontiguousarray(vals, dtype=np.float64)
         if vals.size != self.nnzA:
             raise OracleError("values length does not match the pattern")
         lv = np.zeros(max(self.nnzL, 1), np.float64)
-        info = int(lib().oracle_factor(self._h, vals if vals.size else np.zeros(1), int(variant), lv))
-        return Factor(self, lv[: self.nnzL], info, vals)
+        info = int(lib().oracle_factor(self._h, vals if vals.size else np.zeros(1), int(variant), int(ncols), lv))
+        f = Factor(self, lv[: self.nnzL], info, vals)
+        f.ncols = self.n if ncols < 0 else min(int(ncols), self.n)
+        return f
 
 
 class Factor:
@@ -151,6 +156,8 @@ class Factor:
         self.sym, self.lv, self.info, self.vals = sym, lv, info, vals
 
     def require_ok(self):
+        if getattr(self, "ncols", self.sym.n) < self.sym.n:
+            raise OracleError("partial factor: only the leading columns were computed")
         if self.info != 0:
             raise OracleError(f"not positive definite at (permuted, 1-based) column {self.info}")
 

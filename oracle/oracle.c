@@ -400,7 +400,7 @@ static double *permuted_values(const osym *s, const double *vals) {
  * L_jj = sqrt(x_j) and L_ij = x_i / L_jj.  The columns k with L_jk != 0 are
  * found with per-row linked lists of "next row to be touched" pointers.
  * Returns 0, or 1 + the first column whose pivot is not positive. */
-static int64_t factor_left(const osym *s, const double *cv, double *lv) {
+static int64_t factor_left(const osym *s, const double *cv, double *lv, int64_t ncols) {
   int64_t n = s->n;
   double *x = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
   int64_t *head = (int64_t *)malloc((size_t)(n ? n : 1) * sizeof(int64_t));
@@ -408,7 +408,7 @@ static int64_t factor_left(const osym *s, const double *cv, double *lv) {
   int64_t *nextp = (int64_t *)malloc((size_t)(n ? n : 1) * sizeof(int64_t));
   for (int64_t j = 0; j < n; ++j) head[j] = -1;
   int64_t info = 0;
-  for (int64_t j = 0; j < n && !info; ++j) {
+  for (int64_t j = 0; j < ncols && !info; ++j) {
     for (int64_t p = s->cptr[j]; p < s->cptr[j + 1]; ++p) x[s->crow[p]] += cv[p];
     int64_t k = head[j];
     while (k != -1) {
@@ -498,12 +498,15 @@ static int64_t factor_up(const osym *s, const double *cv, double *lv) {
 
 /* variant 0: left-looking, 1: up-looking.  lv has nnz(L) entries in the
  * order of (lptr, lrow).  Returns 0 or 1-based failing (permuted) column;
- * -1 on allocation failure. */
-int64_t oracle_factor(const osym *s, const double *vals, int32_t variant, double *lv) {
+ * -1 on allocation failure.  ncols >= 0 (left-looking only) stops after the
+ * first ncols columns: column j depends only on columns k < j, so those
+ * columns are final (the rest of lv stays zero). */
+int64_t oracle_factor(const osym *s, const double *vals, int32_t variant, int64_t ncols, double *lv) {
   double *cv = permuted_values(s, vals);
   if (!cv) return -1;
   memset(lv, 0, (size_t)s->lptr[s->n] * sizeof(double));
-  int64_t info = variant == 1 ? factor_up(s, cv, lv) : factor_left(s, cv, lv);
+  if (ncols < 0 || ncols > s->n) ncols = s->n;
+  int64_t info = variant == 1 ? factor_up(s, cv, lv) : factor_left(s, cv, lv, ncols);
   free(cv);
   return info;
 }
@@ -545,9 +548,11 @@ double oracle_logdet(const osym *s, const double *lv) {
   return r;
 }
 
-/* Algorithmic flops sum_j c_j^2 (column Cholesky with sqrt counted once). */
-double oracle_flops(const osym *s) {
+/* Algorithmic flops sum_{j < ncols} c_j^2 (column Cholesky with sqrt
+ * counted once; ncols < 0 = all columns). */
+double oracle_flops(const osym *s, int64_t ncols) {
   double f = 0.0;
-  for (int64_t j = 0; j < s->n; ++j) f += (double)s->count[j] * (double)s->count[j];
+  if (ncols < 0 || ncols > s->n) ncols = s->n;
+  for (int64_t j = 0; j < ncols; ++j) f += (double)s->count[j] * (double)s->count[j];
   return f;
 }

@@ -1,0 +1,219 @@
+"""MI355X-native supernodal sparse Cholesky (right-looking, Sec. II-A).
+
+Thin Python binding over the C ABI of ``libspchol.so`` (include/spchol.h):
+argument marshalling only.  Every numeric step runs in the library's HIP
+kernels; torch supplies device memory and streams.  If the library is not
+built, using it raises ``LibraryMissing`` -- there is no CPU fallback.
+
+    S = SparseCholesky(n, colptr, rowind, perm, amalg_max_zeros=8)
+    F = S.factor(vals_dev)           # torch.float64 CUDA tensor, nnz(A) values
+    x = F.solve(b_dev)               # (n,) or (n, nrhs)
+    ld = F.logdet()
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _capi as capi
+from ._capi import LibraryMissing
+
+__all__ = ["SparseCholesky", "Factor", "SpcholError", "NotPositiveDefinite", "LibraryMissing",
+           "version", "lib"]
+
+
+def lib():
+    return capi.lib()
+
+
+def version() -> str:
+    return capi.lib().spchol_version().decode()
+
+
+class SpcholError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{capi.STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class NotPositiveDefinite(SpcholError):
+    def __init__(self, status, message, info):
+        super().__init__(status, message)
+        self.info = info
+
+
+def _check(rc):
+    if rc != 0:
+        msg = capi.lib().spchol_last_error()
+        raise SpcholError(rc, msg.decode() if msg else "")
+
+
+def _hptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_f64(t, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{what} must be a float64 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class SparseCholesky:
+    """Symbolic analysis of a sparse SPD pattern (host), bound to the device
+    of its first factorization."""
+
+    def __init__(self, n, colptr, rowind, perm=None, snode_mode=0, amalg_max_zeros=0, panel_width=64):
+        L = capi.lib()
+        self.n = int(n)
+        self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
+        self._rowind = np.ascontiguousarray(rowind, dtype=np.int64)
+        self._perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
+        opts = capi.Options(int(snode_mode), int(amalg_max_zeros), int(panel_width), 0)
+        h = C.c_void_p()
+        _check(L.spchol_analyze(self.n, _hptr(self._colptr), _hptr(self._rowind), _hptr(self._perm),
+                                C.byref(opts), C.byref(h)))
+        self._h = h
+        self.nnz_a = int(self._colptr[-1]) if self._colptr.size else 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            capi.lib().spchol_sym_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        s = capi.SymInfo()
+        _check(capi.lib().spchol_sym_info(self._h, C.byref(s)))
+        return {name: getattr(s, name) for name, _ in s._fields_}
+
+    def export(self) -> dict:
+        """Structure arrays (host numpy), names as in spchol_sym_export."""
+        inf = self.info()
+        n, ns, npairs = inf["n"], inf["nsuper"], inf["npairs"]
+        out = dict(parent=np.zeros(n, np.int64), count=np.zeros(n, np.int64),
+                   super_ptr=np.zeros(ns + 1, np.int64), sparent=np.zeros(ns, np.int64),
+                   row_ptr=np.zeros(ns + 1, np.int64), row_idx=np.zeros(inf["nrows_total"], np.int64),
+                   pair_J=np.zeros(npairs, np.int64), pair_P=np.zeros(npairs, np.int64),
+                   pair_a0=np.zeros(npairs, np.int64), relind_ptr=np.zeros(npairs + 1, np.int64),
+                   relind=np.zeros(inf["nrelind"], np.int32), level=np.zeros(ns, np.int64))
+        keys = ["parent", "count", "super_ptr", "sparent", "row_ptr", "row_idx", "pair_J", "pair_P",
+                "pair_a0", "relind_ptr", "relind", "level"]
+        _check(capi.lib().spchol_sym_export(self._h, *[_hptr(out[k]) for k in keys]))
+        return out
+
+    def storage_offsets(self) -> np.ndarray:
+        inf = self.info()
+        off = np.zeros(inf["nsuper"] + 1, np.int64)
+        _check(capi.lib().spchol_sym_storage(self._h, _hptr(off)))
+        return off
+
+    def factor(self, vals, stream=None, check=True) -> "Factor":
+        """Numeric factorization of the values `vals` (float64 CUDA tensor in
+        the pattern's entry order).  Raises NotPositiveDefinite (with .info,
+        the 1-based permuted column) when check is set."""
+        if vals.numel() != self.nnz_a:
+            raise ValueError("vals has the wrong length")
+        h = C.c_void_p()
+        info = C.c_int64(0)
+        rc = capi.lib().spchol_factor(self._h, _dev_f64(vals, "vals"), _stream_ptr(stream), C.byref(h),
+                                      C.byref(info))
+        F = Factor(self, h) if h.value else None
+        if rc == -3:
+            if F is not None:
+                F.info = int(info.value)
+            if check:
+                raise NotPositiveDefinite(rc, capi.lib().spchol_last_error().decode(), int(info.value))
+            return F
+        _check(rc)
+        F.info = 0
+        return F
+
+
+class Factor:
+    """Numeric factor held in device memory."""
+
+    def __init__(self, sym: SparseCholesky, h):
+        self.sym = sym
+        self._h = h
+        self.info = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            capi.lib().spchol_num_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def refactor(self, vals, stream=None, check=True) -> int:
+        info = C.c_int64(0)
+        rc = capi.lib().spchol_refactor(self._h, _dev_f64(vals, "vals"), _stream_ptr(stream), C.byref(info))
+        self.info = int(info.value)
+        if rc == -3 and not check:
+            return self.info
+        if rc == -3:
+            raise NotPositiveDefinite(rc, capi.lib().spchol_last_error().decode(), self.info)
+        _check(rc)
+        return 0
+
+    def solve_(self, Bt, stream=None):
+        """In place on a (nrhs, n) contiguous float64 CUDA tensor, i.e. an
+        n x nrhs column-major block with leading dimension n."""
+        nrhs = Bt.shape[0] if Bt.dim() == 2 else 1
+        _check(capi.lib().spchol_solve(self._h, _dev_f64(Bt, "B"), nrhs, self.sym.n, _stream_ptr(stream)))
+        return Bt
+
+    def solve(self, B, stream=None):
+        """Return A^{-1} B for B of shape (n,) or (n, nrhs)."""
+        if B.dim() == 1:
+            X = B.contiguous().clone()
+            return self.solve_(X.view(1, -1), stream).view(-1)
+        Xt = B.t().contiguous()
+        self.solve_(Xt, stream)
+        return Xt.t()
+
+    def logdet(self, stream=None) -> float:
+        out = C.c_double(0.0)
+        _check(capi.lib().spchol_logdet(self._h, C.byref(out), _stream_ptr(stream)))
+        return float(out.value)
+
+    def profile(self, enable: bool = True):
+        """Start (clearing earlier records) or stop per-launch event timing."""
+        _check(capi.lib().spchol_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """Per kernel kind: launches, ms, flops, bytes summed over the records
+        since profile(True); synchronizes and clears them."""
+        arr = (capi.KernelStat * len(capi.KERNEL_KINDS))()
+        _check(capi.lib().spchol_profile_read(self._h, arr))
+        return {name: dict(launches=arr[i].launches, ms=arr[i].ms, flops=arr[i].flops, bytes=arr[i].bytes)
+                for i, name in enumerate(capi.KERNEL_KINDS)}
+
+    def storage(self, stream=None):
+        """Copy of the supernodal storage of L (float64 CUDA tensor)."""
+        import torch
+        n = int(self.sym.info()["storage"])
+        out = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+        _check(capi.lib().spchol_num_export(self._h, C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out[:n]

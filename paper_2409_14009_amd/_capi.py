@@ -1,0 +1,77 @@
+"""ctypes declarations of the C ABI in include/spchol.h (marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libspchol.so")
+
+i64, i32, f64, vp = C.c_int64, C.c_int32, C.c_double, C.c_void_p
+i64p, i32p, f64p = C.POINTER(i64), C.POINTER(i32), C.POINTER(f64)
+
+STATUS = {
+    0: "SPCHOL_OK", -1: "SPCHOL_ERR_ARG", -2: "SPCHOL_ERR_PATTERN", -3: "SPCHOL_ERR_NOT_SPD",
+    -4: "SPCHOL_ERR_OOM", -5: "SPCHOL_ERR_HIP", -6: "SPCHOL_ERR_NOCONV",
+}
+
+
+class Options(C.Structure):
+    _fields_ = [("snode_mode", i32), ("amalg_max_zeros", i32), ("panel_width", i32), ("reserved", i32)]
+
+
+class SymInfo(C.Structure):
+    _fields_ = [("n", i64), ("nnz_a", i64), ("nnz_l", i64), ("storage", i64), ("nsuper", i64),
+                ("nrows_total", i64), ("npairs", i64), ("nrelind", i64), ("nlevels", i64),
+                ("max_k", i64), ("max_m", i64), ("flops_alg", f64), ("flops_exec", f64)]
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("launches", i64), ("ms", f64), ("flops", f64), ("bytes", f64)]
+
+
+KERNEL_KINDS = ["fill", "scatter_a", "factor", "update_int", "update_ext", "fwd_tri", "fwd_gemv",
+                "bwd_gemvt", "bwd_tri", "perm", "logdet"]
+
+# name -> (restype, argtypes)
+PROTOTYPES = {
+    "spchol_default_options": (i32, [C.POINTER(Options)]),
+    "spchol_analyze": (i32, [i64, vp, vp, vp, C.POINTER(Options), C.POINTER(vp)]),
+    "spchol_sym_info": (i32, [vp, C.POINTER(SymInfo)]),
+    "spchol_sym_export": (i32, [vp] + [vp] * 12),
+    "spchol_sym_storage": (i32, [vp, vp]),
+    "spchol_factor": (i32, [vp, vp, vp, C.POINTER(vp), i64p]),
+    "spchol_refactor": (i32, [vp, vp, vp, i64p]),
+    "spchol_solve": (i32, [vp, vp, i64, i64, vp]),
+    "spchol_logdet": (i32, [vp, f64p, vp]),
+    "spchol_num_export": (i32, [vp, vp, vp]),
+    "spchol_profile": (i32, [vp, i32]),
+    "spchol_profile_read": (i32, [vp, C.POINTER(KernelStat)]),
+    "spchol_sym_destroy": (None, [vp]),
+    "spchol_num_destroy": (None, [vp]),
+    "spchol_last_error": (C.c_char_p, []),
+    "spchol_version": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+class LibraryMissing(ImportError):
+    pass
+
+
+def lib():
+    """The loaded HIP library.  There is no fallback: if libspchol.so is not
+    built this raises (build it with __graft_entry__.build() or
+    python -m paper_2409_14009_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing(f"{LIB_PATH} is not built; run python -m paper_2409_14009_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in PROTOTYPES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib

@@ -1,0 +1,451 @@
+// Symbolic analysis for the right-looking supernodal Cholesky.
+//
+// Steps (host, linear or near-linear in the size of L's supernodal
+// structure):
+//   1. C = P A P^T, lower pattern, by rows and by columns.
+//   2. Elimination tree (Sec. II: the parent of column j is the smallest
+//      off-diagonal row of L_{*,j}) by Liu's algorithm with path compression.
+//   3. Column counts of L by walking each row subtree of the etree.
+//   4. Supernodes (Sec. I): column j+1 continues j's supernode when
+//      parent(j) = j+1 and c_j = c_{j+1} + 1 (then struct(L_j) \ {j} equals
+//      struct(L_{j+1}) by the containment of Sec. II); the fundamental mode
+//      also needs j to be the only child of j+1.
+//   5. Relaxed amalgamation (Sec. IV-A merges supernodes with their parents):
+//      a chain of supernodes is merged into a parent that starts right after
+//      it when the merged dense storage has at most z explicit zeros per
+//      column.  Counted arithmetically from the column counts.
+//   6. Supernodal row lists, the supernodal etree (Fig. 1) and relative
+//      indices relind(J, P) (Sec. II-A): for each ancestor P holding one of
+//      J's off-diagonal rows, the position of J's rows in P's row list.
+//   7. Storage offsets, the map of A's entries into storage, levels and the
+//      batched launch schedule.
+#include "analyze.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+namespace spchol {
+
+namespace {
+
+constexpr int ERR_ARG = -1, ERR_PATTERN = -2, ERR_OOM = -4;
+
+}  // namespace
+
+int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64_t* perm,
+            int snode_mode, int amalg_max_zeros, int panel_width, Symbolic& S, std::string& err) {
+  try {
+    if (n < 0 || !colptr || (n > 0 && !rowind)) { err = "analyze: null pointer or n < 0"; return ERR_ARG; }
+    if (n >= (int64_t(1) << 31) - 1) { err = "analyze: n too large (rows are stored as int32)"; return ERR_ARG; }
+    if (snode_mode != 0 && snode_mode != 1) { err = "analyze: bad snode_mode"; return ERR_ARG; }
+    if (amalg_max_zeros < 0) { err = "analyze: amalg_max_zeros < 0"; return ERR_ARG; }
+    int nb = panel_width == 0 ? 64 : panel_width;
+    if (nb < 16 || nb > kMaxPanel || nb % 16) { err = "analyze: panel_width must be 16, 32, 48 or 64"; return ERR_ARG; }
+    S = Symbolic();
+    S.n = n;
+    S.nb = nb;
+    if (colptr[0] != 0) { err = "analyze: colptr[0] != 0"; return ERR_PATTERN; }
+    for (int64_t j = 0; j < n; ++j)
+      if (colptr[j + 1] < colptr[j]) { err = "analyze: colptr not monotone"; return ERR_PATTERN; }
+    const int64_t nz = colptr[n];
+    S.nnzA = nz;
+    for (int64_t j = 0; j < n; ++j) {
+      if (colptr[j] == colptr[j + 1] || rowind[colptr[j]] != j) {
+        err = "analyze: missing diagonal entry in column " + std::to_string(j);
+        return ERR_PATTERN;
+      }
+      for (int64_t p = colptr[j]; p < colptr[j + 1]; ++p) {
+        int64_t i = rowind[p];
+        if (i < j || i >= n) { err = "analyze: entry outside the lower triangle in column " + std::to_string(j); return ERR_PATTERN; }
+        if (p > colptr[j] && i <= rowind[p - 1]) { err = "analyze: rows not strictly increasing in column " + std::to_string(j); return ERR_PATTERN; }
+      }
+    }
+    // ---- permutation ------------------------------------------------------
+    S.perm.resize(n);
+    S.pinv.assign(n, -1);
+    for (int64_t k = 0; k < n; ++k) {
+      int64_t o = perm ? perm[k] : k;
+      if (o < 0 || o >= n || S.pinv[o] != -1) { err = "analyze: perm is not a permutation"; return ERR_ARG; }
+      S.perm[k] = o;
+      S.pinv[o] = k;
+    }
+    // ---- 1. C = P A P^T lower, by rows (strict) and by columns ------------
+    std::vector<int64_t> rp(n + 1, 0), cp(n + 1, 0);
+    for (int64_t j = 0; j < n; ++j)
+      for (int64_t p = colptr[j]; p < colptr[j + 1]; ++p) {
+        int64_t a = S.pinv[rowind[p]], b = S.pinv[j];
+        int64_t r = std::max(a, b), c = std::min(a, b);
+        if (r != c) rp[r + 1]++;
+        cp[c + 1]++;
+      }
+    for (int64_t i = 0; i < n; ++i) { rp[i + 1] += rp[i]; cp[i + 1] += cp[i]; }
+    std::vector<int32_t> rc(rp[n]), cr(cp[n]);
+    {
+      std::vector<int64_t> fr(rp.begin(), rp.end() - 1), fc(cp.begin(), cp.end() - 1);
+      for (int64_t j = 0; j < n; ++j)
+        for (int64_t p = colptr[j]; p < colptr[j + 1]; ++p) {
+          int64_t a = S.pinv[rowind[p]], b = S.pinv[j];
+          int64_t r = std::max(a, b), c = std::min(a, b);
+          if (r != c) rc[fr[r]++] = (int32_t)c;
+          cr[fc[c]++] = (int32_t)r;
+        }
+    }
+    // ---- 2. elimination tree (Liu, path compression) ---------------------
+    S.parent.assign(n, -1);
+    {
+      std::vector<int64_t> anc(n, -1);
+      for (int64_t i = 0; i < n; ++i) {
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+          int64_t r = rc[p];
+          while (anc[r] != -1 && anc[r] != i) {
+            int64_t nx = anc[r];
+            anc[r] = i;
+            r = nx;
+          }
+          if (anc[r] == -1) {
+            anc[r] = i;
+            S.parent[r] = i;
+          }
+        }
+      }
+    }
+    // ---- 3. column counts by row-subtree walks ----------------------------
+    S.count.assign(n, 0);
+    {
+      std::vector<int64_t> mark(n, -1);
+      for (int64_t i = 0; i < n; ++i) {
+        S.count[i] += 1;
+        mark[i] = i;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+          int64_t k = rc[p];
+          while (mark[k] != i) {
+            S.count[k] += 1;
+            mark[k] = i;
+            k = S.parent[k];
+          }
+        }
+      }
+    }
+    for (int64_t j = 0; j < n; ++j) S.flops_alg += double(S.count[j]) * double(S.count[j]);
+    // ---- 4. base supernodes ---------------------------------------------
+    std::vector<int64_t> nchild(n, 0);
+    for (int64_t j = 0; j < n; ++j)
+      if (S.parent[j] >= 0) nchild[S.parent[j]]++;
+    std::vector<int64_t> bptr;
+    bptr.reserve(n + 1);
+    for (int64_t j = 0; j < n; ++j) {
+      bool cont = j > 0 && S.parent[j - 1] == j && S.count[j - 1] == S.count[j] + 1 &&
+                  (snode_mode == 1 || nchild[j] == 1);
+      if (!cont) bptr.push_back(j);
+    }
+    bptr.push_back(n);
+    const int64_t nbase = (int64_t)bptr.size() - 1;
+    std::vector<int64_t> bsn(n);
+    for (int64_t b = 0; b < nbase; ++b)
+      for (int64_t j = bptr[b]; j < bptr[b + 1]; ++j) bsn[j] = b;
+    // ---- 5. amalgamation (arithmetic on counts) ---------------------------
+    // A group is a run of base supernodes ending at base supernode b; its
+    // rows are its columns plus the off-diagonal rows of b, so m = (columns
+    // of the group) + (rows of b below b).  Merging the group into the base
+    // parent p (which starts right after it) gives k = cols(group) + k_p and
+    // m = cols(group) + m_p.
+    std::vector<int64_t> gfirst(nbase), gtrue(nbase);
+    std::vector<char> alive(nbase, 1);
+    for (int64_t b = 0; b < nbase; ++b) {
+      gfirst[b] = bptr[b];
+      int64_t t = 0;
+      for (int64_t j = bptr[b]; j < bptr[b + 1]; ++j) t += S.count[j];
+      gtrue[b] = t;
+    }
+    if (amalg_max_zeros > 0) {
+      const int64_t z = amalg_max_zeros;
+      for (int64_t b = 0; b < nbase; ++b) {
+        int64_t last = bptr[b + 1] - 1;
+        int64_t pc = S.parent[last];
+        if (pc < 0) continue;
+        int64_t p = bsn[pc];
+        if (bptr[p] != last + 1) continue;
+        int64_t gcols = bptr[p] - gfirst[b];
+        int64_t mp = S.count[bptr[p]];  // rows of base supernode p
+        int64_t k = gcols + (bptr[p + 1] - bptr[p]);
+        int64_t m = gcols + mp;
+        int64_t storage = k * m - k * (k - 1) / 2;
+        int64_t zeros = storage - (gtrue[b] + gtrue[p]);
+        if (zeros <= z * k) {
+          gfirst[p] = gfirst[b];
+          gtrue[p] += gtrue[b];
+          alive[b] = 0;
+        }
+      }
+    }
+    // ---- 6. final supernodes, row lists ----------------------------------
+    std::vector<int64_t> fin;  // base supernode that ends each final supernode
+    for (int64_t b = 0; b < nbase; ++b)
+      if (alive[b]) fin.push_back(b);
+    const int64_t ns = (int64_t)fin.size();
+    S.ns = ns;
+    S.sptr.resize(ns + 1);
+    for (int64_t J = 0; J < ns; ++J) S.sptr[J] = gfirst[fin[J]];
+    S.sptr[ns] = n;
+    S.snode_of.resize(n);
+    for (int64_t J = 0; J < ns; ++J)
+      for (int64_t j = S.sptr[J]; j < S.sptr[J + 1]; ++j) S.snode_of[j] = J;
+    S.sparent.resize(ns);
+    for (int64_t J = 0; J < ns; ++J) {
+      int64_t pc = S.parent[S.sptr[J + 1] - 1];
+      S.sparent[J] = pc < 0 ? -1 : S.snode_of[pc];
+    }
+    // Row lists of base supernodes: the columns, the entries of C below the
+    // supernode, and the rows of the child supernodes below it.
+    std::vector<int64_t> brp(nbase + 1, 0);
+    std::vector<int32_t> brows;
+    {
+      std::vector<int64_t> mark(n, -1);
+      std::vector<std::vector<int64_t>> kids(nbase);
+      for (int64_t b = 0; b < nbase; ++b) {
+        int64_t pc = S.parent[bptr[b + 1] - 1];
+        if (pc >= 0) kids[bsn[pc]].push_back(b);
+      }
+      std::vector<int32_t> tmp;
+      for (int64_t b = 0; b < nbase; ++b) {
+        tmp.clear();
+        int64_t f = bptr[b], l = bptr[b + 1] - 1;
+        for (int64_t j = f; j <= l; ++j) { tmp.push_back((int32_t)j); mark[j] = b; }
+        for (int64_t j = f; j <= l; ++j)
+          for (int64_t p = cp[j]; p < cp[j + 1]; ++p) {
+            int64_t i = cr[p];
+            if (i > l && mark[i] != b) { mark[i] = b; tmp.push_back((int32_t)i); }
+          }
+        for (int64_t c : kids[b])
+          for (int64_t p = brp[c]; p < brp[c + 1]; ++p) {
+            int64_t i = brows[p];
+            if (i > l && mark[i] != b) { mark[i] = b; tmp.push_back((int32_t)i); }
+          }
+        std::sort(tmp.begin() + (l - f + 1), tmp.end());
+        if ((int64_t)tmp.size() != S.count[f]) { err = "analyze: internal error (row list vs column count)"; return ERR_PATTERN; }
+        brows.insert(brows.end(), tmp.begin(), tmp.end());
+        brp[b + 1] = (int64_t)brows.size();
+      }
+    }
+    // final row list = the merged columns before the last base supernode,
+    // then that base supernode's rows
+    S.rptr.assign(ns + 1, 0);
+    for (int64_t J = 0; J < ns; ++J) {
+      int64_t b = fin[J];
+      S.rptr[J + 1] = S.rptr[J] + (bptr[b] - S.sptr[J]) + (brp[b + 1] - brp[b]);
+    }
+    S.rows.resize(S.rptr[ns]);
+    for (int64_t J = 0; J < ns; ++J) {
+      int64_t b = fin[J], q = S.rptr[J];
+      for (int64_t j = S.sptr[J]; j < bptr[b]; ++j) S.rows[q++] = (int32_t)j;
+      for (int64_t p = brp[b]; p < brp[b + 1]; ++p) S.rows[q++] = brows[p];
+    }
+    brows.clear(); brows.shrink_to_fit();
+    // storage offsets, sizes, executed flops
+    S.loff.assign(ns + 1, 0);
+    S.obase.assign(ns + 1, 0);
+    for (int64_t J = 0; J < ns; ++J) {
+      int64_t k = S.sptr[J + 1] - S.sptr[J], m = S.rptr[J + 1] - S.rptr[J];
+      S.loff[J + 1] = S.loff[J] + k * m;
+      S.obase[J + 1] = S.obase[J] + (m - k);
+      S.max_k = std::max(S.max_k, k);
+      S.max_m = std::max(S.max_m, m);
+      for (int64_t t = 0; t < k; ++t) S.flops_exec += double(m - t) * double(m - t);
+    }
+    // ---- relative indices ---------------------------------------------
+    S.opair.resize(S.obase[ns]);
+    S.ocbase.resize(S.obase[ns]);
+    S.relptr.push_back(0);
+    for (int64_t J = 0; J < ns; ++J) {
+      int64_t k = S.sptr[J + 1] - S.sptr[J];
+      const int32_t* R = S.rows.data() + S.rptr[J] + k;
+      int64_t r = S.rptr[J + 1] - S.rptr[J] - k;
+      int64_t a = 0;
+      while (a < r) {
+        int64_t P = S.snode_of[R[a]];
+        int64_t pid = (int64_t)S.pJ.size();
+        S.pJ.push_back(J);
+        S.pP.push_back(P);
+        S.pa0.push_back(a);
+        const int32_t* PR = S.rows.data() + S.rptr[P];
+        int64_t mP = S.rptr[P + 1] - S.rptr[P], q = 0;
+        for (int64_t c = a; c < r; ++c) {
+          while (q < mP && PR[q] < R[c]) ++q;
+          if (q >= mP || PR[q] != R[c]) { err = "analyze: internal error (row missing in ancestor)"; return ERR_PATTERN; }
+          S.tpos.push_back((int32_t)q);
+        }
+        S.relptr.push_back((int64_t)S.tpos.size());
+        int64_t a1 = a;
+        while (a1 < r && S.snode_of[R[a1]] == P) {
+          S.opair[S.obase[J] + a1] = (int32_t)pid;
+          S.ocbase[S.obase[J] + a1] = S.loff[P] + (int64_t(R[a1]) - S.sptr[P]) * mP;
+          ++a1;
+        }
+        a = a1;
+      }
+    }
+    // ---- map of A's entries into supernodal storage ------------------------
+    S.amap.resize(nz);
+    for (int64_t j = 0; j < n; ++j)
+      for (int64_t p = colptr[j]; p < colptr[j + 1]; ++p) {
+        int64_t a = S.pinv[rowind[p]], b = S.pinv[j];
+        int64_t r = std::max(a, b), c = std::min(a, b);
+        int64_t J = S.snode_of[c];
+        int64_t f = S.sptr[J], k = S.sptr[J + 1] - f, m = S.rptr[J + 1] - S.rptr[J];
+        int64_t pos;
+        if (r < f + k) {
+          pos = r - f;
+        } else {
+          const int32_t* R = S.rows.data() + S.rptr[J];
+          pos = std::lower_bound(R + k, R + m, (int32_t)r) - R;
+        }
+        S.amap[p] = S.loff[J] + (c - f) * m + pos;
+      }
+    // ---- levels --------------------------------------------------------
+    S.level.assign(ns, 0);
+    for (int64_t J = 0; J < ns; ++J)
+      if (S.sparent[J] >= 0) S.level[S.sparent[J]] = std::max(S.level[S.sparent[J]], S.level[J] + 1);
+    S.nlevels = 0;
+    for (int64_t J = 0; J < ns; ++J) S.nlevels = std::max(S.nlevels, S.level[J] + 1);
+    // ---- launch schedule ------------------------------------------------
+    std::vector<std::vector<int32_t>> bylev(S.nlevels);
+    for (int64_t J = 0; J < ns; ++J) bylev[S.level[J]].push_back((int32_t)J);
+    auto K = [&](int64_t J) { return S.sptr[J + 1] - S.sptr[J]; };
+    auto M = [&](int64_t J) { return S.rptr[J + 1] - S.rptr[J]; };
+    auto npan = [&](int64_t J) { return (K(J) + nb - 1) / nb; };
+    auto open = [&](std::vector<Launch>& plan, int32_t kind, int32_t lev, int32_t pan) {
+      Launch L;
+      L.kind = kind; L.ntasks = 0; L.off = (int64_t)S.tasks.size(); L.level = lev; L.panel = pan;
+      plan.push_back(L);
+    };
+    // lower-triangle entries (i >= c) of rows [r0, r1) x cols [c0, c1)
+    auto lower_count = [](int64_t r0, int64_t r1, int64_t c0, int64_t c1) {
+      int64_t s = 0;
+      for (int64_t c = c0; c < c1; ++c) s += std::max<int64_t>(0, r1 - std::max(r0, c));
+      return s;
+    };
+    // algorithmic flops and HBM bytes of one task (solves: per right-hand side)
+    auto cost = [&](int32_t kind, const Task& t, double& fl, double& by) {
+      const int64_t J = t.J, k = K(J), m = M(J);
+      switch (kind) {
+        case K_FACTOR: {
+          const int64_t c0 = int64_t(t.a) * nb, kp = std::min<int64_t>(nb, k - c0);
+          const bool diag = t.b == c0;
+          const int64_t rb = diag ? c0 + kp : t.b, re = std::min<int64_t>(t.b + kTile, m);
+          const int64_t nr = std::max<int64_t>(0, re - rb);
+          if (diag) {
+            for (int64_t j = 0; j < kp; ++j) fl += double(kp - j) * double(kp - j);
+            by += 16.0 * double(kp * (kp + 1) / 2);
+          } else {
+            by += 8.0 * double(kp * (kp + 1) / 2);
+          }
+          fl += double(nr) * double(kp) * double(kp);
+          by += 16.0 * double(nr * kp);
+          break;
+        }
+        case K_UPD_INT:
+        case K_UPD_EXT: {
+          const int64_t kb = kind == K_UPD_INT ? int64_t(t.c) * nb : 0;
+          const int64_t kk = kind == K_UPD_INT ? std::min<int64_t>(nb, k - kb) : k;
+          const int64_t colEnd = kind == K_UPD_INT ? k : m;
+          const int64_t r1 = std::min<int64_t>(t.a + kTile, m), c1 = std::min<int64_t>(t.b + kTile, colEnd);
+          const int64_t valid = lower_count(t.a, r1, t.b, c1);
+          fl += 2.0 * double(kk) * double(valid);
+          by += 8.0 * double(kk) * double((r1 - t.a) + (c1 - t.b)) + 16.0 * double(valid);
+          break;
+        }
+        case K_FWD_TRI:
+        case K_BWD_TRI: {
+          const int64_t kp = std::min<int64_t>(nb, k - int64_t(t.a) * nb);
+          fl += double(kp) * double(kp);
+          by += 8.0 * double(kp * (kp + 1) / 2) + 16.0 * double(kp);
+          break;
+        }
+        case K_FWD_GEMV:
+        case K_BWD_GEMVT: {
+          const int64_t kp = std::min<int64_t>(nb, k - int64_t(t.a) * nb);
+          const int64_t nr = std::min<int64_t>(t.b + kTile, m) - t.b;
+          fl += 2.0 * double(nr) * double(kp);
+          by += 8.0 * double(nr) * double(kp) + 16.0 * double(nr);
+          break;
+        }
+        default: break;
+      }
+    };
+    auto close = [&](std::vector<Launch>& plan) {
+      Launch& L = plan.back();
+      L.ntasks = (int32_t)((int64_t)S.tasks.size() - L.off);
+      if (L.ntasks == 0) { plan.pop_back(); return; }
+      for (int64_t q = L.off; q < L.off + L.ntasks; ++q) cost(L.kind, S.tasks[q], L.flops, L.bytes);
+    };
+    for (int64_t l = 0; l < S.nlevels; ++l) {
+      int64_t maxp = 0;
+      for (int32_t J : bylev[l]) maxp = std::max(maxp, npan(J));
+      for (int64_t p = 0; p < maxp; ++p) {
+        open(S.factor_plan, K_FACTOR, (int32_t)l, (int32_t)p);
+        for (int32_t J : bylev[l]) {
+          if (npan(J) <= p) continue;
+          for (int64_t r0 = p * nb; r0 < M(J); r0 += kTile) S.tasks.push_back({J, (int32_t)p, (int32_t)r0, 0});
+        }
+        close(S.factor_plan);
+        open(S.factor_plan, K_UPD_INT, (int32_t)l, (int32_t)p);
+        for (int32_t J : bylev[l]) {
+          if (npan(J) <= p + 1) continue;
+          for (int64_t c0 = (p + 1) * nb; c0 < K(J); c0 += kTile)
+            for (int64_t r0 = c0; r0 < M(J); r0 += kTile) S.tasks.push_back({J, (int32_t)r0, (int32_t)c0, (int32_t)p});
+        }
+        close(S.factor_plan);
+      }
+      open(S.factor_plan, K_UPD_EXT, (int32_t)l, -1);
+      for (int32_t J : bylev[l]) {
+        for (int64_t c0 = K(J); c0 < M(J); c0 += kTile)
+          for (int64_t r0 = c0; r0 < M(J); r0 += kTile) S.tasks.push_back({J, (int32_t)r0, (int32_t)c0, -1});
+      }
+      close(S.factor_plan);
+    }
+    // forward solve: leaves to root, panels ascending
+    for (int64_t l = 0; l < S.nlevels; ++l) {
+      int64_t maxp = 0;
+      for (int32_t J : bylev[l]) maxp = std::max(maxp, npan(J));
+      for (int64_t p = 0; p < maxp; ++p) {
+        open(S.fwd_plan, K_FWD_TRI, (int32_t)l, (int32_t)p);
+        for (int32_t J : bylev[l])
+          if (npan(J) > p) S.tasks.push_back({J, (int32_t)p, 0, 0});
+        close(S.fwd_plan);
+        open(S.fwd_plan, K_FWD_GEMV, (int32_t)l, (int32_t)p);
+        for (int32_t J : bylev[l]) {
+          if (npan(J) <= p) continue;
+          int64_t below = std::min<int64_t>(K(J), (p + 1) * nb);
+          for (int64_t r0 = below; r0 < M(J); r0 += kTile) S.tasks.push_back({J, (int32_t)p, (int32_t)r0, 0});
+        }
+        close(S.fwd_plan);
+      }
+    }
+    // backward solve: root to leaves, panels descending
+    for (int64_t l = S.nlevels - 1; l >= 0; --l) {
+      int64_t maxp = 0;
+      for (int32_t J : bylev[l]) maxp = std::max(maxp, npan(J));
+      for (int64_t p = maxp - 1; p >= 0; --p) {
+        open(S.bwd_plan, K_BWD_GEMVT, (int32_t)l, (int32_t)p);
+        for (int32_t J : bylev[l]) {
+          if (npan(J) <= p) continue;
+          int64_t below = std::min<int64_t>(K(J), (p + 1) * nb);
+          for (int64_t r0 = below; r0 < M(J); r0 += kTile) S.tasks.push_back({J, (int32_t)p, (int32_t)r0, 0});
+        }
+        close(S.bwd_plan);
+        open(S.bwd_plan, K_BWD_TRI, (int32_t)l, (int32_t)p);
+        for (int32_t J : bylev[l])
+          if (npan(J) > p) S.tasks.push_back({J, (int32_t)p, 0, 0});
+        close(S.bwd_plan);
+      }
+    }
+    if (S.tasks.size() >= (size_t(1) << 31)) { err = "analyze: schedule too large"; return ERR_OOM; }
+    return 0;
+  } catch (const std::bad_alloc&) {
+    err = "analyze: out of host memory";
+    return ERR_OOM;
+  }
+}
+
+}  // namespace spchol

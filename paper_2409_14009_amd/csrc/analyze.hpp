@@ -1,0 +1,76 @@
+// Host-side symbolic analysis and launch-schedule construction.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace spchol {
+
+// Work item of a batched launch.  Meaning of the fields per launch kind:
+//   FACTOR     J, panel, first local row of the 64-row tile, -
+//   UPD_INT    J, first local row (target rows), first local col (target
+//              cols), panel (the K range)
+//   UPD_EXT    J, first local row, first local col, -1
+//   FWD_TRI    J, panel, -, -
+//   FWD_GEMV   J, panel, first local row, -
+//   BWD_GEMVT  J, panel, first local row, -
+//   BWD_TRI    J, panel, -, -
+struct Task {
+  int32_t J, a, b, c;
+};
+
+enum Kind : int32_t {
+  K_FACTOR = 0,
+  K_UPD_INT = 1,
+  K_UPD_EXT = 2,
+  K_FWD_TRI = 3,
+  K_FWD_GEMV = 4,
+  K_BWD_GEMVT = 5,
+  K_BWD_TRI = 6,
+};
+
+struct Launch {
+  int32_t kind;
+  int32_t ntasks;
+  int64_t off;  // first task in the task array
+  int32_t level;
+  int32_t panel;
+  double flops = 0;  // algorithmic flops of the launch (stored structure)
+  double bytes = 0;  // algorithmic HBM bytes of the launch
+};
+
+constexpr int kTile = 64;      // rows (and cols) of a tile
+constexpr int kMaxPanel = 64;  // largest panel width
+
+struct Symbolic {
+  int64_t n = 0, nnzA = 0;
+  int nb = 64;  // panel width
+  std::vector<int64_t> perm, pinv;
+  std::vector<int64_t> parent, count;  // column etree and column counts of L
+  int64_t ns = 0;
+  std::vector<int64_t> sptr;     // ns+1, first column of each supernode
+  std::vector<int64_t> sparent;  // ns
+  std::vector<int64_t> rptr;     // ns+1, offsets of the row lists
+  std::vector<int32_t> rows;     // concatenated sorted row lists
+  std::vector<int64_t> loff;     // ns+1, storage offsets (doubles)
+  std::vector<int64_t> obase;    // ns+1, offsets of per-off-diagonal-row arrays
+  std::vector<int32_t> opair;    // pair id of each off-diagonal row
+  std::vector<int64_t> ocbase;   // storage offset of the target column of each off-diagonal row
+  std::vector<int64_t> pJ, pP, pa0, relptr;
+  std::vector<int32_t> tpos;     // position (from the top) of the row in P's row list
+  std::vector<int64_t> level;    // per supernode
+  std::vector<int64_t> amap;     // nnzA: storage offset of each entry of A
+  std::vector<int64_t> snode_of; // n: supernode of each column
+  int64_t nlevels = 0;
+  int64_t max_k = 0, max_m = 0;
+  double flops_alg = 0, flops_exec = 0;
+  // schedule
+  std::vector<Task> tasks;
+  std::vector<Launch> factor_plan, fwd_plan, bwd_plan;
+};
+
+// Returns 0, or a negative spchol_status with a message in err.
+int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64_t* perm,
+            int snode_mode, int amalg_max_zeros, int panel_width, Symbolic& S, std::string& err);
+
+}  // namespace spchol

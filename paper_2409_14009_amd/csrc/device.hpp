@@ -1,0 +1,53 @@
+// Device-side view of the symbolic analysis and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace spchol {
+
+struct DevTask {
+  int32_t J, a, b, c;
+};
+
+// All arrays live in device memory; passed to kernels by value.
+struct DevSym {
+  const int64_t* loff;    // ns+1 storage offsets (doubles)
+  const int32_t* sk;      // ns: columns k_J
+  const int32_t* sm;      // ns: rows m_J
+  const int32_t* sfirst;  // ns: first column
+  const int64_t* rptr;    // ns+1 row-list offsets
+  const int32_t* rows;    // row lists (permuted global indices)
+  const int64_t* obase;   // ns+1 offsets of per-off-diagonal-row arrays
+  const int32_t* opair;   // pair id of each off-diagonal row
+  const int64_t* ocbase;  // storage offset of the target column of each off-diagonal row
+  const int32_t* pa0;     // npairs: first off-diagonal row of J inside P
+  const int64_t* relptr;  // npairs+1
+  const int32_t* tpos;    // position from the top of the row in P's row list
+  const int32_t* snode_of;// n
+  const int64_t* amap;    // nnzA
+  const int64_t* perm;    // n
+  const DevTask* tasks;
+  int64_t n, ns, nnzA, storage;
+  int32_t nb;
+};
+
+// launchers (kernels.hip); all enqueue on `st` and return hipGetLastError()
+hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t st);
+hipError_t launch_status_init(unsigned long long* status, hipStream_t st);
+hipError_t launch_scatter_values(const DevSym& S, const double* vals, double* L, hipStream_t st);
+hipError_t launch_factor_panel(const DevSym& S, double* L, int64_t off, int32_t ntasks,
+                               unsigned long long* status, hipStream_t st);
+hipError_t launch_update(const DevSym& S, double* L, int32_t kind, int64_t off, int32_t ntasks,
+                         hipStream_t st);
+hipError_t launch_perm_gather(const DevSym& S, const double* B, int64_t ldb, int64_t nrhs, double* y,
+                              hipStream_t st);
+hipError_t launch_perm_scatter(const DevSym& S, const double* y, int64_t nrhs, double* B, int64_t ldb,
+                               hipStream_t st);
+hipError_t launch_solve_step(const DevSym& S, const double* L, int32_t kind, int64_t off,
+                             int32_t ntasks, double* y, int64_t nrhs, hipStream_t st);
+hipError_t launch_logdet(const DevSym& S, const double* L, double* partial, int32_t npartial,
+                         double* out, hipStream_t st);
+int32_t logdet_partials(int64_t n);
+
+}  // namespace spchol

@@ -1,0 +1,407 @@
+// C ABI: handles, device upload of the symbolic analysis, launch sequencing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/spchol.h"
+#include "analyze.hpp"
+#include "device.hpp"
+
+using namespace spchol;
+
+namespace {
+
+thread_local std::string g_err;
+
+spchol_status fail(spchol_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(e_ == hipErrorOutOfMemory ? SPCHOL_ERR_OOM : SPCHOL_ERR_HIP,            \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                     \
+  } while (0)
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& v) {
+  *dst = nullptr;
+  size_t bytes = v.size() * sizeof(T);
+  if (bytes == 0) bytes = sizeof(T);
+  hipError_t e = hipMalloc((void**)dst, bytes);
+  if (e != hipSuccess) return e;
+  if (!v.empty()) e = hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+}  // namespace
+
+struct spchol_sym_s {
+  Symbolic S;
+  bool uploaded = false;
+  int device = -1;
+  DevSym dev{};
+  std::vector<void*> allocs;
+
+  ~spchol_sym_s() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+
+  template <class T>
+  hipError_t up(const T** dst, const std::vector<T>& v) {
+    T* p = nullptr;
+    hipError_t e = upload(&p, v);
+    if (p) allocs.push_back(p);
+    *dst = p;
+    return e;
+  }
+
+  spchol_status ensure_device() {
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (uploaded) {
+      if (cur != device) return fail(SPCHOL_ERR_ARG, "symbolic handle is bound to another device");
+      return SPCHOL_OK;
+    }
+    const int64_t ns = S.ns;
+    std::vector<int32_t> sk(ns), sm(ns), sf(ns), pa0(S.pa0.size()), snode(S.n);
+    for (int64_t J = 0; J < ns; ++J) {
+      sk[J] = (int32_t)(S.sptr[J + 1] - S.sptr[J]);
+      sm[J] = (int32_t)(S.rptr[J + 1] - S.rptr[J]);
+      sf[J] = (int32_t)S.sptr[J];
+    }
+    for (size_t t = 0; t < S.pa0.size(); ++t) pa0[t] = (int32_t)S.pa0[t];
+    for (int64_t j = 0; j < S.n; ++j) snode[j] = (int32_t)S.snode_of[j];
+    std::vector<DevTask> tasks(S.tasks.size());
+    for (size_t t = 0; t < S.tasks.size(); ++t) tasks[t] = {S.tasks[t].J, S.tasks[t].a, S.tasks[t].b, S.tasks[t].c};
+    HIP_TRY(up(&dev.loff, S.loff));
+    HIP_TRY(up(&dev.sk, sk));
+    HIP_TRY(up(&dev.sm, sm));
+    HIP_TRY(up(&dev.sfirst, sf));
+    HIP_TRY(up(&dev.rptr, S.rptr));
+    HIP_TRY(up(&dev.rows, S.rows));
+    HIP_TRY(up(&dev.obase, S.obase));
+    HIP_TRY(up(&dev.opair, S.opair));
+    HIP_TRY(up(&dev.ocbase, S.ocbase));
+    HIP_TRY(up(&dev.pa0, pa0));
+    HIP_TRY(up(&dev.relptr, S.relptr));
+    HIP_TRY(up(&dev.tpos, S.tpos));
+    HIP_TRY(up(&dev.snode_of, snode));
+    HIP_TRY(up(&dev.amap, S.amap));
+    HIP_TRY(up(&dev.perm, S.perm));
+    HIP_TRY(up(&dev.tasks, tasks));
+    dev.n = S.n;
+    dev.ns = ns;
+    dev.nnzA = S.nnzA;
+    dev.storage = S.loff[ns];
+    dev.nb = S.nb;
+    device = cur;
+    uploaded = true;
+    return SPCHOL_OK;
+  }
+};
+
+// HIP events around launches, summed per kernel kind on request.
+struct Profiler {
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<Rec> recs;
+
+  ~Profiler() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+  hipError_t take(hipEvent_t* e) {
+    if (used == pool.size()) {
+      hipEvent_t ne;
+      hipError_t err = hipEventCreate(&ne);
+      if (err != hipSuccess) return err;
+      pool.push_back(ne);
+    }
+    *e = pool[used++];
+    return hipSuccess;
+  }
+};
+
+struct spchol_num_s {
+  spchol_sym_s* sym = nullptr;
+  double* L = nullptr;
+  unsigned long long* status = nullptr;
+  double* y = nullptr;
+  int64_t ycap = 0;
+  double* red = nullptr;  // logdet partials + result
+  Profiler prof;
+  ~spchol_num_s() {
+    if (L) (void)hipFree(L);
+    if (status) (void)hipFree(status);
+    if (y) (void)hipFree(y);
+    if (red) (void)hipFree(red);
+  }
+};
+
+// Run `launch` (returning hipError_t), bracketed by events when profiling.
+template <class F>
+static hipError_t timed(spchol_num_s* N, int kind, double flops, double bytes, hipStream_t st, F&& launch) {
+  if (!N->prof.on) return launch();
+  Profiler::Rec r{kind, nullptr, nullptr, flops, bytes};
+  hipError_t e = N->prof.take(&r.a);
+  if (e == hipSuccess) e = N->prof.take(&r.b);
+  if (e == hipSuccess) e = hipEventRecord(r.a, st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(r.b, st);
+  if (e == hipSuccess) N->prof.recs.push_back(r);
+  return e;
+}
+
+static spchol_status run_factor(spchol_num_s* N, const double* vals, hipStream_t st, int64_t* info) {
+  const Symbolic& S = N->sym->S;
+  const DevSym& D = N->sym->dev;
+  HIP_TRY(timed(N, SPCHOL_KERNEL_FILL, 0.0, 8.0 * D.storage, st,
+                [&] { return launch_fill(N->L, D.storage, 0.0, st); }));
+  HIP_TRY(launch_status_init(N->status, st));
+  HIP_TRY(timed(N, SPCHOL_KERNEL_SCATTER_A, 0.0, 24.0 * D.nnzA, st,
+                [&] { return launch_scatter_values(D, vals, N->L, st); }));
+  for (const Launch& l : S.factor_plan) {
+    if (l.kind == K_FACTOR) {
+      HIP_TRY(timed(N, SPCHOL_KERNEL_FACTOR, l.flops, l.bytes, st,
+                    [&] { return launch_factor_panel(D, N->L, l.off, l.ntasks, N->status, st); }));
+    } else {
+      HIP_TRY(timed(N, l.kind == K_UPD_INT ? SPCHOL_KERNEL_UPDATE_INT : SPCHOL_KERNEL_UPDATE_EXT, l.flops,
+                    l.bytes, st, [&] { return launch_update(D, N->L, l.kind, l.off, l.ntasks, st); }));
+    }
+  }
+  unsigned long long h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, N->status, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  int64_t inf = (h == ~0ULL) ? 0 : (int64_t)h + 1;
+  if (info) *info = inf;
+  if (inf) return fail(SPCHOL_ERR_NOT_SPD, "matrix is not positive definite at permuted column " + std::to_string(inf));
+  return SPCHOL_OK;
+}
+
+extern "C" {
+
+const char* spchol_last_error(void) { return g_err.c_str(); }
+
+const char* spchol_version(void) { return "spchol-mi355x 0.1"; }
+
+spchol_status spchol_default_options(spchol_options* opt) {
+  if (!opt) return fail(SPCHOL_ERR_ARG, "null options");
+  opt->snode_mode = SPCHOL_SNODE_FUNDAMENTAL;
+  opt->amalg_max_zeros = 0;
+  opt->panel_width = 64;
+  opt->reserved = 0;
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64_t* perm,
+                             const spchol_options* opt, spchol_sym* out) {
+  if (!out) return fail(SPCHOL_ERR_ARG, "null output handle");
+  *out = nullptr;
+  spchol_options o;
+  spchol_default_options(&o);
+  if (opt) o = *opt;
+  spchol_sym_s* h = new (std::nothrow) spchol_sym_s();
+  if (!h) return fail(SPCHOL_ERR_OOM, "out of host memory");
+  std::string err;
+  int rc = analyze(n, colptr, rowind, perm, o.snode_mode, o.amalg_max_zeros, o.panel_width, h->S, err);
+  if (rc) {
+    delete h;
+    return fail((spchol_status)rc, err);
+  }
+  *out = h;
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_sym_info(spchol_sym sym, spchol_sym_info_t* info) {
+  if (!sym || !info) return fail(SPCHOL_ERR_ARG, "null argument");
+  const Symbolic& S = sym->S;
+  info->n = S.n;
+  info->nnz_a = S.nnzA;
+  int64_t nz = 0;
+  for (int64_t c : S.count) nz += c;
+  info->nnz_l = nz;
+  info->storage = S.loff[S.ns];
+  info->nsuper = S.ns;
+  info->nrows_total = S.rptr[S.ns];
+  info->npairs = (int64_t)S.pJ.size();
+  info->nrelind = (int64_t)S.tpos.size();
+  info->nlevels = S.nlevels;
+  info->max_k = S.max_k;
+  info->max_m = S.max_m;
+  info->flops_alg = S.flops_alg;
+  info->flops_exec = S.flops_exec;
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_sym_export(spchol_sym sym, int64_t* parent, int64_t* count, int64_t* super_ptr,
+                                int64_t* sparent, int64_t* row_ptr, int64_t* row_idx, int64_t* pair_J,
+                                int64_t* pair_P, int64_t* pair_a0, int64_t* relind_ptr, int32_t* relind,
+                                int64_t* level) {
+  if (!sym) return fail(SPCHOL_ERR_ARG, "null handle");
+  const Symbolic& S = sym->S;
+  auto cp = [](int64_t* dst, const std::vector<int64_t>& v) {
+    if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(int64_t));
+  };
+  cp(parent, S.parent);
+  cp(count, S.count);
+  cp(super_ptr, S.sptr);
+  cp(sparent, S.sparent);
+  cp(row_ptr, S.rptr);
+  if (row_idx)
+    for (size_t i = 0; i < S.rows.size(); ++i) row_idx[i] = S.rows[i];
+  cp(pair_J, S.pJ);
+  cp(pair_P, S.pP);
+  cp(pair_a0, S.pa0);
+  cp(relind_ptr, S.relptr);
+  if (relind) {
+    // device form is the position from the top; export the distance from the bottom
+    for (size_t t = 0; t + 1 < S.relptr.size(); ++t) {
+      int64_t P = S.pP[t];
+      int64_t mP = S.rptr[P + 1] - S.rptr[P];
+      for (int64_t q = S.relptr[t]; q < S.relptr[t + 1]; ++q) relind[q] = (int32_t)(mP - 1 - S.tpos[q]);
+    }
+  }
+  cp(level, S.level);
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_sym_storage(spchol_sym sym, int64_t* storage_off) {
+  if (!sym || !storage_off) return fail(SPCHOL_ERR_ARG, "null argument");
+  std::memcpy(storage_off, sym->S.loff.data(), sym->S.loff.size() * sizeof(int64_t));
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_factor(spchol_sym sym, const double* vals_dev, void* stream, spchol_num* out,
+                            int64_t* info) {
+  if (!sym || !out) return fail(SPCHOL_ERR_ARG, "null argument");
+  if (!vals_dev && sym->S.nnzA > 0) return fail(SPCHOL_ERR_ARG, "null values");
+  *out = nullptr;
+  if (info) *info = 0;
+  spchol_status s = sym->ensure_device();
+  if (s) return s;
+  spchol_num_s* N = new (std::nothrow) spchol_num_s();
+  if (!N) return fail(SPCHOL_ERR_OOM, "out of host memory");
+  N->sym = sym;
+  const int64_t storage = sym->S.loff[sym->S.ns];
+  hipError_t e = hipMalloc((void**)&N->L, (size_t)(storage > 0 ? storage : 1) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&N->status, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc((void**)&N->red, (size_t)(logdet_partials(sym->S.n) + 1) * sizeof(double));
+  if (e != hipSuccess) {
+    delete N;
+    return fail(e == hipErrorOutOfMemory ? SPCHOL_ERR_OOM : SPCHOL_ERR_HIP,
+                std::string("device allocation: ") + hipGetErrorString(e));
+  }
+  *out = N;
+  return run_factor(N, vals_dev, (hipStream_t)stream, info);
+}
+
+spchol_status spchol_refactor(spchol_num num, const double* vals_dev, void* stream, int64_t* info) {
+  if (!num) return fail(SPCHOL_ERR_ARG, "null handle");
+  if (!vals_dev && num->sym->S.nnzA > 0) return fail(SPCHOL_ERR_ARG, "null values");
+  if (info) *info = 0;
+  spchol_status s = num->sym->ensure_device();
+  if (s) return s;
+  return run_factor(num, vals_dev, (hipStream_t)stream, info);
+}
+
+spchol_status spchol_solve(spchol_num num, double* B_dev, int64_t nrhs, int64_t ldb, void* stream) {
+  if (!num) return fail(SPCHOL_ERR_ARG, "null handle");
+  const Symbolic& S = num->sym->S;
+  if (nrhs < 0 || ldb < S.n || ldb < 1) return fail(SPCHOL_ERR_ARG, "bad nrhs or ldb");
+  if (nrhs == 0 || S.n == 0) return SPCHOL_OK;
+  if (!B_dev) return fail(SPCHOL_ERR_ARG, "null right-hand side");
+  hipStream_t st = (hipStream_t)stream;
+  const DevSym& D = num->sym->dev;
+  if (num->ycap < S.n * nrhs) {
+    if (num->y) HIP_TRY(hipFree(num->y));
+    num->y = nullptr;
+    num->ycap = 0;
+    HIP_TRY(hipMalloc((void**)&num->y, (size_t)(S.n * nrhs) * sizeof(double)));
+    num->ycap = S.n * nrhs;
+  }
+  const double pbytes = 24.0 * double(S.n) * double(nrhs);
+  HIP_TRY(timed(num, SPCHOL_KERNEL_PERM, 0.0, pbytes, st,
+                [&] { return launch_perm_gather(D, B_dev, ldb, nrhs, num->y, st); }));
+  auto step = [&](const Launch& l) {
+    // solve flops/bytes were counted for one right-hand side; L is read once
+    const double fl = l.flops * double(nrhs);
+    const double by = l.bytes;
+    return timed(num, l.kind + 2, fl, by, st,
+                 [&] { return launch_solve_step(D, num->L, l.kind, l.off, l.ntasks, num->y, nrhs, st); });
+  };
+  for (const Launch& l : S.fwd_plan) HIP_TRY(step(l));
+  for (const Launch& l : S.bwd_plan) HIP_TRY(step(l));
+  HIP_TRY(timed(num, SPCHOL_KERNEL_PERM, 0.0, pbytes, st,
+                [&] { return launch_perm_scatter(D, num->y, nrhs, B_dev, ldb, st); }));
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_logdet(spchol_num num, double* out_host, void* stream) {
+  if (!num || !out_host) return fail(SPCHOL_ERR_ARG, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  const DevSym& D = num->sym->dev;
+  const int32_t np = logdet_partials(num->sym->S.n);
+  HIP_TRY(timed(num, SPCHOL_KERNEL_LOGDET, 0.0, 8.0 * double(num->sym->S.n), st,
+                [&] { return launch_logdet(D, num->L, num->red, np, num->red + np, st); }));
+  HIP_TRY(hipMemcpyAsync(out_host, num->red + np, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_num_export(spchol_num num, double* dst_dev, void* stream) {
+  if (!num || !dst_dev) return fail(SPCHOL_ERR_ARG, "null argument");
+  const int64_t storage = num->sym->S.loff[num->sym->S.ns];
+  if (storage == 0) return SPCHOL_OK;
+  HIP_TRY(hipMemcpyAsync(dst_dev, num->L, (size_t)storage * sizeof(double), hipMemcpyDeviceToDevice,
+                         (hipStream_t)stream));
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_profile(spchol_num num, int32_t enable) {
+  if (!num) return fail(SPCHOL_ERR_ARG, "null handle");
+  num->prof.on = enable != 0;
+  if (num->prof.on) {
+    num->prof.recs.clear();
+    num->prof.used = 0;
+  }
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_profile_read(spchol_num num, spchol_kernel_stat* out) {
+  if (!num || !out) return fail(SPCHOL_ERR_ARG, "null argument");
+  for (int k = 0; k < SPCHOL_KERNEL_KINDS; ++k) out[k] = spchol_kernel_stat{0, 0.0, 0.0, 0.0};
+  for (const Profiler::Rec& r : num->prof.recs) {
+    HIP_TRY(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    spchol_kernel_stat& s = out[r.kind];
+    s.launches += 1;
+    s.ms += ms;
+    s.flops += r.flops;
+    s.bytes += r.bytes;
+  }
+  num->prof.recs.clear();
+  num->prof.used = 0;
+  return SPCHOL_OK;
+}
+
+void spchol_sym_destroy(spchol_sym sym) { delete sym; }
+void spchol_num_destroy(spchol_num num) { delete num; }
+
+}  // extern "C"

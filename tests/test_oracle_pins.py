@@ -452,3 +452,19 @@ def test_backward_error_hand_example():
     assert abs(eta[0] - 0.2) < 1e-16
     # |A||x| + |b| = [3+1, 3+2]; componentwise max(0/4, 1/5)
     assert abs(comp[0] - 0.2) < 1e-16
+
+
+def test_prefix_columns_equal_full_factor():
+    """Column j of L depends only on columns k < j: a factorization stopped
+    after t columns agrees with the full one on those columns, bit for bit."""
+    p = gen.make_config(4, side=10)
+    s = oracle.Symbolic(p.n, p.colptr, p.rowind, p.perm, 0, 8)
+    full = s.factor(p.vals)
+    t = p.n // 3
+    part = s.factor(p.vals, ncols=t)
+    e = s.lptr[t]
+    assert np.array_equal(part.lv[:e], full.lv[:e])
+    assert not part.lv[e:].any()
+    assert s.flops(t) == float((s.count[:t].astype(np.float64) ** 2).sum())
+    with pytest.raises(oracle.OracleError):
+        part.solve(p.B)
