@@ -314,6 +314,7 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
     auto K = [&](int64_t J) { return S.sptr[J + 1] - S.sptr[J]; };
     auto M = [&](int64_t J) { return S.rptr[J + 1] - S.rptr[J]; };
     auto npan = [&](int64_t J) { return (K(J) + nb - 1) / nb; };
+    auto kpan = [&](int64_t J, int64_t p) { return std::min<int64_t>(nb, K(J) - p * nb); };
     auto open = [&](std::vector<Launch>& plan, int32_t kind, int32_t lev, int32_t pan) {
       Launch L;
       L.kind = kind; L.ntasks = 0; L.off = (int64_t)S.tasks.size(); L.level = lev; L.panel = pan;
@@ -329,10 +330,11 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
     auto cost = [&](int32_t kind, const Task& t, double& fl, double& by) {
       const int64_t J = t.J, k = K(J), m = M(J);
       switch (kind) {
-        case K_FACTOR: {
+        case K_FACTOR:
+        case K_TRSM: {
           const int64_t c0 = int64_t(t.a) * nb, kp = std::min<int64_t>(nb, k - c0);
-          const bool diag = t.b == c0;
-          const int64_t rb = diag ? c0 + kp : t.b, re = std::min<int64_t>(t.b + kTile, m);
+          const bool diag = kind == K_FACTOR;
+          const int64_t rb = t.b, re = std::min<int64_t>(t.b + (diag ? kTrsmRows : kTile), m);
           const int64_t nr = std::max<int64_t>(0, re - rb);
           if (diag) {
             for (int64_t j = 0; j < kp; ++j) fl += double(kp - j) * double(kp - j);
@@ -383,10 +385,33 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       int64_t maxp = 0;
       for (int32_t J : bylev[l]) maxp = std::max(maxp, npan(J));
       for (int64_t p = 0; p < maxp; ++p) {
+        // the tile holding the diagonal block factors it and writes it back;
+        // the other tiles of the panel run in a second launch that reads the
+        // factored block
+        // diagonal task: Cholesky of the block, its inverse, the first
+        // kTrsmRows rows below; a panel with more rows gets a scratch slot
+        // for the inverse, read by the row-tile tasks
         open(S.factor_plan, K_FACTOR, (int32_t)l, (int32_t)p);
+        std::vector<int32_t> slot_of;
+        int32_t nslot = 0;
         for (int32_t J : bylev[l]) {
           if (npan(J) <= p) continue;
-          for (int64_t r0 = p * nb; r0 < M(J); r0 += kTile) S.tasks.push_back({J, (int32_t)p, (int32_t)r0, 0});
+          const int64_t rb = p * nb + kpan(J, p);
+          const int32_t slot = (M(J) > rb + kTrsmRows) ? nslot++ : -1;
+          slot_of.push_back(slot);
+          S.tasks.push_back({J, (int32_t)p, (int32_t)rb, slot});
+        }
+        close(S.factor_plan);
+        S.max_slots = std::max<int64_t>(S.max_slots, nslot);
+        open(S.factor_plan, K_TRSM, (int32_t)l, (int32_t)p);
+        {
+          size_t q = 0;
+          for (int32_t J : bylev[l]) {
+            if (npan(J) <= p) continue;
+            const int32_t slot = slot_of[q++];
+            for (int64_t r0 = p * nb + kpan(J, p) + kTrsmRows; r0 < M(J); r0 += kTile)
+              S.tasks.push_back({J, (int32_t)p, (int32_t)r0, slot});
+          }
         }
         close(S.factor_plan);
         open(S.factor_plan, K_UPD_INT, (int32_t)l, (int32_t)p);

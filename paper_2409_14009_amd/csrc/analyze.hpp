@@ -7,7 +7,10 @@
 namespace spchol {
 
 // Work item of a batched launch.  Meaning of the fields per launch kind:
-//   FACTOR     J, panel, first local row of the 64-row tile, -
+//   FACTOR     J, panel, first local row below the panel's diagonal block
+//              (the task also solves the 256 rows from there), scratch
+//              slot for the inverted diagonal block (-1: none needed)
+//   TRSM       J, panel, first local row of a further 64-row tile, slot
 //   UPD_INT    J, first local row (target rows), first local col (target
 //              cols), panel (the K range)
 //   UPD_EXT    J, first local row, first local col, -1
@@ -27,6 +30,7 @@ enum Kind : int32_t {
   K_FWD_GEMV = 4,
   K_BWD_GEMVT = 5,
   K_BWD_TRI = 6,
+  K_TRSM = 7,
 };
 
 struct Launch {
@@ -39,7 +43,8 @@ struct Launch {
   double bytes = 0;  // algorithmic HBM bytes of the launch
 };
 
-constexpr int kTile = 64;      // rows (and cols) of a tile
+constexpr int kTile = 64;      // rows (and cols) of an update tile
+constexpr int kTrsmRows = 256; // rows solved by the diagonal-block workgroup
 constexpr int kMaxPanel = 64;  // largest panel width
 
 struct Symbolic {
@@ -63,6 +68,7 @@ struct Symbolic {
   std::vector<int64_t> snode_of; // n: supernode of each column
   int64_t nlevels = 0;
   int64_t max_k = 0, max_m = 0;
+  int64_t max_slots = 0;  // inverted diagonal blocks held at once (scratch)
   double flops_alg = 0, flops_exec = 0;
   // schedule
   std::vector<Task> tasks;

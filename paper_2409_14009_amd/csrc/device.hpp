@@ -37,7 +37,7 @@ hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t st);
 hipError_t launch_status_init(unsigned long long* status, hipStream_t st);
 hipError_t launch_scatter_values(const DevSym& S, const double* vals, double* L, hipStream_t st);
 hipError_t launch_factor_panel(const DevSym& S, double* L, int64_t off, int32_t ntasks,
-                               unsigned long long* status, hipStream_t st);
+                               unsigned long long* status, double* scratch, bool diag, hipStream_t st);
 hipError_t launch_update(const DevSym& S, double* L, int32_t kind, int64_t off, int32_t ntasks,
                          hipStream_t st);
 hipError_t launch_perm_gather(const DevSym& S, const double* B, int64_t ldb, int64_t nrhs, double* y,

@@ -143,9 +143,11 @@ struct spchol_num_s {
   double* y = nullptr;
   int64_t ycap = 0;
   double* red = nullptr;  // logdet partials + result
+  double* scratch = nullptr;  // inverted diagonal blocks of the panels of one launch
   Profiler prof;
   ~spchol_num_s() {
     if (L) (void)hipFree(L);
+    if (scratch) (void)hipFree(scratch);
     if (status) (void)hipFree(status);
     if (y) (void)hipFree(y);
     if (red) (void)hipFree(red);
@@ -177,9 +179,10 @@ static spchol_status run_factor(spchol_num_s* N, const double* vals, hipStream_t
   HIP_TRY(timed(N, SPCHOL_KERNEL_SCATTER_A, 0.0, 24.0 * D.nnzA, st,
                 [&] { return launch_scatter_values(D, vals, N->L, st); }));
   for (const Launch& l : S.factor_plan) {
-    if (l.kind == K_FACTOR) {
+    if (l.kind == K_FACTOR || l.kind == K_TRSM) {
+      const bool diag = l.kind == K_FACTOR;
       HIP_TRY(timed(N, SPCHOL_KERNEL_FACTOR, l.flops, l.bytes, st,
-                    [&] { return launch_factor_panel(D, N->L, l.off, l.ntasks, N->status, st); }));
+                    [&] { return launch_factor_panel(D, N->L, l.off, l.ntasks, N->status, N->scratch, diag, st); }));
     } else {
       HIP_TRY(timed(N, l.kind == K_UPD_INT ? SPCHOL_KERNEL_UPDATE_INT : SPCHOL_KERNEL_UPDATE_EXT, l.flops,
                     l.bytes, st, [&] { return launch_update(D, N->L, l.kind, l.off, l.ntasks, st); }));
@@ -302,6 +305,8 @@ spchol_status spchol_factor(spchol_sym sym, const double* vals_dev, void* stream
   hipError_t e = hipMalloc((void**)&N->L, (size_t)(storage > 0 ? storage : 1) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&N->status, sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMalloc((void**)&N->red, (size_t)(logdet_partials(sym->S.n) + 1) * sizeof(double));
+  if (e == hipSuccess)
+    e = hipMalloc((void**)&N->scratch, (size_t)(sym->S.max_slots > 0 ? sym->S.max_slots : 1) * 64 * 64 * sizeof(double));
   if (e != hipSuccess) {
     delete N;
     return fail(e == hipErrorOutOfMemory ? SPCHOL_ERR_OOM : SPCHOL_ERR_HIP,
