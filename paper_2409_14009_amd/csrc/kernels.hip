@@ -56,7 +56,6 @@ __device__ inline double readlane_d(double x, int l) {
 // Cholesky of the block runs on one wavefront, lane = row, over 16-column
 // blocks with small register micro-kernels inside rolled loops (code that
 // stays in the instruction cache):
-//   upd16:   xb -= xa * D[rows of block b, cols of block b2]^T
 //   potrf16: right-looking sweep over the 16 columns of block b, one row per
 //            lane, column j broadcast with readlane: factors D_bb on its
 //            lanes and solves the rows below it on theirs
@@ -67,33 +66,34 @@ __device__ inline double readlane_d(double x, int l) {
 constexpr int DLD = NBMAX + 2;  // even: 16-byte aligned columns
 constexpr int MB = 16;          // micro-block width
 
-__device__ __forceinline__ void upd16(double (&xb)[MB], const double (&xa)[MB], const double* __restrict__ Dc,
-                                      int r0, int c0) {
-#pragma unroll
-  for (int t = 0; t < MB; ++t) {
-    const double* col = Dc + (c0 + t) * DLD + r0;
-#pragma unroll
-    for (int q = 0; q < MB; ++q) xb[q] = fma(-xa[t], col[q], xb[q]);
-  }
-}
-
-__device__ __forceinline__ void potrf16(double (&r)[MB], int lane, int j0, int jn,
+// Columns of the block past kp are padded with an identity (unit
+// diagonal, zero off-diagonal), so they factor to themselves and the sweep
+// needs no per-column branch.  The pivot comes from its lane with readlane;
+// the scaled column goes through LDS (colb, one wavefront) and is read back
+// as a broadcast.  Like LAPACK's unblocked Cholesky, the column is scaled
+// by the reciprocal of the pivot's square root.
+__device__ __forceinline__ void potrf16(double (&r)[MB], int lane, int j0, double* __restrict__ colb,
                                         unsigned long long* __restrict__ status, int64_t col0) {
 #pragma unroll
   for (int q = 0; q < MB; ++q) {
-    if (q < jn) {
-      double piv = readlane_d(r[q], j0 + q);
-      if (!(piv > 0.0)) {
-        if (lane == j0 + q) atomicMin(status, (unsigned long long)(col0 + q));
-        piv = 1.0;
-      }
-      const double ljj = sqrt(piv);
-      const double lq = (lane == j0 + q) ? ljj : (lane > j0 + q ? r[q] / ljj : 0.0);
-      r[q] = lq;
-#pragma unroll
-      for (int c = q + 1; c < MB; ++c)
-        if (c < jn) r[c] = fma(-lq, readlane_d(lq, j0 + c), r[c]);
+    double piv = readlane_d(r[q], j0 + q);
+    if (!(piv > 0.0)) {
+      if (lane == j0 + q) atomicMin(status, (unsigned long long)(col0 + q));
+      piv = 1.0;
     }
+    const double ljj = sqrt(piv);
+    const double rinv = 1.0 / ljj;
+    const double lq = (lane == j0 + q) ? ljj : (lane > j0 + q ? r[q] * rinv : 0.0);
+    r[q] = lq;
+    colb[lane] = lq;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int c = q + 1; c < MB; ++c) r[c] = fma(-lq, colb[j0 + c], r[c]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -109,15 +109,21 @@ __device__ __forceinline__ void trsm_tile_mfma(const double* __restrict__ As, co
   d4 acc[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
-  const int ks = (kp + 3) & ~3;
-  for (int s = 0; s < ks; s += 4) {
-    // B operand: B[k][c] = W[c][k], c = 16w + li, k = s + lk
-    const double bv = Wc[(s + lk) * DLD + MB * w + li];
+  // k in chunks of 16: all LDS operands of a chunk are read before its
+  // 16 MFMAs (columns past kp are zero in As)
+  for (int s0 = 0; s0 < kp; s0 += 16) {
+    double bv[4], av[4][4];
 #pragma unroll
-    for (int rb2 = 0; rb2 < 4; ++rb2) {
-      const double av = As[(s + lk) * DLD + 16 * rb2 + li];
-      acc[rb2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[rb2], 0, 0, 0);
+    for (int s = 0; s < 4; ++s) {
+      bv[s] = Wc[(s0 + 4 * s + lk) * DLD + MB * w + li];
+#pragma unroll
+      for (int rb2 = 0; rb2 < 4; ++rb2) av[s][rb2] = As[(s0 + 4 * s + lk) * DLD + 16 * rb2 + li];
     }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int rb2 = 0; rb2 < 4; ++rb2)
+        acc[rb2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][rb2], bv[s], acc[rb2], 0, 0, 0);
   }
   const int c = MB * w + li;
   if (c < kp) {
@@ -167,6 +173,7 @@ __global__ __launch_bounds__(256) void k_panel(DevSym S, double* __restrict__ L,
                                                double* __restrict__ scratch) {
   __shared__ __attribute__((aligned(16))) double Dc[NBMAX * DLD];
   __shared__ __attribute__((aligned(16))) double Wc[NBMAX * DLD];
+  __shared__ __attribute__((aligned(16))) double colb[NBMAX];
   const DevTask t = S.tasks[off + blockIdx.x];
   const int J = t.J, p = t.a, rb = t.b, slot = t.c;
   const int m = S.sm[J], k = S.sk[J];
@@ -182,7 +189,10 @@ __global__ __launch_bounds__(256) void k_panel(DevSym S, double* __restrict__ L,
     for (int u = 0; u < 16; ++u) {
       const int idx = base + u * 256 + tid;
       const int i = idx & 63, c = idx >> 6;
-      v[u] = (i < kp && c <= i) ? Lp[(int64_t)c * m + c0 + i] : (i == c ? 1.0 : 0.0);
+      const bool in = i < kp && c <= i;
+      // clamped in-bounds address, value selected afterwards (no branch)
+      const double x = Lp[(int64_t)min(c, kp - 1) * m + c0 + min(i, kp - 1)];
+      v[u] = in ? x : (i == c ? 1.0 : 0.0);
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -193,28 +203,48 @@ __global__ __launch_bounds__(256) void k_panel(DevSym S, double* __restrict__ L,
   }
   __syncthreads();
 
-  // 1. Cholesky of the diagonal block
+  // 1. Cholesky of the diagonal block, right-looking over 16-column blocks:
+  //    wavefront 0 sweeps block column b (rows >= 16b), then the four
+  //    wavefronts apply its update to the 16 x 16 blocks (i, b') with
+  //    i >= b' > b on the matrix cores:
+  //    D[i][b'] -= L[i][b] L[b'][b]^T
   for (int b = 0; b < nblk; ++b) {
     const int j0 = MB * b, jn = min(MB, kp - j0);
     const bool mine = (w == 0) && lane >= j0 && lane < kp;
-    double xb[MB];
+    if (w == 0) {
+      double xb[MB];
 #pragma unroll
-    for (int q = 0; q < MB; ++q) xb[q] = mine ? Dc[(j0 + q) * DLD + lane] : 0.0;
-    if (mine) {
-      for (int b2 = 0; b2 < b; ++b2) {
-        double xa[MB];
+      for (int q = 0; q < MB; ++q) xb[q] = (lane >= j0) ? Dc[(j0 + q) * DLD + lane] : 0.0;
+      // the sweep factors the 16 x 16 block (its lanes) and, on the lanes
+      // below it, solves those rows against it
+      potrf16(xb, lane, j0, colb, status, (int64_t)S.sfirst[J] + c0 + j0);
+      if (mine) {
 #pragma unroll
-        for (int q = 0; q < MB; ++q) xa[q] = Dc[(MB * b2 + q) * DLD + lane];
-        upd16(xb, xa, Dc, j0, MB * b2);
+        for (int q = 0; q < MB; ++q)
+          if (q < jn) Dc[(j0 + q) * DLD + lane] = (j0 + q <= lane) ? xb[q] : 0.0;
       }
     }
-    // the sweep over the wavefront factors the 16 x 16 block (its lanes)
-    // and, on the lanes below it, solves those rows against it
-    if (w == 0) potrf16(xb, lane, j0, jn, status, (int64_t)S.sfirst[J] + c0 + j0);
-    if (mine) {
+    __syncthreads();
+    const int nrest = nblk - 1 - b;  // block columns right of b
+    const int npairs = nrest * (nrest + 1) / 2;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int pr = w; pr < npairs; pr += 4) {
+      // pair index -> (i, bp) with b < bp <= i < nblk
+      int bp = b + 1, rem = pr;
+      while (rem >= nblk - bp) { rem -= nblk - bp; ++bp; }
+      const int i = bp + rem;
+      d4 P = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < MB; ++q)
-        if (q < jn) Dc[(j0 + q) * DLD + lane] = (j0 + q <= lane) ? xb[q] : 0.0;
+      for (int s = 0; s < MB; s += 4) {
+        const double av = Dc[(j0 + s + lk) * DLD + MB * i + li];   // L[16i + li][16b + s + lk]
+        const double bv = Dc[(j0 + s + lk) * DLD + MB * bp + li];  // L[16bp + li][16b + s + lk]
+        P = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, P, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double* d = Dc + (MB * bp + li) * DLD + MB * i + 4 * v + lk;
+        *d -= P[v];
+      }
     }
     __syncthreads();
   }
