@@ -147,15 +147,69 @@ spchol_status spchol_factor(spchol_sym sym, const double *vals_dev, void *stream
                             spchol_num *out, int64_t *info);
 
 /* Re-run the numeric factorization into an existing handle (same pattern,
- * new values), without reallocating.  Same semantics as spchol_factor. */
+ * new values), without reallocating.  Same semantics as spchol_factor; keeps
+ * the update precision of the handle. */
 spchol_status spchol_refactor(spchol_num num, const double *vals_dev, void *stream,
                               int64_t *info);
+
+/* Precision of the update products (SYRK/GEMM of the panels, Sec. II-A).
+ * The diagonal-block Cholesky, the triangular solves and the factor storage
+ * stay fp64 in every mode; F32 rounds the update operands to fp32 and
+ * accumulates in fp32 on the matrix cores, then adds the result into the
+ * fp64 factor.  The factor is then that of a nearby matrix: pair it with
+ * spchol_refine to recover fp64 accuracy. */
+enum { SPCHOL_UPD_F64 = 0, SPCHOL_UPD_F32 = 1 };
+
+/* spchol_factor / spchol_refactor with an update precision (SPCHOL_UPD_*);
+ * SPCHOL_ERR_ARG for an unsupported value. */
+spchol_status spchol_factor_prec(spchol_sym sym, const double *vals_dev, int32_t update_precision,
+                                 void *stream, spchol_num *out, int64_t *info);
+spchol_status spchol_refactor_prec(spchol_num num, const double *vals_dev, int32_t update_precision,
+                                   void *stream, int64_t *info);
+
+/* Iterative refinement against the fp64 matrix: X = A~^{-1} B with the
+ * (possibly mixed-precision) factor, then repeatedly R = B - A X (fp64,
+ * original ordering), X += A~^{-1} R, until the normwise backward error
+ * eta = ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf) of every column is
+ * <= tol or max_iter corrections were applied.
+ *   vals_dev: device, the fp64 values of A (same order as the pattern);
+ *   B_dev: device, n x nrhs, leading dimension ldb (read only);
+ *   X_dev: device, n x nrhs, leading dimension ldx (output);
+ *   berr_out: host, nrhs entries (eta of the returned X), may be NULL;
+ *   iters_out: host, corrections applied, may be NULL.
+ * Returns SPCHOL_ERR_NOCONV (X holds the last iterate) when the tolerance
+ * is not reached.  Synchronizes `stream` once per iteration. */
+spchol_status spchol_refine(spchol_num num, const double *vals_dev, const double *B_dev,
+                            double *X_dev, int64_t nrhs, int64_t ldb, int64_t ldx, double tol,
+                            int32_t max_iter, void *stream, double *berr_out, int32_t *iters_out);
 
 /* Solve A X = B in place.  B_dev: device, n x nrhs column-major, leading
  * dimension ldb >= n, original (unpermuted) ordering.  Forward solve with L
  * leaves to root, backward solve with L^T root to leaves. */
 spchol_status spchol_solve(spchol_num num, double *B_dev, int64_t nrhs, int64_t ldb,
                            void *stream);
+
+/* Reverse mode of (logdet(A), X = A^{-1} B) with respect to the stored
+ * lower values of A (each off-diagonal entry stands for a_ij and a_ji) and
+ * to B, for cotangents gbar_logdet (scalar) and Xbar:
+ *   lam = A^{-1} Xbar,  Bbar = lam,
+ *   Abar_ij = gbar w_ij Z_ij - sum_c (lam_ic x_jc + lam_jc x_ic)  (i != j),
+ *   Abar_ii = gbar Z_ii - sum_c lam_ic x_ic,
+ * w_ij = 2 off the diagonal, with Z = A^{-1} on the pattern obtained by
+ * supernodal selected inversion (from Z L = L^{-T}; panels root to leaves).
+ *   X_dev, Xbar_dev: device, n x nrhs, leading dimension ld (original
+ *     ordering); Xbar_dev may be NULL (then nrhs terms are skipped);
+ *   Abar_dev: device, colptr[n] entries, overwritten;
+ *   Bbar_dev: device, n x nrhs with ld, may be NULL.
+ * gbar_logdet = 0 skips the selected inversion. */
+spchol_status spchol_backward(spchol_num num, const double *X_dev, const double *Xbar_dev,
+                              int64_t nrhs, int64_t ld, double gbar_logdet, double *Abar_dev,
+                              double *Bbar_dev, void *stream);
+
+/* Selected inverse Z = C^{-1} (C = P A P^T) on the supernodal pattern,
+ * written to caller-owned device memory in the layout of the factor
+ * (spchol_sym_storage); upper triangles of the diagonal blocks unspecified. */
+spchol_status spchol_selinv_export(spchol_num num, double *dst_dev, void *stream);
 
 /* log det(A) = 2 sum_j log L_jj, reduced on the device (pairwise tree);
  * out_host receives the value.  Synchronizes `stream`. */
@@ -179,7 +233,8 @@ enum {
   SPCHOL_KERNEL_BWD_TRI = 8,
   SPCHOL_KERNEL_PERM = 9,        /* solve permutation gather/scatter         */
   SPCHOL_KERNEL_LOGDET = 10,
-  SPCHOL_KERNEL_KINDS = 11
+  SPCHOL_KERNEL_SELINV = 11,     /* selected inversion (reverse mode)       */
+  SPCHOL_KERNEL_KINDS = 12
 };
 
 typedef struct {

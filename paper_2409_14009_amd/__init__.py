@@ -20,7 +20,7 @@ from . import _capi as capi
 from ._capi import LibraryMissing
 
 __all__ = ["SparseCholesky", "Factor", "SpcholError", "NotPositiveDefinite", "LibraryMissing",
-           "version", "lib"]
+           "version", "lib", "logdet_solve"]
 
 
 def lib():
@@ -69,6 +69,18 @@ def _dev_f64(t, what):
     if not t.is_contiguous():
         raise ValueError(f"{what} must be contiguous")
     return C.c_void_p(t.data_ptr())
+
+
+PRECISIONS = {"f64": 0, "f32": 1}
+
+
+def _precision(p):
+    if isinstance(p, int):
+        return p
+    try:
+        return PRECISIONS[p]
+    except KeyError:
+        raise ValueError(f"unknown update precision {p!r}") from None
 
 
 class SparseCholesky:
@@ -125,16 +137,18 @@ class SparseCholesky:
         _check(capi.lib().spchol_sym_storage(self._h, _hptr(off)))
         return off
 
-    def factor(self, vals, stream=None, check=True) -> "Factor":
+    def factor(self, vals, stream=None, check=True, precision="f64") -> "Factor":
         """Numeric factorization of the values `vals` (float64 CUDA tensor in
-        the pattern's entry order).  Raises NotPositiveDefinite (with .info,
-        the 1-based permuted column) when check is set."""
+        the pattern's entry order).  precision: "f64" or "f32" for the update
+        products (the diagonal-block Cholesky and the solves stay fp64).
+        Raises NotPositiveDefinite (with .info, the 1-based permuted column)
+        when check is set."""
         if vals.numel() != self.nnz_a:
             raise ValueError("vals has the wrong length")
         h = C.c_void_p()
         info = C.c_int64(0)
-        rc = capi.lib().spchol_factor(self._h, _dev_f64(vals, "vals"), _stream_ptr(stream), C.byref(h),
-                                      C.byref(info))
+        rc = capi.lib().spchol_factor_prec(self._h, _dev_f64(vals, "vals"), _precision(precision),
+                                           _stream_ptr(stream), C.byref(h), C.byref(info))
         F = Factor(self, h) if h.value else None
         if rc == -3:
             if F is not None:
@@ -166,9 +180,13 @@ class Factor:
         except Exception:
             pass
 
-    def refactor(self, vals, stream=None, check=True) -> int:
+    def refactor(self, vals, stream=None, check=True, precision=None) -> int:
         info = C.c_int64(0)
-        rc = capi.lib().spchol_refactor(self._h, _dev_f64(vals, "vals"), _stream_ptr(stream), C.byref(info))
+        if precision is None:
+            rc = capi.lib().spchol_refactor(self._h, _dev_f64(vals, "vals"), _stream_ptr(stream), C.byref(info))
+        else:
+            rc = capi.lib().spchol_refactor_prec(self._h, _dev_f64(vals, "vals"), _precision(precision),
+                                                 _stream_ptr(stream), C.byref(info))
         self.info = int(info.value)
         if rc == -3 and not check:
             return self.info
@@ -192,6 +210,65 @@ class Factor:
         Xt = B.t().contiguous()
         self.solve_(Xt, stream)
         return Xt.t()
+
+    def refine_(self, vals, Bt, Xt, tol=1e-12, max_iter=10, stream=None, check=True):
+        """Iterative refinement on (nrhs, n) contiguous tensors (column-major
+        n x nrhs blocks): Xt <- A^{-1} Bt.  Returns (berr per RHS, iterations).
+        Raises SpcholError(SPCHOL_ERR_NOCONV) when check is set and the
+        tolerance is not reached."""
+        nrhs = Bt.shape[0] if Bt.dim() == 2 else 1
+        berr = (C.c_double * max(nrhs, 1))()
+        iters = C.c_int32(0)
+        rc = capi.lib().spchol_refine(self._h, _dev_f64(vals, "vals"), _dev_f64(Bt, "B"), _dev_f64(Xt, "X"),
+                                      nrhs, self.sym.n, self.sym.n, float(tol), int(max_iter), _stream_ptr(stream),
+                                      berr, C.byref(iters))
+        out = ([berr[c] for c in range(nrhs)], int(iters.value))
+        if rc == -6 and not check:
+            return out
+        _check(rc)
+        return out
+
+    def refine(self, vals, B, tol=1e-12, max_iter=10, stream=None, check=True):
+        """X = A^{-1} B by iterative refinement with this factor; B of shape
+        (n,) or (n, nrhs).  Returns (X, berr list, iterations)."""
+        import torch
+        one = B.dim() == 1
+        Bt = (B.view(1, -1) if one else B.t()).contiguous()
+        Xt = torch.empty_like(Bt)
+        berr, it = self.refine_(vals, Bt, Xt, tol, max_iter, stream, check)
+        X = Xt.view(-1) if one else Xt.t()
+        return X, berr, it
+
+    def backward(self, X, Xbar, gbar_logdet, stream=None):
+        """Reverse mode of (logdet, X = A^{-1} B): returns (Abar, Bbar) for
+        the stored lower values of A and for B.  X, Xbar: (n,) or (n, nrhs)
+        float64 CUDA tensors (Xbar may be None); gbar_logdet: float."""
+        import torch
+        n = self.sym.n
+        Abar = torch.empty(max(self.sym.nnz_a, 1), dtype=torch.float64, device="cuda")[: self.sym.nnz_a]
+        if Xbar is None or X is None:
+            _check(capi.lib().spchol_backward(self._h, None, None, 0, max(n, 1), float(gbar_logdet),
+                                              C.c_void_p(Abar.data_ptr()), None, _stream_ptr(stream)))
+            return Abar, None
+        one = X.dim() == 1
+        Xt = (X.view(1, -1) if one else X.t()).contiguous()
+        Gt = (Xbar.view(1, -1) if one else Xbar.t()).contiguous()
+        Bt = torch.empty_like(Xt)
+        nrhs = Xt.shape[0]
+        _check(capi.lib().spchol_backward(self._h, _dev_f64(Xt, "X"), _dev_f64(Gt, "Xbar"), nrhs, n,
+                                          float(gbar_logdet), C.c_void_p(Abar.data_ptr()),
+                                          _dev_f64(Bt, "Bbar"), _stream_ptr(stream)))
+        Bbar = Bt.view(-1) if one else Bt.t()
+        return Abar, Bbar
+
+    def selinv(self, stream=None):
+        """Selected inverse of C = P A P^T on the supernodal pattern, in the
+        storage layout of L (float64 CUDA tensor)."""
+        import torch
+        n = int(self.sym.info()["storage"])
+        out = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+        _check(capi.lib().spchol_selinv_export(self._h, C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out[:n]
 
     def logdet(self, stream=None) -> float:
         out = C.c_double(0.0)
@@ -217,3 +294,44 @@ class Factor:
         out = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
         _check(capi.lib().spchol_num_export(self._h, C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out[:n]
+
+
+def _autograd():
+    import torch
+
+    class LogdetSolve(torch.autograd.Function):
+        """(logdet(A), A^{-1} b) as a differentiable function of the stored
+        lower values of A and of b; the backward pass is the library's
+        reverse-mode kernels (selected inversion + adjoint solve)."""
+
+        @staticmethod
+        def forward(ctx, vals, b, sym, precision):
+            F = sym.factor(vals.detach(), precision=precision)
+            x = F.solve(b.detach())
+            ld = F.logdet()
+            ctx.F = F
+            ctx.save_for_backward(x)
+            return torch.tensor(ld, dtype=torch.float64, device=vals.device), x
+
+        @staticmethod
+        def backward(ctx, gld, gx):
+            (x,) = ctx.saved_tensors
+            gl = float(gld) if gld is not None else 0.0
+            Abar, Bbar = ctx.F.backward(x, gx.contiguous() if gx is not None else None, gl)
+            if Bbar is None:
+                Bbar = torch.zeros_like(x)
+            return Abar, Bbar, None, None
+
+    return LogdetSolve
+
+
+_LogdetSolve = None
+
+
+def logdet_solve(sym: SparseCholesky, vals, b, precision="f64"):
+    """Differentiable (logdet(A), x = A^{-1} b) for the pattern analysed in
+    `sym`; gradients flow to `vals` (stored lower entries) and `b`."""
+    global _LogdetSolve
+    if _LogdetSolve is None:
+        _LogdetSolve = _autograd()
+    return _LogdetSolve.apply(vals, b, sym, precision)

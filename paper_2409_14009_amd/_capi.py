@@ -31,7 +31,7 @@ class KernelStat(C.Structure):
 
 
 KERNEL_KINDS = ["fill", "scatter_a", "factor", "update_int", "update_ext", "fwd_tri", "fwd_gemv",
-                "bwd_gemvt", "bwd_tri", "perm", "logdet"]
+                "bwd_gemvt", "bwd_tri", "perm", "logdet", "selinv"]
 
 # name -> (restype, argtypes)
 PROTOTYPES = {
@@ -42,9 +42,14 @@ PROTOTYPES = {
     "spchol_sym_storage": (i32, [vp, vp]),
     "spchol_factor": (i32, [vp, vp, vp, C.POINTER(vp), i64p]),
     "spchol_refactor": (i32, [vp, vp, vp, i64p]),
+    "spchol_factor_prec": (i32, [vp, vp, i32, vp, C.POINTER(vp), i64p]),
+    "spchol_refactor_prec": (i32, [vp, vp, i32, vp, i64p]),
+    "spchol_refine": (i32, [vp, vp, vp, vp, i64, i64, i64, f64, i32, vp, f64p, C.POINTER(i32)]),
     "spchol_solve": (i32, [vp, vp, i64, i64, vp]),
     "spchol_logdet": (i32, [vp, f64p, vp]),
     "spchol_num_export": (i32, [vp, vp, vp]),
+    "spchol_backward": (i32, [vp, vp, vp, i64, i64, f64, vp, vp, vp]),
+    "spchol_selinv_export": (i32, [vp, vp, vp]),
     "spchol_profile": (i32, [vp, i32]),
     "spchol_profile_read": (i32, [vp, C.POINTER(KernelStat)]),
     "spchol_sym_destroy": (None, [vp]),

@@ -302,6 +302,33 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
         }
         S.amap[p] = S.loff[J] + (c - f) * m + pos;
       }
+    // ---- full-symmetric CSR of A (original ordering) ----------------------
+    S.a_rp.assign(n + 1, 0);
+    for (int64_t j = 0; j < n; ++j)
+      for (int64_t p = colptr[j]; p < colptr[j + 1]; ++p) {
+        S.a_rp[rowind[p] + 1]++;
+        if (rowind[p] != j) S.a_rp[j + 1]++;
+      }
+    for (int64_t i = 0; i < n; ++i) S.a_rp[i + 1] += S.a_rp[i];
+    S.a_col.resize(S.a_rp[n]);
+    S.a_vidx.resize(S.a_rp[n]);
+    {
+      // row i gets (i, j) for the lower entries of row i (j <= i, from the
+      // columns j in increasing order) and then (i, r) for the entries of
+      // column i below the diagonal: columns ascend within each row
+      std::vector<int64_t> fill(S.a_rp.begin(), S.a_rp.end() - 1);
+      for (int64_t j = 0; j < n; ++j)
+        for (int64_t p = colptr[j]; p < colptr[j + 1]; ++p) {
+          const int64_t i = rowind[p];
+          S.a_col[fill[i]] = (int32_t)j;
+          S.a_vidx[fill[i]++] = p;
+        }
+      for (int64_t j = 0; j < n; ++j)
+        for (int64_t p = colptr[j] + 1; p < colptr[j + 1]; ++p) {
+          S.a_col[fill[j]] = (int32_t)rowind[p];
+          S.a_vidx[fill[j]++] = p;
+        }
+    }
     // ---- levels --------------------------------------------------------
     S.level.assign(ns, 0);
     for (int64_t J = 0; J < ns; ++J)
@@ -465,6 +492,52 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
         close(S.bwd_plan);
       }
     }
+    // selected inversion (reverse mode): root to leaves, last panel first;
+    // the panels of one round get slots 0.. (inverse, T) and Y blocks
+    for (int64_t l = S.nlevels - 1; l >= 0; --l) {
+      int64_t maxp = 0;
+      for (int32_t J : bylev[l]) maxp = std::max(maxp, npan(J));
+      for (int64_t p = maxp - 1; p >= 0; --p) {
+        std::vector<int32_t> js;
+        for (int32_t J : bylev[l])
+          if (npan(J) > p) js.push_back(J);
+        const int64_t base = (int64_t)S.si_yoff.size();
+        int64_t yo = 0;
+        for (int32_t J : js) {
+          S.si_yoff.push_back(yo);
+          yo += (M(J) - (p * nb + kpan(J, p))) * kMaxPanel;
+        }
+        S.si_max_slots = std::max<int64_t>(S.si_max_slots, (int64_t)js.size());
+        S.si_max_y = std::max(S.si_max_y, yo);
+        const int32_t kinds[4] = {K_SI_W, K_SI_Y, K_SI_ZB, K_SI_ZD};
+        for (int32_t kind : kinds) {
+          open(S.si_plan, kind, (int32_t)l, (int32_t)p);
+          S.si_plan.back().slot_base = base;
+          for (size_t s = 0; s < js.size(); ++s) {
+            const int32_t J = js[s];
+            if (kind == K_SI_Y || kind == K_SI_ZB) {
+              for (int64_t a0 = p * nb + kpan(J, p); a0 < M(J); a0 += kTile)
+                S.tasks.push_back({J, (int32_t)p, (int32_t)a0, (int32_t)s});
+            } else {
+              S.tasks.push_back({J, (int32_t)p, 0, (int32_t)s});
+            }
+          }
+          // keep the launch even when empty for K_SI_W (it carries the
+          // round's slot count for the T reset)
+          Launch& Lb = S.si_plan.back();
+          Lb.ntasks = (int32_t)((int64_t)S.tasks.size() - Lb.off);
+          if (Lb.ntasks == 0) S.si_plan.pop_back();
+        }
+      }
+    }
+    // row and column of each stored entry (original ordering)
+    S.e_row.resize(nz);
+    S.e_col.resize(nz);
+    for (int64_t j = 0; j < n; ++j)
+      for (int64_t p = colptr[j]; p < colptr[j + 1]; ++p) {
+        S.e_row[p] = (int32_t)rowind[p];
+        S.e_col[p] = (int32_t)j;
+      }
     if (S.tasks.size() >= (size_t(1) << 31)) { err = "analyze: schedule too large"; return ERR_OOM; }
     return 0;
   } catch (const std::bad_alloc&) {

@@ -31,6 +31,10 @@ enum Kind : int32_t {
   K_BWD_GEMVT = 5,
   K_BWD_TRI = 6,
   K_TRSM = 7,
+  K_SI_W = 8,   // selected inversion: inverse of the panel's diagonal block
+  K_SI_Y = 9,   // Y = Z_BB L_Bp tiles
+  K_SI_ZB = 10, // Z_Bp = -Y W tiles (+ T)
+  K_SI_ZD = 11, // Z_pp = (W^T - T) W
 };
 
 struct Launch {
@@ -41,6 +45,7 @@ struct Launch {
   int32_t panel;
   double flops = 0;  // algorithmic flops of the launch (stored structure)
   double bytes = 0;  // algorithmic HBM bytes of the launch
+  int64_t slot_base = 0;  // selected inversion: first entry of si_yoff for this round
 };
 
 constexpr int kTile = 64;      // rows (and cols) of an update tile
@@ -66,13 +71,20 @@ struct Symbolic {
   std::vector<int64_t> level;    // per supernode
   std::vector<int64_t> amap;     // nnzA: storage offset of each entry of A
   std::vector<int64_t> snode_of; // n: supernode of each column
+  // full-symmetric CSR of A in the original ordering; each entry indexes the
+  // stored lower-triangle value array (residuals of iterative refinement)
+  std::vector<int64_t> a_rp, a_vidx;
+  std::vector<int32_t> a_col;
   int64_t nlevels = 0;
   int64_t max_k = 0, max_m = 0;
   int64_t max_slots = 0;  // inverted diagonal blocks held at once (scratch)
   double flops_alg = 0, flops_exec = 0;
   // schedule
   std::vector<Task> tasks;
-  std::vector<Launch> factor_plan, fwd_plan, bwd_plan;
+  std::vector<Launch> factor_plan, fwd_plan, bwd_plan, si_plan;
+  std::vector<int64_t> si_yoff;  // per selected-inversion slot: offset of its Y block
+  int64_t si_max_slots = 0, si_max_y = 0;
+  std::vector<int32_t> e_row, e_col;  // row and column of each stored entry of A
 };
 
 // Returns 0, or a negative spchol_status with a message in err.

@@ -28,6 +28,11 @@ struct DevSym {
   const int64_t* amap;    // nnzA
   const int64_t* perm;    // n
   const DevTask* tasks;
+  const int64_t* a_rp;    // n+1: full-symmetric CSR of A (original ordering)
+  const int32_t* a_col;   // column of each entry
+  const int64_t* a_vidx;  // index of each entry in the stored lower values
+  const int32_t* e_row;   // nnzA: row of each stored lower entry of A (original)
+  const int32_t* e_col;   // nnzA: its column
   int64_t n, ns, nnzA, storage;
   int32_t nb;
 };
@@ -39,7 +44,17 @@ hipError_t launch_scatter_values(const DevSym& S, const double* vals, double* L,
 hipError_t launch_factor_panel(const DevSym& S, double* L, int64_t off, int32_t ntasks,
                                unsigned long long* status, double* scratch, bool diag, hipStream_t st);
 hipError_t launch_update(const DevSym& S, double* L, int32_t kind, int64_t off, int32_t ntasks,
-                         hipStream_t st);
+                         int32_t prec, hipStream_t st);
+hipError_t launch_si(const DevSym& S, int32_t kind, int64_t off, int32_t ntasks, const double* L, double* Z,
+                     const int64_t* yoff, double* ybuf, double* wbuf, double* tbuf, hipStream_t st);
+hipError_t launch_abar(const DevSym& S, const double* Z, double g, const double* X, const double* lam, int64_t ld,
+                       int64_t nrhs, double* Abar, hipStream_t st);
+hipError_t launch_anorm(const DevSym& S, const double* vals, unsigned long long* out, hipStream_t st);
+hipError_t launch_residual(const DevSym& S, const double* vals, const double* B, int64_t ldb, const double* X,
+                           int64_t ldx, int64_t nrhs, double* R, unsigned long long* stats, hipStream_t st);
+hipError_t launch_axpy(double* X, int64_t ldx, const double* D, int64_t n, int64_t nrhs, hipStream_t st);
+hipError_t launch_copy_cols(double* Y, int64_t ldy, const double* B, int64_t ldb, int64_t n, int64_t nrhs,
+                            hipStream_t st);
 hipError_t launch_perm_gather(const DevSym& S, const double* B, int64_t ldb, int64_t nrhs, double* y,
                               hipStream_t st);
 hipError_t launch_perm_scatter(const DevSym& S, const double* y, int64_t nrhs, double* B, int64_t ldb,

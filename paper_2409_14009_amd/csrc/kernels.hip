@@ -97,20 +97,22 @@ __device__ __forceinline__ void potrf16(double (&r)[MB], int lane, int j0, doubl
   }
 }
 
-// One wavefront's share of X = B W^T for a 64-row tile (B staged in LDS
-// column-major As[k * DLD + r], W column-major Wc[c * DLD + i] = W_ic):
+// One wavefront's share of X = A V^T for a 64-row tile (A staged in LDS
+// column-major As[k * DLD + r], V column-major Wc[c * DLD + i] = V_ic):
 // wavefront w computes the 16 output columns 16w..16w+15 of all 64 rows on
-// the fp64 matrix cores and writes them to rows R0.. of the panel.
-__device__ __forceinline__ void trsm_tile_mfma(const double* __restrict__ As, const double* __restrict__ Wc,
-                                               int kp, int lane, int w, double* __restrict__ Lp, int m,
-                                               int R0) {
+// the fp64 matrix cores and stores sign * X to rows R0 + r < rowEnd of dst
+// (dst[c * ld + row]); with lower set only entries row >= R0 + c are stored.
+// K = kp (columns past kp are zero in As).
+__device__ __forceinline__ void tile_mfma(const double* __restrict__ As, const double* __restrict__ Wc, int kp,
+                                          int lane, int w, double* __restrict__ dst, int ld, int R0, int rowEnd,
+                                          bool lower, double sign) {
   if (MB * w >= kp) return;
   const int li = lane & 15, lk = lane >> 4;
   d4 acc[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
   // k in chunks of 16: all LDS operands of a chunk are read before its
-  // 16 MFMAs (columns past kp are zero in As)
+  // 16 MFMAs
   for (int s0 = 0; s0 < kp; s0 += 16) {
     double bv[4], av[4][4];
 #pragma unroll
@@ -127,13 +129,14 @@ __device__ __forceinline__ void trsm_tile_mfma(const double* __restrict__ As, co
   }
   const int c = MB * w + li;
   if (c < kp) {
-    double* dst = Lp + (int64_t)c * m;
+    double* d = dst + (int64_t)c * ld;
 #pragma unroll
     for (int rb2 = 0; rb2 < 4; ++rb2)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = R0 + 16 * rb2 + 4 * v + lk;
-        if (r < m) dst[r] = acc[rb2][v];
+        const int rr = 16 * rb2 + 4 * v + lk;
+        const int r = R0 + rr;
+        if (r < rowEnd && (!lower || rr >= c)) d[r] = sign * acc[rb2][v];
       }
   }
 }
@@ -153,6 +156,54 @@ __device__ __forceinline__ void stage_rows(double* __restrict__ As, const double
     for (int u = 0; u < 16; ++u) {
       const int idx = base + u * nthr + tid;
       As[(idx >> 6) * DLD + (idx & 63)] = v[u];
+    }
+  }
+}
+
+// W = inverse of the lower-triangular block in Dc (column-major, padded
+// with an identity past kp; Wc zeroed beforehand), by 16 x 16 blocks:
+// wavefront b inverts L_bb by substitution, then computes
+// W_ib = -W_ii sum_{t=b}^{i-1} L_it W_tb on the matrix cores.
+__device__ __forceinline__ void invert_diag_block(const double* __restrict__ Dc, double* __restrict__ Wc, int nblk,
+                                                  int lane, int w) {
+  // inverses of the 16 x 16 diagonal blocks: lane l < 16 of wavefront w
+  //     computes column l of inv(L_ww)
+  if (w < nblk && lane < MB) {
+    const int b0 = MB * w;
+    double x[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+      double s = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+      for (int q = 0; q < i; ++q) s = fma(-Dc[(b0 + q) * DLD + b0 + i], x[q], s);
+      x[i] = s / Dc[(b0 + i) * DLD + b0 + i];
+    }
+#pragma unroll
+    for (int i = 0; i < MB; ++i) Wc[(b0 + lane) * DLD + b0 + i] = x[i];
+  }
+  __syncthreads();
+  // off-diagonal blocks of column block b = w, top to bottom
+  if (w < nblk) {
+    const int b = w, li = lane & 15, lk = lane >> 4;
+    for (int i = b + 1; i < nblk; ++i) {
+      d4 T = d4{0.0, 0.0, 0.0, 0.0};
+      for (int tb = b; tb < i; ++tb)
+#pragma unroll
+        for (int s = 0; s < MB; s += 4) {
+          const double av = Dc[(MB * tb + s + lk) * DLD + MB * i + li];   // L[16i + li][16tb + s + lk]
+          const double bv = Wc[(MB * b + li) * DLD + MB * tb + s + lk];   // W[16tb + s + lk][16b + li]
+          T = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, T, 0, 0, 0);
+        }
+      // W_ib = -W_ii T; T's accumulator element v is exactly the B operand
+      // of k-step v (row 4v + lk, column li)
+      d4 O = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double av = Wc[(MB * i + 4 * s + lk) * DLD + MB * i + li];  // W[16i + li][16i + 4s + lk]
+        O = __builtin_amdgcn_mfma_f64_16x16x4f64(av, T[s], O, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Wc[(MB * b + li) * DLD + MB * i + 4 * v + lk] = -O[v];
     }
   }
 }
@@ -255,46 +306,8 @@ __global__ __launch_bounds__(256) void k_panel(DevSym S, double* __restrict__ L,
       if (c < kp && c <= lane) dst[(int64_t)c * m] = Dc[c * DLD + lane];
   }
 
-  // 2a. inverses of the 16 x 16 diagonal blocks: lane l < 16 of wavefront w
-  //     computes column l of inv(L_ww)
-  if (w < nblk && lane < MB) {
-    const int b0 = MB * w;
-    double x[MB];
-#pragma unroll
-    for (int i = 0; i < MB; ++i) {
-      double s = (i == lane) ? 1.0 : 0.0;
-#pragma unroll
-      for (int q = 0; q < i; ++q) s = fma(-Dc[(b0 + q) * DLD + b0 + i], x[q], s);
-      x[i] = s / Dc[(b0 + i) * DLD + b0 + i];
-    }
-#pragma unroll
-    for (int i = 0; i < MB; ++i) Wc[(b0 + lane) * DLD + b0 + i] = x[i];
-  }
-  __syncthreads();
-  // 2b. off-diagonal blocks of column block b = w, top to bottom
-  if (w < nblk) {
-    const int b = w, li = lane & 15, lk = lane >> 4;
-    for (int i = b + 1; i < nblk; ++i) {
-      d4 T = d4{0.0, 0.0, 0.0, 0.0};
-      for (int tb = b; tb < i; ++tb)
-#pragma unroll
-        for (int s = 0; s < MB; s += 4) {
-          const double av = Dc[(MB * tb + s + lk) * DLD + MB * i + li];   // L[16i + li][16tb + s + lk]
-          const double bv = Wc[(MB * b + li) * DLD + MB * tb + s + lk];   // W[16tb + s + lk][16b + li]
-          T = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, T, 0, 0, 0);
-        }
-      // W_ib = -W_ii T; T's accumulator element v is exactly the B operand
-      // of k-step v (row 4v + lk, column li)
-      d4 O = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const double av = Wc[(MB * i + 4 * s + lk) * DLD + MB * i + li];  // W[16i + li][16i + 4s + lk]
-        O = __builtin_amdgcn_mfma_f64_16x16x4f64(av, T[s], O, 0, 0, 0);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Wc[(MB * b + li) * DLD + MB * i + 4 * v + lk] = -O[v];
-    }
-  }
+  // 2. W = L_pp^{-1}
+  invert_diag_block(Dc, Wc, nblk, lane, w);
   __syncthreads();
 
   // 4. W for the row-tile launch, row-major: scratch[slot][r * 64 + c] = W_rc
@@ -306,7 +319,7 @@ __global__ __launch_bounds__(256) void k_panel(DevSym S, double* __restrict__ L,
   for (int R0 = rb; R0 < min(rb + 4 * 64, m); R0 += 64) {
     stage_rows(Dc, Lp, m, kp, R0, tid, 256);
     __syncthreads();
-    trsm_tile_mfma(Dc, Wc, kp, lane, w, Lp, m, R0);
+    tile_mfma(Dc, Wc, kp, lane, w, Lp, m, R0, m, false, 1.0);
     __syncthreads();
   }
 }
@@ -337,28 +350,57 @@ __global__ __launch_bounds__(256) void k_panel_rows(DevSym S, double* __restrict
   }
   stage_rows(As, Lp, m, kp, R0, tid, 256);
   __syncthreads();
-  trsm_tile_mfma(As, Wc, kp, lane, w, Lp, m, R0);
+  tile_mfma(As, Wc, kp, lane, w, Lp, m, R0, m, false, 1.0);
 }
 
 // ---------------------------------------------------------------------------
 // update: C[i, c] -= sum_t L[i, t] L[c, t] over a 64 x 64 tile, lower part,
-// on the fp64 matrix cores (16x16x4 MFMA, four wavefronts of 32 x 32).
+// on the matrix cores (16x16x4 MFMA, four wavefronts of 32 x 32).
 //   kind 1 (internal): the remaining columns of J itself, K = one panel;
 //                      plain read-modify-write (one writer per entry).
 //   kind 2 (external): the update matrix L_RJ L_RJ^T (Sec. II-A, Fig. 2),
 //                      K = all columns of J, scattered into the ancestors
 //                      through the relative indices; atomic adds because
 //                      several supernodes of a level may hit one ancestor.
-// MFMA operand layout (one wavefront, fp64 16x16x4, checked on gfx950):
-// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
-// D[4 v + l / 16][l % 16] in its accumulator element v = 0..3.
+// Precision P: 0 = fp64 operands and accumulation; 1 = operands rounded to
+// fp32 while staging into LDS, fp32 accumulation (the mixed-precision
+// form); the scatter is always fp64.
+// MFMA operand layout (one wavefront, 16x16x4, checked on gfx950): lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; fp64 accumulator
+// element v holds D[4 v + l / 16][l % 16], fp32 element v holds
+// D[4 (l / 16) + v][l % 16].
 // ---------------------------------------------------------------------------
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <int P> struct UpdPrec;
+template <> struct UpdPrec<0> {
+  using T = double;
+  using Acc = d4;
+  static __device__ __forceinline__ Acc zero() { return d4{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ Acc mma(T a, T b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int v, int lk) { return 4 * v + lk; }
+};
+template <> struct UpdPrec<1> {
+  using T = float;
+  using Acc = f4;
+  static __device__ __forceinline__ Acc zero() { return f4{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ Acc mma(T a, T b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int v, int lk) { return 4 * lk + v; }
+};
 
 constexpr int ALD = TILE + 2;
 
+template <int P>
 __global__ __launch_bounds__(256) void k_update(DevSym S, double* __restrict__ L, int32_t kind, int64_t off) {
-  __shared__ double As[KC * ALD];
-  __shared__ double Bs[KC * ALD];
+  using Pr = UpdPrec<P>;
+  using T = typename Pr::T;
+  __shared__ T As[KC * ALD];
+  __shared__ T Bs[KC * ALD];
   const DevTask t = S.tasks[off + blockIdx.x];
   const int J = t.J, row0 = t.a, col0 = t.b;
   const int m = S.sm[J], k = S.sk[J];
@@ -376,11 +418,11 @@ __global__ __launch_bounds__(256) void k_update(DevSym S, double* __restrict__ L
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
-  d4 acc[2][2];
+  typename Pr::Acc acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 2; ++j) acc[i][j] = Pr::zero();
 
   // staging: thread loads rows (tid & 63) of chunk columns (tid >> 6) + 4q
   const int sr = tid & 63, sc = tid >> 6;
@@ -400,20 +442,20 @@ __global__ __launch_bounds__(256) void k_update(DevSym S, double* __restrict__ L
   for (int kk = kb; kk < ke; kk += KC) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      As[(sc + 4 * q) * ALD + sr] = ra[q];
-      Bs[(sc + 4 * q) * ALD + sr] = rb[q];
+      As[(sc + 4 * q) * ALD + sr] = (T)ra[q];
+      Bs[(sc + 4 * q) * ALD + sr] = (T)rb[q];
     }
     __syncthreads();
     if (kk + KC < ke) fetch(kk + KC);
 #pragma unroll
     for (int ks = 0; ks < KC; ks += 4) {
       const int kr = (ks + lk) * ALD;
-      const double a0 = As[kr + wr + li], a1 = As[kr + wr + 16 + li];
-      const double b0 = Bs[kr + wc + li], b1 = Bs[kr + wc + 16 + li];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      const T a0 = As[kr + wr + li], a1 = As[kr + wr + 16 + li];
+      const T b0 = Bs[kr + wc + li], b1 = Bs[kr + wc + 16 + li];
+      acc[0][0] = Pr::mma(a0, b0, acc[0][0]);
+      acc[0][1] = Pr::mma(a0, b1, acc[0][1]);
+      acc[1][0] = Pr::mma(a1, b0, acc[1][0]);
+      acc[1][1] = Pr::mma(a1, b1, acc[1][1]);
     }
     __syncthreads();
   }
@@ -427,8 +469,8 @@ __global__ __launch_bounds__(256) void k_update(DevSym S, double* __restrict__ L
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int gr = row0 + wr + 16 * bi + 4 * v + lk;
-          if (gr < m && gr >= gc) Lj[(int64_t)gc * m + gr] -= acc[bi][bj][v];
+          const int gr = row0 + wr + 16 * bi + Pr::row(v, lk);
+          if (gr < m && gr >= gc) Lj[(int64_t)gc * m + gr] -= (double)acc[bi][bj][v];
         }
     }
   } else {
@@ -445,8 +487,8 @@ __global__ __launch_bounds__(256) void k_update(DevSym S, double* __restrict__ L
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int gr = row0 + wr + 16 * bi + 4 * v + lk;
-          if (gr < m && gr >= gc) atomicAdd(L + cbase + tp[gr], -acc[bi][bj][v]);
+          const int gr = row0 + wr + 16 * bi + Pr::row(v, lk);
+          if (gr < m && gr >= gc) atomicAdd(L + cbase + tp[gr], -(double)acc[bi][bj][v]);
         }
     }
   }
@@ -663,6 +705,289 @@ __global__ __launch_bounds__(256) void k_logdet_final(const double* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// reverse mode: selected inversion Z = C^{-1} on the supernodal pattern of L
+// (C = P A P^T), stored in the layout of L.  From Z L = L^{-T} (upper
+// triangular) follow, for a panel p of supernode J (columns c0..c0+kp) with
+// the rows B of J below it:
+//   Z_Bp = -Z_BB L_Bp L_pp^{-1},      Z_pp = (W^T - Z_Bp^T L_Bp) W,
+// with W = L_pp^{-1}.  Panels are visited root to leaves and, inside a
+// supernode, last panel first, so Z_BB (later columns of J, then ancestors
+// reached through the relative indices) is final when needed.  Per panel:
+//   k_si_w   W into scratch (row-major, slot s);
+//   k_si_y   Y = Z_BB L_Bp, 64-row tiles, Z_BB gathered (symmetric);
+//   k_si_zb  Z_Bp = -Y W per tile, and T += Z_Bp^T L_Bp (atomic);
+//   k_si_zd  Z_pp = (W^T - T) W, lower part.
+// Task fields: J, panel, first local row of the tile, slot in the launch.
+// ---------------------------------------------------------------------------
+
+// offset in Z (layout of L) of the symmetric entry at local rows (a, b) of
+// J, both at or below J's first column
+__device__ __forceinline__ int64_t zsym_off(const DevSym& S, int J, int k, int m, int64_t ob, int a, int b) {
+  const int lo = min(a, b), hi = max(a, b);
+  if (lo < k) return S.loff[J] + (int64_t)lo * m + hi;
+  const int pair = S.opair[ob + lo - k];
+  return S.ocbase[ob + lo - k] + S.tpos[S.relptr[pair] - S.pa0[pair] + (hi - k)];
+}
+
+__global__ __launch_bounds__(256) void k_si_w(DevSym S, const double* __restrict__ L, int64_t off,
+                                              double* __restrict__ wbuf) {
+  __shared__ __attribute__((aligned(16))) double Dc[NBMAX * DLD];
+  __shared__ __attribute__((aligned(16))) double Wc[NBMAX * DLD];
+  const DevTask t = S.tasks[off + blockIdx.x];
+  const int J = t.J, p = t.a, slot = t.c;
+  const int m = S.sm[J], k = S.sk[J];
+  const int c0 = p * S.nb, kp = min(S.nb, k - c0);
+  const double* __restrict__ Lp = L + S.loff[J] + (int64_t)c0 * m;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int idx = tid; idx < NBMAX * NBMAX; idx += 256) {
+    const int i = idx & 63, c = idx >> 6;
+    Dc[c * DLD + i] = (i < kp && c <= i) ? Lp[(int64_t)c * m + c0 + i] : (i == c ? 1.0 : 0.0);
+    Wc[c * DLD + i] = 0.0;
+  }
+  __syncthreads();
+  invert_diag_block(Dc, Wc, (kp + MB - 1) / MB, lane, w);
+  __syncthreads();
+  double* dst = wbuf + (int64_t)slot * NBMAX * NBMAX;
+  for (int idx = tid; idx < NBMAX * NBMAX; idx += 256) dst[idx] = Wc[(idx & 63) * DLD + (idx >> 6)];
+}
+
+// Y[a][t] = sum_{b in B} Z(a, b) L[b][c0 + t] for a in [a0, a0 + 64)
+__global__ __launch_bounds__(256) void k_si_y(DevSym S, const double* __restrict__ L, const double* __restrict__ Z,
+                                              int64_t off, const int64_t* __restrict__ yoff,
+                                              double* __restrict__ ybuf) {
+  __shared__ double As[KC * ALD];
+  __shared__ double Bs[KC * ALD];
+  const DevTask t = S.tasks[off + blockIdx.x];
+  const int J = t.J, p = t.a, a0 = t.b, slot = t.c;
+  const int m = S.sm[J], k = S.sk[J];
+  const int c0 = p * S.nb, kp = min(S.nb, k - c0);
+  const int rb = c0 + kp;
+  const double* __restrict__ Lj = L + S.loff[J];
+  const int64_t ob = S.obase[J];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  d4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  const int sr = tid & 63, sc = tid >> 6;
+  const int a = a0 + sr;
+  for (int b0 = rb; b0 < m; b0 += KC) {
+    double ra[4], rbv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = b0 + sc + 4 * q;
+      ra[q] = (a < m && b < m) ? Z[zsym_off(S, J, k, m, ob, a, b)] : 0.0;
+      rbv[q] = (b < m && sr < kp) ? Lj[(int64_t)(c0 + sr) * m + b] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      As[(sc + 4 * q) * ALD + sr] = ra[q];   // As[kb][a - a0]
+      Bs[(sc + 4 * q) * ALD + sr] = rbv[q];  // Bs[kb][t]
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < KC; ks += 4) {
+      const int kr = (ks + lk) * ALD;
+      const double x0 = As[kr + wr + li], x1 = As[kr + wr + 16 + li];
+      const double y0 = Bs[kr + wc + li], y1 = Bs[kr + wc + 16 + li];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* __restrict__ Y = ybuf + yoff[slot];
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj) {
+    const int tc = wc + 16 * bj + li;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ar = a0 + wr + 16 * bi + 4 * v + lk;
+        if (ar < m && tc < kp) Y[(int64_t)(ar - rb) * NBMAX + tc] = acc[bi][bj][v];
+      }
+  }
+}
+
+// Z_Bp = -Y W on rows [a0, a0 + 64), and T += Z_Bp^T L_Bp
+__global__ __launch_bounds__(256) void k_si_zb(DevSym S, const double* __restrict__ L, double* __restrict__ Z,
+                                               int64_t off, const int64_t* __restrict__ yoff,
+                                               const double* __restrict__ ybuf, const double* __restrict__ wbuf,
+                                               double* __restrict__ tbuf) {
+  __shared__ __attribute__((aligned(16))) double As[NBMAX * DLD];
+  __shared__ __attribute__((aligned(16))) double Wc[NBMAX * DLD];
+  const DevTask t = S.tasks[off + blockIdx.x];
+  const int J = t.J, p = t.a, a0 = t.b, slot = t.c;
+  const int m = S.sm[J], k = S.sk[J];
+  const int c0 = p * S.nb, kp = min(S.nb, k - c0);
+  const int rb = c0 + kp;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const double* __restrict__ Y = ybuf + yoff[slot];
+  const double* __restrict__ W = wbuf + (int64_t)slot * NBMAX * NBMAX;
+  for (int idx = tid; idx < NBMAX * NBMAX; idx += 256) {
+    const int r = idx >> 6, c = idx & 63;  // Y row-major, W row-major
+    As[c * DLD + r] = (a0 + r < m && c < kp) ? Y[(int64_t)(a0 + r - rb) * NBMAX + c] : 0.0;
+    // V = W^T column-major: Wc[c * DLD + i] = V_ic = W_ci
+    Wc[r * DLD + c] = W[idx];
+  }
+  __syncthreads();
+  double* __restrict__ Zp = Z + S.loff[J] + (int64_t)c0 * m;
+  // Z_Bp = -(Y V^T) = -(Y W)
+  tile_mfma(As, Wc, kp, lane, w, Zp, m, a0, m, false, -1.0);
+  __syncthreads();
+  // T partial: stage Z tile (column-major, zero past m) in As and L_Bp tile in Wc
+  const double* __restrict__ Lp = L + S.loff[J] + (int64_t)c0 * m;
+  for (int idx = tid; idx < NBMAX * NBMAX; idx += 256) {
+    const int r = idx & 63, c = idx >> 6;
+    const bool in = a0 + r < m && c < kp;
+    As[c * DLD + r] = in ? Zp[(int64_t)c * m + a0 + r] : 0.0;
+    Wc[c * DLD + r] = in ? Lp[(int64_t)c * m + a0 + r] : 0.0;
+  }
+  __syncthreads();
+  // T[s][c] = sum_r Z[r][s] L[r][c]: A operand A[s][r] = Z[r][s] = As[s * DLD + r],
+  // B operand B[r][c] = L[r][c] = Wc[c * DLD + r]; wavefront w owns columns 16w..
+  if (MB * w < kp) {
+    const int li = lane & 15, lk = lane >> 4;
+    d4 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int r0 = 0; r0 < NBMAX; r0 += 4) {
+      const double bv = Wc[(MB * w + li) * DLD + r0 + lk];
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) {
+        const double av = As[(16 * sb + li) * DLD + r0 + lk];
+        acc[sb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[sb], 0, 0, 0);
+      }
+    }
+    double* Tt = tbuf + (int64_t)slot * NBMAX * NBMAX;
+    const int c = MB * w + li;
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int s = 16 * sb + 4 * v + lk;
+        if (s < kp && c < kp) atomicAdd(Tt + s * NBMAX + c, acc[sb][v]);
+      }
+  }
+}
+
+// Z_pp = (W^T - T) W, lower part
+__global__ __launch_bounds__(256) void k_si_zd(DevSym S, double* __restrict__ Z, int64_t off,
+                                               const double* __restrict__ wbuf, const double* __restrict__ tbuf) {
+  __shared__ __attribute__((aligned(16))) double As[NBMAX * DLD];
+  __shared__ __attribute__((aligned(16))) double Wc[NBMAX * DLD];
+  const DevTask t = S.tasks[off + blockIdx.x];
+  const int J = t.J, p = t.a, slot = t.c;
+  const int m = S.sm[J], k = S.sk[J];
+  const int c0 = p * S.nb, kp = min(S.nb, k - c0);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const double* __restrict__ W = wbuf + (int64_t)slot * NBMAX * NBMAX;
+  const double* __restrict__ T = tbuf + (int64_t)slot * NBMAX * NBMAX;
+  for (int idx = tid; idx < NBMAX * NBMAX; idx += 256) {
+    const int r = idx >> 6, c = idx & 63;
+    // M = W^T - T column-major: As[c * DLD + r] = W[c][r] - T[r][c]
+    As[c * DLD + r] = W[c * NBMAX + r] - T[idx];
+    Wc[r * DLD + c] = W[idx];  // V = W^T column-major
+  }
+  __syncthreads();
+  double* __restrict__ Zp = Z + S.loff[J] + (int64_t)c0 * m;
+  tile_mfma(As, Wc, kp, lane, w, Zp, m, c0, c0 + kp, true, 1.0);
+}
+
+// Abar for every stored entry p = (i, j) of A (original ordering):
+//   Abar_p = g w_p Z(i, j) - sum_c (lam_ic x_jc + [i != j] lam_jc x_ic),
+// w_p = 2 off the diagonal (the entry stands for a_ij and a_ji), 1 on it.
+__global__ void k_abar(const DevSym S, const double* __restrict__ Z, double g, const double* __restrict__ X,
+                       const double* __restrict__ lam, int64_t ld, int64_t nrhs, double* __restrict__ Abar) {
+  int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; q < S.nnzA; q += stride) {
+    const int i = S.e_row[q], j = S.e_col[q];
+    double s = 0.0;
+    if (Z) s = g * (i != j ? 2.0 : 1.0) * Z[S.amap[q]];
+    if (lam) {
+      for (int64_t c = 0; c < nrhs; ++c) {
+        s -= lam[i + c * ld] * X[j + c * ld];
+        if (i != j) s -= lam[j + c * ld] * X[i + c * ld];
+      }
+    }
+    Abar[q] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// iterative refinement against the fp64 matrix (original ordering).  A is
+// applied from its stored lower triangle through a full-symmetric CSR whose
+// entries index the value array (gather, no atomics).  Norm reductions keep
+// non-negative doubles as their bit patterns (monotone as unsigned).
+// stats[3c + 0] = max_i |r_i|, [3c + 1] = max_i |x_i|, [3c + 2] = max_i |b_i|.
+// ---------------------------------------------------------------------------
+
+__device__ inline void atomic_max_nonneg(unsigned long long* p, double v) {
+  atomicMax(p, (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ void k_zero_u64(unsigned long long* __restrict__ p, int64_t count) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_anorm(const int64_t* __restrict__ rp, const int64_t* __restrict__ vidx,
+                                               const double* __restrict__ vals, int64_t n,
+                                               unsigned long long* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int64_t q = rp[i]; q < rp[i + 1]; ++q) s += fabs(vals[vidx[q]]);
+  atomic_max_nonneg(out, s);
+}
+
+// R = B - A X for nrhs columns, with the normwise statistics
+__global__ __launch_bounds__(256) void k_residual(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                  const int64_t* __restrict__ vidx, const double* __restrict__ vals,
+                                                  int64_t n, const double* __restrict__ B, int64_t ldb,
+                                                  const double* __restrict__ X, int64_t ldx, int64_t nrhs,
+                                                  double* __restrict__ R, unsigned long long* __restrict__ stats) {
+  const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t c = 0; c < nrhs; ++c) {
+    const double* x = X + c * ldx;
+    double s = B[i + c * ldb];
+    for (int64_t q = rp[i]; q < rp[i + 1]; ++q) s = fma(-vals[vidx[q]], x[col[q]], s);
+    R[i + c * n] = s;
+    atomic_max_nonneg(stats + 3 * c + 0, fabs(s));
+    atomic_max_nonneg(stats + 3 * c + 1, fabs(x[i]));
+    atomic_max_nonneg(stats + 3 * c + 2, fabs(B[i + c * ldb]));
+  }
+}
+
+// X += D (n x nrhs, D with leading dimension n)
+__global__ void k_axpy(double* __restrict__ X, int64_t ldx, const double* __restrict__ D, int64_t n, int64_t nrhs) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n * nrhs; i += stride) {
+    const int64_t c = i / n, r = i % n;
+    X[c * ldx + r] += D[i];
+  }
+}
+
+// Y (leading dimension ldy) <- B (leading dimension ldb)
+__global__ void k_copy_cols(double* __restrict__ Y, int64_t ldy, const double* __restrict__ B, int64_t ldb,
+                            int64_t n, int64_t nrhs) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n * nrhs; i += stride) {
+    const int64_t c = i / n, r = i % n;
+    Y[c * ldy + r] = B[c * ldb + r];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
@@ -699,9 +1024,10 @@ hipError_t launch_factor_panel(const DevSym& S, double* L, int64_t off, int32_t 
 }
 
 hipError_t launch_update(const DevSym& S, double* L, int32_t kind, int64_t off, int32_t ntasks,
-                         hipStream_t st) {
+                         int32_t prec, hipStream_t st) {
   if (ntasks <= 0) return hipSuccess;
-  k_update<<<ntasks, 256, 0, st>>>(S, L, kind, off);
+  if (prec == 1) k_update<1><<<ntasks, 256, 0, st>>>(S, L, kind, off);
+  else k_update<0><<<ntasks, 256, 0, st>>>(S, L, kind, off);
   return hipGetLastError();
 }
 
@@ -740,6 +1066,62 @@ hipError_t launch_logdet(const DevSym& S, const double* L, double* partial, int3
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_logdet_final<<<1, 256, 0, st>>>(partial, npartial, out);
+  return hipGetLastError();
+}
+
+}  // namespace spchol
+
+namespace spchol {
+
+hipError_t launch_anorm(const DevSym& S, const double* vals, unsigned long long* out, hipStream_t st) {
+  k_zero_u64<<<1, 64, 0, st>>>(out, 1);
+  if (S.n > 0) k_anorm<<<(unsigned)((S.n + 255) / 256), 256, 0, st>>>(S.a_rp, S.a_vidx, vals, S.n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const DevSym& S, const double* vals, const double* B, int64_t ldb, const double* X,
+                           int64_t ldx, int64_t nrhs, double* R, unsigned long long* stats, hipStream_t st) {
+  k_zero_u64<<<(unsigned)((3 * nrhs + 63) / 64), 64, 0, st>>>(stats, 3 * nrhs);
+  if (S.n > 0)
+    k_residual<<<(unsigned)((S.n + 255) / 256), 256, 0, st>>>(S.a_rp, S.a_col, S.a_vidx, vals, S.n, B, ldb, X, ldx,
+                                                              nrhs, R, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(double* X, int64_t ldx, const double* D, int64_t n, int64_t nrhs, hipStream_t st) {
+  if (n * nrhs <= 0) return hipSuccess;
+  k_axpy<<<grid_for(n * nrhs), 256, 0, st>>>(X, ldx, D, n, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_cols(double* Y, int64_t ldy, const double* B, int64_t ldb, int64_t n, int64_t nrhs,
+                            hipStream_t st) {
+  if (n * nrhs <= 0) return hipSuccess;
+  k_copy_cols<<<grid_for(n * nrhs), 256, 0, st>>>(Y, ldy, B, ldb, n, nrhs);
+  return hipGetLastError();
+}
+
+}  // namespace spchol
+
+namespace spchol {
+
+hipError_t launch_si(const DevSym& S, int32_t kind, int64_t off, int32_t ntasks, const double* L, double* Z,
+                     const int64_t* yoff, double* ybuf, double* wbuf, double* tbuf, hipStream_t st) {
+  if (ntasks <= 0) return hipSuccess;
+  switch (kind) {
+    case 8: k_si_w<<<ntasks, 256, 0, st>>>(S, L, off, wbuf); break;
+    case 9: k_si_y<<<ntasks, 256, 0, st>>>(S, L, Z, off, yoff, ybuf); break;
+    case 10: k_si_zb<<<ntasks, 256, 0, st>>>(S, L, Z, off, yoff, ybuf, wbuf, tbuf); break;
+    case 11: k_si_zd<<<ntasks, 256, 0, st>>>(S, Z, off, wbuf, tbuf); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_abar(const DevSym& S, const double* Z, double g, const double* X, const double* lam, int64_t ld,
+                       int64_t nrhs, double* Abar, hipStream_t st) {
+  if (S.nnzA <= 0) return hipSuccess;
+  k_abar<<<grid_for(S.nnzA), 256, 0, st>>>(S, Z, g, X, lam, ld, nrhs, Abar);
   return hipGetLastError();
 }
 

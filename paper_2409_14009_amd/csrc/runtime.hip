@@ -49,6 +49,7 @@ struct spchol_sym_s {
   bool uploaded = false;
   int device = -1;
   DevSym dev{};
+  const int64_t* si_yoff = nullptr;
   std::vector<void*> allocs;
 
   ~spchol_sym_s() {
@@ -98,6 +99,12 @@ struct spchol_sym_s {
     HIP_TRY(up(&dev.amap, S.amap));
     HIP_TRY(up(&dev.perm, S.perm));
     HIP_TRY(up(&dev.tasks, tasks));
+    HIP_TRY(up(&dev.a_rp, S.a_rp));
+    HIP_TRY(up(&dev.a_col, S.a_col));
+    HIP_TRY(up(&dev.a_vidx, S.a_vidx));
+    HIP_TRY(up(&dev.e_row, S.e_row));
+    HIP_TRY(up(&dev.e_col, S.e_col));
+    HIP_TRY(up(&si_yoff, S.si_yoff));
     dev.n = S.n;
     dev.ns = ns;
     dev.nnzA = S.nnzA;
@@ -144,8 +151,22 @@ struct spchol_num_s {
   int64_t ycap = 0;
   double* red = nullptr;  // logdet partials + result
   double* scratch = nullptr;  // inverted diagonal blocks of the panels of one launch
+  int32_t prec = 0;           // update precision of the last factorization
+  double* rwork = nullptr;    // refinement residual / correction, n x nrhs
+  int64_t rcap = 0;
+  unsigned long long* stats = nullptr;  // refinement norms (3 per RHS + 1)
+  int64_t scap = 0;
+  double* Z = nullptr;     // selected inverse, layout of L
+  double* sibuf = nullptr; // Y blocks, inverses and T of one round
+  double* lam = nullptr;   // adjoint solve, n x nrhs
+  int64_t lcap = 0;
   Profiler prof;
   ~spchol_num_s() {
+    if (Z) (void)hipFree(Z);
+    if (sibuf) (void)hipFree(sibuf);
+    if (lam) (void)hipFree(lam);
+    if (rwork) (void)hipFree(rwork);
+    if (stats) (void)hipFree(stats);
     if (L) (void)hipFree(L);
     if (scratch) (void)hipFree(scratch);
     if (status) (void)hipFree(status);
@@ -172,6 +193,7 @@ static hipError_t timed(spchol_num_s* N, int kind, double flops, double bytes, h
 
 static spchol_status run_factor(spchol_num_s* N, const double* vals, hipStream_t st, int64_t* info) {
   const Symbolic& S = N->sym->S;
+  const int32_t prec = N->prec;
   const DevSym& D = N->sym->dev;
   HIP_TRY(timed(N, SPCHOL_KERNEL_FILL, 0.0, 8.0 * D.storage, st,
                 [&] { return launch_fill(N->L, D.storage, 0.0, st); }));
@@ -185,7 +207,7 @@ static spchol_status run_factor(spchol_num_s* N, const double* vals, hipStream_t
                     [&] { return launch_factor_panel(D, N->L, l.off, l.ntasks, N->status, N->scratch, diag, st); }));
     } else {
       HIP_TRY(timed(N, l.kind == K_UPD_INT ? SPCHOL_KERNEL_UPDATE_INT : SPCHOL_KERNEL_UPDATE_EXT, l.flops,
-                    l.bytes, st, [&] { return launch_update(D, N->L, l.kind, l.off, l.ntasks, st); }));
+                    l.bytes, st, [&] { return launch_update(D, N->L, l.kind, l.off, l.ntasks, prec, st); }));
     }
   }
   unsigned long long h = 0;
@@ -292,7 +314,14 @@ spchol_status spchol_sym_storage(spchol_sym sym, int64_t* storage_off) {
 
 spchol_status spchol_factor(spchol_sym sym, const double* vals_dev, void* stream, spchol_num* out,
                             int64_t* info) {
+  return spchol_factor_prec(sym, vals_dev, SPCHOL_UPD_F64, stream, out, info);
+}
+
+spchol_status spchol_factor_prec(spchol_sym sym, const double* vals_dev, int32_t update_precision, void* stream,
+                                 spchol_num* out, int64_t* info) {
   if (!sym || !out) return fail(SPCHOL_ERR_ARG, "null argument");
+  if (update_precision != SPCHOL_UPD_F64 && update_precision != SPCHOL_UPD_F32)
+    return fail(SPCHOL_ERR_ARG, "unsupported update precision");
   if (!vals_dev && sym->S.nnzA > 0) return fail(SPCHOL_ERR_ARG, "null values");
   *out = nullptr;
   if (info) *info = 0;
@@ -312,12 +341,22 @@ spchol_status spchol_factor(spchol_sym sym, const double* vals_dev, void* stream
     return fail(e == hipErrorOutOfMemory ? SPCHOL_ERR_OOM : SPCHOL_ERR_HIP,
                 std::string("device allocation: ") + hipGetErrorString(e));
   }
+  N->prec = update_precision;
   *out = N;
   return run_factor(N, vals_dev, (hipStream_t)stream, info);
 }
 
 spchol_status spchol_refactor(spchol_num num, const double* vals_dev, void* stream, int64_t* info) {
   if (!num) return fail(SPCHOL_ERR_ARG, "null handle");
+  return spchol_refactor_prec(num, vals_dev, num->prec, stream, info);
+}
+
+spchol_status spchol_refactor_prec(spchol_num num, const double* vals_dev, int32_t update_precision, void* stream,
+                                   int64_t* info) {
+  if (!num) return fail(SPCHOL_ERR_ARG, "null handle");
+  if (update_precision != SPCHOL_UPD_F64 && update_precision != SPCHOL_UPD_F32)
+    return fail(SPCHOL_ERR_ARG, "unsupported update precision");
+  num->prec = update_precision;
   if (!vals_dev && num->sym->S.nnzA > 0) return fail(SPCHOL_ERR_ARG, "null values");
   if (info) *info = 0;
   spchol_status s = num->sym->ensure_device();
@@ -354,6 +393,158 @@ spchol_status spchol_solve(spchol_num num, double* B_dev, int64_t nrhs, int64_t 
   for (const Launch& l : S.bwd_plan) HIP_TRY(step(l));
   HIP_TRY(timed(num, SPCHOL_KERNEL_PERM, 0.0, pbytes, st,
                 [&] { return launch_perm_scatter(D, num->y, nrhs, B_dev, ldb, st); }));
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_refine(spchol_num num, const double* vals_dev, const double* B_dev, double* X_dev,
+                            int64_t nrhs, int64_t ldb, int64_t ldx, double tol, int32_t max_iter, void* stream,
+                            double* berr_out, int32_t* iters_out) {
+  if (!num) return fail(SPCHOL_ERR_ARG, "null handle");
+  const Symbolic& S = num->sym->S;
+  if (nrhs < 0 || ldb < S.n || ldx < S.n || ldb < 1 || ldx < 1 || max_iter < 0)
+    return fail(SPCHOL_ERR_ARG, "bad nrhs, leading dimension or max_iter");
+  if (iters_out) *iters_out = 0;
+  if (nrhs == 0 || S.n == 0) {
+    for (int64_t c = 0; c < nrhs; ++c)
+      if (berr_out) berr_out[c] = 0.0;
+    return SPCHOL_OK;
+  }
+  if (!vals_dev || !B_dev || !X_dev) return fail(SPCHOL_ERR_ARG, "null device pointer");
+  hipStream_t st = (hipStream_t)stream;
+  const DevSym& D = num->sym->dev;
+  if (num->rcap < S.n * nrhs) {
+    if (num->rwork) HIP_TRY(hipFree(num->rwork));
+    num->rwork = nullptr;
+    num->rcap = 0;
+    HIP_TRY(hipMalloc((void**)&num->rwork, (size_t)(S.n * nrhs) * sizeof(double)));
+    num->rcap = S.n * nrhs;
+  }
+  if (num->scap < 3 * nrhs + 1) {
+    if (num->stats) HIP_TRY(hipFree(num->stats));
+    num->stats = nullptr;
+    num->scap = 0;
+    HIP_TRY(hipMalloc((void**)&num->stats, (size_t)(3 * nrhs + 1) * sizeof(unsigned long long)));
+    num->scap = 3 * nrhs + 1;
+  }
+  unsigned long long* anorm = num->stats + 3 * nrhs;
+  // x0 = A~^{-1} b
+  HIP_TRY(launch_copy_cols(X_dev, ldx, B_dev, ldb, S.n, nrhs, st));
+  if (ldx == S.n) {
+    spchol_status s = spchol_solve(num, X_dev, nrhs, ldx, stream);
+    if (s) return s;
+  } else {
+    HIP_TRY(launch_copy_cols(num->rwork, S.n, X_dev, ldx, S.n, nrhs, st));
+    spchol_status s = spchol_solve(num, num->rwork, nrhs, S.n, stream);
+    if (s) return s;
+    HIP_TRY(launch_copy_cols(X_dev, ldx, num->rwork, S.n, S.n, nrhs, st));
+  }
+  HIP_TRY(launch_anorm(D, vals_dev, anorm, st));
+  std::vector<unsigned long long> h(3 * nrhs + 1);
+  std::vector<double> eta(nrhs, 0.0);
+  int32_t it = 0;
+  bool ok = false;
+  for (;; ++it) {
+    HIP_TRY(launch_residual(D, vals_dev, B_dev, ldb, X_dev, ldx, nrhs, num->rwork, num->stats, st));
+    HIP_TRY(hipMemcpyAsync(h.data(), num->stats, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double an;
+    std::memcpy(&an, &h[3 * nrhs], sizeof(double));
+    ok = true;
+    for (int64_t c = 0; c < nrhs; ++c) {
+      double r, x, b;
+      std::memcpy(&r, &h[3 * c], sizeof(double));
+      std::memcpy(&x, &h[3 * c + 1], sizeof(double));
+      std::memcpy(&b, &h[3 * c + 2], sizeof(double));
+      const double den = an * x + b;
+      eta[c] = den > 0 ? r / den : (r > 0 ? INFINITY : 0.0);
+      if (!(eta[c] <= tol)) ok = false;
+    }
+    if (ok || it >= max_iter) break;
+    spchol_status s = spchol_solve(num, num->rwork, nrhs, S.n, stream);
+    if (s) return s;
+    HIP_TRY(launch_axpy(X_dev, ldx, num->rwork, S.n, nrhs, st));
+  }
+  if (berr_out)
+    for (int64_t c = 0; c < nrhs; ++c) berr_out[c] = eta[c];
+  if (iters_out) *iters_out = it;
+  if (!ok) return fail(SPCHOL_ERR_NOCONV, "iterative refinement did not reach the tolerance");
+  return SPCHOL_OK;
+}
+
+static spchol_status run_selinv(spchol_num_s* N, hipStream_t st) {
+  const Symbolic& S = N->sym->S;
+  const DevSym& D = N->sym->dev;
+  const int64_t storage = S.loff[S.ns];
+  const int64_t blk = (int64_t)kMaxPanel * kMaxPanel;
+  if (!N->Z) {
+    HIP_TRY(hipMalloc((void**)&N->Z, (size_t)(storage > 0 ? storage : 1) * sizeof(double)));
+    const int64_t ws = S.si_max_y + 2 * S.si_max_slots * blk;
+    HIP_TRY(hipMalloc((void**)&N->sibuf, (size_t)(ws > 0 ? ws : 1) * sizeof(double)));
+  }
+  double* ybuf = N->sibuf;
+  double* wbuf = ybuf + S.si_max_y;
+  double* tbuf = wbuf + S.si_max_slots * blk;
+  for (const Launch& l : S.si_plan) {
+    if (l.kind == K_SI_W) HIP_TRY(launch_fill(tbuf, (int64_t)l.ntasks * blk, 0.0, st));
+    const int64_t* yoff = N->sym->si_yoff + l.slot_base;
+    HIP_TRY(timed(N, SPCHOL_KERNEL_SELINV, 0.0, 0.0, st, [&] {
+      return launch_si(D, l.kind, l.off, l.ntasks, N->L, N->Z, yoff, ybuf, wbuf, tbuf, st);
+    }));
+  }
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_backward(spchol_num num, const double* X_dev, const double* Xbar_dev, int64_t nrhs,
+                              int64_t ld, double gbar_logdet, double* Abar_dev, double* Bbar_dev, void* stream) {
+  if (!num || !Abar_dev) return fail(SPCHOL_ERR_ARG, "null argument");
+  const Symbolic& S = num->sym->S;
+  if (nrhs < 0 || (nrhs > 0 && (ld < S.n || ld < 1))) return fail(SPCHOL_ERR_ARG, "bad nrhs or leading dimension");
+  if (nrhs > 0 && Xbar_dev && !X_dev) return fail(SPCHOL_ERR_ARG, "X is needed with Xbar");
+  hipStream_t st = (hipStream_t)stream;
+  const DevSym& D = num->sym->dev;
+  const bool use_lam = nrhs > 0 && Xbar_dev != nullptr && S.n > 0;
+  if (use_lam) {
+    if (num->lcap < S.n * nrhs) {
+      if (num->lam) HIP_TRY(hipFree(num->lam));
+      num->lam = nullptr;
+      num->lcap = 0;
+      HIP_TRY(hipMalloc((void**)&num->lam, (size_t)(S.n * nrhs) * sizeof(double)));
+      num->lcap = S.n * nrhs;
+    }
+    HIP_TRY(launch_copy_cols(num->lam, S.n, Xbar_dev, ld, S.n, nrhs, st));
+    spchol_status s = spchol_solve(num, num->lam, nrhs, S.n, stream);
+    if (s) return s;
+    if (Bbar_dev) HIP_TRY(launch_copy_cols(Bbar_dev, ld, num->lam, S.n, S.n, nrhs, st));
+  }
+  const bool use_z = gbar_logdet != 0.0 && S.n > 0;
+  if (use_z) {
+    spchol_status s = run_selinv(num, st);
+    if (s) return s;
+  }
+  // X may have a leading dimension other than n: lam uses n, X uses ld;
+  // k_abar indexes both with one leading dimension, so copy X when they differ
+  const double* Xc = X_dev;
+  if (use_lam && ld != S.n) {
+    double* tmp = nullptr;
+    HIP_TRY(hipMallocAsync((void**)&tmp, (size_t)(S.n * nrhs) * sizeof(double), st));
+    HIP_TRY(launch_copy_cols(tmp, S.n, X_dev, ld, S.n, nrhs, st));
+    HIP_TRY(launch_abar(D, use_z ? num->Z : nullptr, gbar_logdet, tmp, num->lam, S.n, nrhs, Abar_dev, st));
+    HIP_TRY(hipFreeAsync(tmp, st));
+  } else {
+    HIP_TRY(launch_abar(D, use_z ? num->Z : nullptr, gbar_logdet, Xc, use_lam ? num->lam : nullptr, S.n,
+                        use_lam ? nrhs : 0, Abar_dev, st));
+  }
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_selinv_export(spchol_num num, double* dst_dev, void* stream) {
+  if (!num || !dst_dev) return fail(SPCHOL_ERR_ARG, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  spchol_status s = run_selinv(num, st);
+  if (s) return s;
+  const int64_t storage = num->sym->S.loff[num->sym->S.ns];
+  if (storage > 0)
+    HIP_TRY(hipMemcpyAsync(dst_dev, num->Z, (size_t)storage * sizeof(double), hipMemcpyDeviceToDevice, st));
   return SPCHOL_OK;
 }
 
