@@ -42,6 +42,7 @@ extern "C" {
 
 typedef struct spchol_sym_s *spchol_sym; /* symbolic analysis (host + device copy) */
 typedef struct spchol_num_s *spchol_num; /* numeric factor (device memory)        */
+typedef struct spchol_graph_s *spchol_graph; /* captured factor (+ solve) launch sequence */
 
 typedef enum {
   SPCHOL_OK = 0,
@@ -86,6 +87,21 @@ spchol_status spchol_default_options(spchol_options *opt);
  * SPCHOL_ERR_PATTERN (pattern violates the conventions), SPCHOL_ERR_OOM. */
 spchol_status spchol_analyze(int64_t n, const int64_t *colptr, const int64_t *rowind,
                              const int64_t *perm, const spchol_options *opt, spchol_sym *out);
+
+/* Batch of independent matrices analysed as one block-diagonal matrix (a
+ * forest of elimination trees): every level launch of the factorization,
+ * the solves and the reverse mode then covers the supernodes of all the
+ * matrices at once.  Matrix b occupies columns col_off[b]..col_off[b+1]-1
+ * (in both the original and the permuted numbering) and stored entries
+ * nz_off[b].. of the concatenated value array.  Arrays as in
+ * spchol_analyze, one per matrix (host); perm may be NULL or hold NULLs. */
+spchol_status spchol_batch_analyze(int32_t count, const int64_t *n, const int64_t *const *colptr,
+                                   const int64_t *const *rowind, const int64_t *const *perm,
+                                   const spchol_options *opt, spchol_sym *out);
+
+/* Batch layout (host outputs, may be NULL): count; col_off[count+1];
+ * nz_off[count+1].  A handle from spchol_analyze reports one matrix. */
+spchol_status spchol_batch_info(spchol_sym sym, int32_t *count, int64_t *col_off, int64_t *nz_off);
 
 /* Summary of a symbolic analysis (host output). */
 typedef struct {
@@ -214,6 +230,27 @@ spchol_status spchol_selinv_export(spchol_num num, double *dst_dev, void *stream
 /* log det(A) = 2 sum_j log L_jj, reduced on the device (pairwise tree);
  * out_host receives the value.  Synchronizes `stream`. */
 spchol_status spchol_logdet(spchol_num num, double *out_host, void *stream);
+
+/* log det of every matrix of a batch (one for a single matrix), written to
+ * device memory out_dev[count]; asynchronous on `stream`. */
+spchol_status spchol_logdet_batch(spchol_num num, double *out_dev, void *stream);
+
+/* Pivot status of the last factorization enqueued into `num` (the same
+ * info as spchol_factor's); synchronizes `stream`.  Needed after a graph
+ * replay, which does not read it back. */
+spchol_status spchol_info(spchol_num num, int64_t *info, void *stream);
+
+/* Capture the whole numeric factorization of `num` (values from vals_dev)
+ * and, when nrhs > 0, the solve of B_dev in place, as one hipGraph on the
+ * (non-null) stream; spchol_graph_launch replays it as a single launch.  The
+ * pointers are fixed in the graph: update the contents of vals_dev and
+ * B_dev between replays.  The graph contains no host synchronization and no
+ * memset nodes (buffers are cleared by kernels); read the pivot status with
+ * spchol_info.  Destroy the graph before `num`. */
+spchol_status spchol_graph_create(spchol_num num, const double *vals_dev, double *B_dev, int64_t nrhs,
+                                  int64_t ldb, void *stream, spchol_graph *out);
+spchol_status spchol_graph_launch(spchol_graph graph, void *stream);
+void spchol_graph_destroy(spchol_graph graph);
 
 /* Copy the supernodal storage of L (storage doubles, layout as in
  * spchol_sym_storage) to caller-owned device memory dst_dev. */

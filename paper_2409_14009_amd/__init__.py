@@ -19,8 +19,8 @@ import numpy as np
 from . import _capi as capi
 from ._capi import LibraryMissing
 
-__all__ = ["SparseCholesky", "Factor", "SpcholError", "NotPositiveDefinite", "LibraryMissing",
-           "version", "lib", "logdet_solve"]
+__all__ = ["SparseCholesky", "BatchCholesky", "Factor", "Graph", "SpcholError", "NotPositiveDefinite",
+           "LibraryMissing", "version", "lib", "logdet_solve"]
 
 
 def lib():
@@ -131,6 +131,15 @@ class SparseCholesky:
         _check(capi.lib().spchol_sym_export(self._h, *[_hptr(out[k]) for k in keys]))
         return out
 
+    def batch_info(self):
+        """(count, col_off[count+1], nz_off[count+1]) of a batch handle."""
+        cnt = C.c_int32(0)
+        _check(capi.lib().spchol_batch_info(self._h, C.byref(cnt), None, None))
+        co = np.zeros(cnt.value + 1, np.int64)
+        no = np.zeros(cnt.value + 1, np.int64)
+        _check(capi.lib().spchol_batch_info(self._h, C.byref(cnt), _hptr(co), _hptr(no)))
+        return cnt.value, co, no
+
     def storage_offsets(self) -> np.ndarray:
         inf = self.info()
         off = np.zeros(inf["nsuper"] + 1, np.int64)
@@ -159,6 +168,54 @@ class SparseCholesky:
         _check(rc)
         F.info = 0
         return F
+
+
+class BatchCholesky(SparseCholesky):
+    """Symbolic analysis of many independent matrices as one block-diagonal
+    matrix: `mats` is a list of (n, colptr, rowind, perm) tuples.  Values
+    and right-hand sides are the concatenation of the per-matrix ones."""
+
+    def __init__(self, mats, snode_mode=0, amalg_max_zeros=0, panel_width=64):
+        L = capi.lib()
+        self._keep = []
+        cnt = len(mats)
+        ns = np.array([int(m[0]) for m in mats], np.int64)
+        cps = [np.ascontiguousarray(m[1], np.int64) for m in mats]
+        ris = [np.ascontiguousarray(m[2], np.int64) for m in mats]
+        pms = [None if m[3] is None else np.ascontiguousarray(m[3], np.int64) for m in mats]
+        self._keep = [ns, cps, ris, pms]
+        arr = lambda xs: (C.c_void_p * max(cnt, 1))(*[None if x is None else x.ctypes.data for x in xs])
+        self._pa = (arr(cps), arr(ris), arr(pms))
+        opts = capi.Options(int(snode_mode), int(amalg_max_zeros), int(panel_width), 0)
+        h = C.c_void_p()
+        _check(L.spchol_batch_analyze(cnt, _hptr(ns), C.cast(self._pa[0], C.c_void_p), C.cast(self._pa[1], C.c_void_p),
+                                      C.cast(self._pa[2], C.c_void_p), C.byref(opts), C.byref(h)))
+        self._h = h
+        self.n = int(ns.sum())
+        self.nnz_a = int(sum(int(c[-1]) for c in cps))
+        self.count = cnt
+
+
+class Graph:
+    """A captured factorization (+ solve) replayed as one launch."""
+
+    def __init__(self, factor, h):
+        self.factor = factor
+        self._h = h
+
+    def replay(self, stream=None):
+        _check(capi.lib().spchol_graph_launch(self._h, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            capi.lib().spchol_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Factor:
@@ -260,6 +317,33 @@ class Factor:
                                           _dev_f64(Bt, "Bbar"), _stream_ptr(stream)))
         Bbar = Bt.view(-1) if one else Bt.t()
         return Abar, Bbar
+
+    def logdet_batch(self, stream=None):
+        """Per-matrix log-determinants of a batch (float64 CUDA tensor)."""
+        import torch
+        cnt = self.sym.batch_info()[0]
+        out = torch.empty(cnt, dtype=torch.float64, device="cuda")
+        _check(capi.lib().spchol_logdet_batch(self._h, C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def status(self, stream=None) -> int:
+        """Pivot status of the last factorization enqueued (0 = SPD)."""
+        info = C.c_int64(0)
+        rc = capi.lib().spchol_info(self._h, C.byref(info), _stream_ptr(stream))
+        if rc not in (0, -3):
+            _check(rc)
+        return int(info.value)
+
+    def capture(self, vals, Bt=None, stream=None) -> Graph:
+        """Capture factorization (+ in-place solve of the (nrhs, n) tensor Bt)
+        as a hipGraph on `stream` (default: torch's current stream, which
+        must not be the null stream)."""
+        h = C.c_void_p()
+        nrhs = 0 if Bt is None else (Bt.shape[0] if Bt.dim() == 2 else 1)
+        bp = None if Bt is None else _dev_f64(Bt, "B")
+        _check(capi.lib().spchol_graph_create(self._h, _dev_f64(vals, "vals"), bp, nrhs, max(self.sym.n, 1),
+                                              _stream_ptr(stream), C.byref(h)))
+        return Graph(self, h)
 
     def selinv(self, stream=None):
         """Selected inverse of C = P A P^T on the supernodal pattern, in the

@@ -38,6 +38,13 @@ PROTOTYPES = {
     "spchol_default_options": (i32, [C.POINTER(Options)]),
     "spchol_analyze": (i32, [i64, vp, vp, vp, C.POINTER(Options), C.POINTER(vp)]),
     "spchol_sym_info": (i32, [vp, C.POINTER(SymInfo)]),
+    "spchol_batch_analyze": (i32, [i32, vp, vp, vp, vp, C.POINTER(Options), C.POINTER(vp)]),
+    "spchol_batch_info": (i32, [vp, C.POINTER(i32), vp, vp]),
+    "spchol_logdet_batch": (i32, [vp, vp, vp]),
+    "spchol_info": (i32, [vp, i64p, vp]),
+    "spchol_graph_create": (i32, [vp, vp, vp, i64, i64, vp, C.POINTER(vp)]),
+    "spchol_graph_launch": (i32, [vp, vp]),
+    "spchol_graph_destroy": (None, [vp]),
     "spchol_sym_export": (i32, [vp] + [vp] * 12),
     "spchol_sym_storage": (i32, [vp, vp]),
     "spchol_factor": (i32, [vp, vp, vp, C.POINTER(vp), i64p]),

@@ -64,5 +64,7 @@ hipError_t launch_solve_step(const DevSym& S, const double* L, int32_t kind, int
 hipError_t launch_logdet(const DevSym& S, const double* L, double* partial, int32_t npartial,
                          double* out, hipStream_t st);
 int32_t logdet_partials(int64_t n);
+hipError_t launch_logdet_segments(const DevSym& S, const double* L, const int64_t* off, int32_t count, double* out,
+                                  hipStream_t st);
 
 }  // namespace spchol

@@ -1126,3 +1126,30 @@ hipError_t launch_abar(const DevSym& S, const double* Z, double g, const double*
 }
 
 }  // namespace spchol
+
+namespace spchol {
+
+// per-matrix logdet of a batch: one workgroup per matrix, columns of the
+// matrix (permuted space keeps the blocks contiguous), tree reduction
+__global__ __launch_bounds__(256) void k_logdet_segments(DevSym S, const double* __restrict__ L,
+                                                         const int64_t* __restrict__ off, double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int64_t b0 = off[blockIdx.x], b1 = off[blockIdx.x + 1];
+  double v = 0.0;
+  for (int64_t j = b0 + threadIdx.x; j < b1; j += 256) {
+    const int J = S.snode_of[j];
+    const int64_t d = j - S.sfirst[J];
+    v += log(L[S.loff[J] + d * S.sm[J] + d]);
+  }
+  const double s = block_sum_256(v, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = 2.0 * s;
+}
+
+hipError_t launch_logdet_segments(const DevSym& S, const double* L, const int64_t* off, int32_t count, double* out,
+                                  hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  k_logdet_segments<<<count, 256, 0, st>>>(S, L, off, out);
+  return hipGetLastError();
+}
+
+}  // namespace spchol

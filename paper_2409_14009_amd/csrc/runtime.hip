@@ -46,6 +46,8 @@ hipError_t upload(T** dst, const std::vector<T>& v) {
 
 struct spchol_sym_s {
   Symbolic S;
+  std::vector<int64_t> batch_off, batch_nzoff;  // block boundaries of a batch (empty: one matrix)
+  const int64_t* dev_batch_off = nullptr;
   bool uploaded = false;
   int device = -1;
   DevSym dev{};
@@ -105,6 +107,11 @@ struct spchol_sym_s {
     HIP_TRY(up(&dev.e_row, S.e_row));
     HIP_TRY(up(&dev.e_col, S.e_col));
     HIP_TRY(up(&si_yoff, S.si_yoff));
+    {
+      std::vector<int64_t> bo = batch_off;
+      if (bo.empty()) bo = {0, S.n};
+      HIP_TRY(up(&dev_batch_off, bo));
+    }
     dev.n = S.n;
     dev.ns = ns;
     dev.nnzA = S.nnzA;
@@ -191,7 +198,9 @@ static hipError_t timed(spchol_num_s* N, int kind, double flops, double bytes, h
   return e;
 }
 
-static spchol_status run_factor(spchol_num_s* N, const double* vals, hipStream_t st, int64_t* info) {
+// Enqueue the whole numeric factorization on st (no host synchronization:
+// also what a graph capture records).
+static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStream_t st) {
   const Symbolic& S = N->sym->S;
   const int32_t prec = N->prec;
   const DevSym& D = N->sym->dev;
@@ -210,6 +219,11 @@ static spchol_status run_factor(spchol_num_s* N, const double* vals, hipStream_t
                     l.bytes, st, [&] { return launch_update(D, N->L, l.kind, l.off, l.ntasks, prec, st); }));
     }
   }
+  return SPCHOL_OK;
+}
+
+// Read the pivot status word (synchronizes st).
+static spchol_status read_info(spchol_num_s* N, hipStream_t st, int64_t* info) {
   unsigned long long h = 0;
   HIP_TRY(hipMemcpyAsync(&h, N->status, sizeof(h), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -217,6 +231,35 @@ static spchol_status run_factor(spchol_num_s* N, const double* vals, hipStream_t
   if (info) *info = inf;
   if (inf) return fail(SPCHOL_ERR_NOT_SPD, "matrix is not positive definite at permuted column " + std::to_string(inf));
   return SPCHOL_OK;
+}
+
+// Permute, forward and backward supernodal solves, permute back, with the
+// work vector y (n x nrhs).
+static spchol_status enqueue_solve(spchol_num_s* num, double* y, double* B_dev, int64_t nrhs, int64_t ldb,
+                                   hipStream_t st) {
+  const Symbolic& S = num->sym->S;
+  const DevSym& D = num->sym->dev;
+  const double pbytes = 24.0 * double(S.n) * double(nrhs);
+  HIP_TRY(timed(num, SPCHOL_KERNEL_PERM, 0.0, pbytes, st,
+                [&] { return launch_perm_gather(D, B_dev, ldb, nrhs, y, st); }));
+  auto step = [&](const Launch& l) {
+    // solve flops/bytes were counted for one right-hand side; L is read once
+    const double fl = l.flops * double(nrhs);
+    const double by = l.bytes;
+    return timed(num, l.kind + 2, fl, by, st,
+                 [&] { return launch_solve_step(D, num->L, l.kind, l.off, l.ntasks, y, nrhs, st); });
+  };
+  for (const Launch& l : S.fwd_plan) HIP_TRY(step(l));
+  for (const Launch& l : S.bwd_plan) HIP_TRY(step(l));
+  HIP_TRY(timed(num, SPCHOL_KERNEL_PERM, 0.0, pbytes, st,
+                [&] { return launch_perm_scatter(D, y, nrhs, B_dev, ldb, st); }));
+  return SPCHOL_OK;
+}
+
+static spchol_status run_factor(spchol_num_s* N, const double* vals, hipStream_t st, int64_t* info) {
+  spchol_status s = enqueue_factor(N, vals, st);
+  if (s) return s;
+  return read_info(N, st, info);
 }
 
 extern "C" {
@@ -250,6 +293,56 @@ spchol_status spchol_analyze(int64_t n, const int64_t* colptr, const int64_t* ro
     return fail((spchol_status)rc, err);
   }
   *out = h;
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_batch_analyze(int32_t count, const int64_t* n, const int64_t* const* colptr,
+                                   const int64_t* const* rowind, const int64_t* const* perm,
+                                   const spchol_options* opt, spchol_sym* out) {
+  if (!out) return fail(SPCHOL_ERR_ARG, "null output handle");
+  *out = nullptr;
+  if (count < 0 || (count > 0 && (!n || !colptr || !rowind))) return fail(SPCHOL_ERR_ARG, "bad batch arguments");
+  try {
+    std::vector<int64_t> off(count + 1, 0), nzoff(count + 1, 0);
+    for (int32_t b = 0; b < count; ++b) {
+      if (n[b] < 0 || !colptr[b] || (n[b] > 0 && !rowind[b]))
+        return fail(SPCHOL_ERR_ARG, "bad matrix " + std::to_string(b) + " in batch");
+      off[b + 1] = off[b] + n[b];
+      nzoff[b + 1] = nzoff[b] + colptr[b][n[b]];
+    }
+    const int64_t N = off[count];
+    std::vector<int64_t> cp(N + 1, 0), ri(nzoff[count]), pm(N);
+    for (int32_t b = 0; b < count; ++b) {
+      for (int64_t j = 0; j < n[b]; ++j) cp[off[b] + j + 1] = nzoff[b] + colptr[b][j + 1];
+      for (int64_t p = 0; p < colptr[b][n[b]]; ++p) ri[nzoff[b] + p] = off[b] + rowind[b][p];
+      for (int64_t k = 0; k < n[b]; ++k) {
+        const int64_t o = (perm && perm[b]) ? perm[b][k] : k;
+        if (o < 0 || o >= n[b]) return fail(SPCHOL_ERR_ARG, "bad permutation of matrix " + std::to_string(b));
+        pm[off[b] + k] = off[b] + o;
+      }
+    }
+    spchol_status s = spchol_analyze(N, cp.data(), ri.data(), pm.data(), opt, out);
+    if (s) return s;
+    (*out)->batch_off = off;
+    (*out)->batch_nzoff = nzoff;
+    return SPCHOL_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(SPCHOL_ERR_OOM, "out of host memory");
+  }
+}
+
+spchol_status spchol_batch_info(spchol_sym sym, int32_t* count, int64_t* col_off, int64_t* nz_off) {
+  if (!sym || !count) return fail(SPCHOL_ERR_ARG, "null argument");
+  const int32_t c = sym->batch_off.empty() ? 1 : (int32_t)sym->batch_off.size() - 1;
+  *count = c;
+  if (col_off) {
+    if (sym->batch_off.empty()) { col_off[0] = 0; col_off[1] = sym->S.n; }
+    else std::memcpy(col_off, sym->batch_off.data(), sym->batch_off.size() * sizeof(int64_t));
+  }
+  if (nz_off) {
+    if (sym->batch_nzoff.empty()) { nz_off[0] = 0; nz_off[1] = sym->S.nnzA; }
+    else std::memcpy(nz_off, sym->batch_nzoff.data(), sym->batch_nzoff.size() * sizeof(int64_t));
+  }
   return SPCHOL_OK;
 }
 
@@ -371,7 +464,6 @@ spchol_status spchol_solve(spchol_num num, double* B_dev, int64_t nrhs, int64_t 
   if (nrhs == 0 || S.n == 0) return SPCHOL_OK;
   if (!B_dev) return fail(SPCHOL_ERR_ARG, "null right-hand side");
   hipStream_t st = (hipStream_t)stream;
-  const DevSym& D = num->sym->dev;
   if (num->ycap < S.n * nrhs) {
     if (num->y) HIP_TRY(hipFree(num->y));
     num->y = nullptr;
@@ -379,21 +471,7 @@ spchol_status spchol_solve(spchol_num num, double* B_dev, int64_t nrhs, int64_t 
     HIP_TRY(hipMalloc((void**)&num->y, (size_t)(S.n * nrhs) * sizeof(double)));
     num->ycap = S.n * nrhs;
   }
-  const double pbytes = 24.0 * double(S.n) * double(nrhs);
-  HIP_TRY(timed(num, SPCHOL_KERNEL_PERM, 0.0, pbytes, st,
-                [&] { return launch_perm_gather(D, B_dev, ldb, nrhs, num->y, st); }));
-  auto step = [&](const Launch& l) {
-    // solve flops/bytes were counted for one right-hand side; L is read once
-    const double fl = l.flops * double(nrhs);
-    const double by = l.bytes;
-    return timed(num, l.kind + 2, fl, by, st,
-                 [&] { return launch_solve_step(D, num->L, l.kind, l.off, l.ntasks, num->y, nrhs, st); });
-  };
-  for (const Launch& l : S.fwd_plan) HIP_TRY(step(l));
-  for (const Launch& l : S.bwd_plan) HIP_TRY(step(l));
-  HIP_TRY(timed(num, SPCHOL_KERNEL_PERM, 0.0, pbytes, st,
-                [&] { return launch_perm_scatter(D, num->y, nrhs, B_dev, ldb, st); }));
-  return SPCHOL_OK;
+  return enqueue_solve(num, num->y, B_dev, nrhs, ldb, st);
 }
 
 spchol_status spchol_refine(spchol_num num, const double* vals_dev, const double* B_dev, double* X_dev,
@@ -559,6 +637,87 @@ spchol_status spchol_logdet(spchol_num num, double* out_host, void* stream) {
   HIP_TRY(hipStreamSynchronize(st));
   return SPCHOL_OK;
 }
+
+spchol_status spchol_logdet_batch(spchol_num num, double* out_dev, void* stream) {
+  if (!num || !out_dev) return fail(SPCHOL_ERR_ARG, "null argument");
+  const int32_t count = num->sym->batch_off.empty() ? 1 : (int32_t)num->sym->batch_off.size() - 1;
+  HIP_TRY(timed(num, SPCHOL_KERNEL_LOGDET, 0.0, 8.0 * double(num->sym->S.n), (hipStream_t)stream, [&] {
+    return launch_logdet_segments(num->sym->dev, num->L, num->sym->dev_batch_off, count, out_dev,
+                                  (hipStream_t)stream);
+  }));
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_info(spchol_num num, int64_t* info, void* stream) {
+  if (!num) return fail(SPCHOL_ERR_ARG, "null handle");
+  int64_t v = 0;
+  spchol_status s = read_info(num, (hipStream_t)stream, &v);
+  if (info) *info = v;
+  return s;
+}
+
+struct spchol_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double* y = nullptr;  // the captured solve's own work vector
+  ~spchol_graph_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (y) (void)hipFree(y);
+  }
+};
+
+spchol_status spchol_graph_create(spchol_num num, const double* vals_dev, double* B_dev, int64_t nrhs, int64_t ldb,
+                                  void* stream, spchol_graph* out) {
+  if (!num || !out) return fail(SPCHOL_ERR_ARG, "null argument");
+  *out = nullptr;
+  const Symbolic& S = num->sym->S;
+  if (nrhs < 0 || (nrhs > 0 && (!B_dev || ldb < S.n || ldb < 1))) return fail(SPCHOL_ERR_ARG, "bad right-hand side");
+  if (!vals_dev && S.nnzA > 0) return fail(SPCHOL_ERR_ARG, "null values");
+  hipStream_t st = (hipStream_t)stream;
+  if (!st) return fail(SPCHOL_ERR_ARG, "graph capture needs a non-null stream");
+  spchol_graph_s* G = new (std::nothrow) spchol_graph_s();
+  if (!G) return fail(SPCHOL_ERR_OOM, "out of host memory");
+  // buffers the captured work uses must exist before the capture; the graph
+  // owns its solve vector so that later eager solves cannot move it
+  if (nrhs > 0 && S.n > 0) {
+    hipError_t ea = hipMalloc((void**)&G->y, (size_t)(S.n * nrhs) * sizeof(double));
+    if (ea != hipSuccess) {
+      delete G;
+      return fail(SPCHOL_ERR_OOM, std::string("graph work vector: ") + hipGetErrorString(ea));
+    }
+  }
+  const bool prof = num->prof.on;
+  num->prof.on = false;
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  spchol_status s = SPCHOL_OK;
+  if (e == hipSuccess) {
+    s = enqueue_factor(num, vals_dev, st);
+    if (!s && nrhs > 0 && S.n > 0) s = enqueue_solve(num, G->y, B_dev, nrhs, ldb, st);
+    hipError_t e2 = hipStreamEndCapture(st, &G->graph);
+    if (!s && e2 != hipSuccess) e = e2;
+  }
+  num->prof.on = prof;
+  if (s) {
+    delete G;
+    return s;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    delete G;
+    return fail(SPCHOL_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  *out = G;
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_graph_launch(spchol_graph graph, void* stream) {
+  if (!graph) return fail(SPCHOL_ERR_ARG, "null graph");
+  HIP_TRY(hipGraphLaunch(graph->exec, (hipStream_t)stream));
+  return SPCHOL_OK;
+}
+
+void spchol_graph_destroy(spchol_graph graph) { delete graph; }
 
 spchol_status spchol_num_export(spchol_num num, double* dst_dev, void* stream) {
   if (!num || !dst_dev) return fail(SPCHOL_ERR_ARG, "null argument");

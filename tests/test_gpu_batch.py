@@ -1,0 +1,153 @@
+"""GPU: batched factorization of many independent matrices (one block-
+diagonal analysis), per-matrix log-determinants, hipGraph capture and
+replay, and the panel-width autotuner.
+
+Gates: per matrix, logdet relative difference to the oracle <= 1e-12 and
+normwise backward error of the solve <= 1e-12 (fp64); a graph replay equals
+the eager computation on the same values to the same bars (update
+accumulation order through atomics is not fixed, so bit equality is not
+asked), on every replay, with eager work and synchronizations between
+replays and with the values changed in place between replays.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+torch = pytest.importorskip("torch")
+sc = pytest.importorskip("paper_2409_14009_amd")
+
+
+def _batch(count, seed=None, nrhs=2, side2=(12, 48), side3=(8, 20)):
+    probs = gen.make_batch(count=count, seed=seed, nrhs=nrhs, side2=side2, side3=side3)
+    mats = [(p.n, p.colptr, p.rowind, p.perm) for p in probs]
+    vals = np.concatenate([p.vals for p in probs])
+    Bt = np.concatenate([p.B.T for p in probs], axis=1)  # (nrhs, N)
+    return probs, mats, vals, np.ascontiguousarray(Bt)
+
+
+def _check_per_matrix(probs, co, logdets, X, tol_eta=1e-12, tol_ld=1e-12):
+    worst = (0.0, 0.0)
+    for b, p in enumerate(probs):
+        o = oracle.Symbolic(p.n, p.colptr, p.rowind, p.perm, 0, 0).factor(p.vals)
+        assert o.info == 0
+        ldo = o.logdet()
+        rel = abs(logdets[b] - ldo) / max(abs(ldo), 1.0)
+        A = oracle.full_matrix(p.n, p.colptr, p.rowind, p.vals)
+        eta, _ = oracle.backward_error(A, X[:, co[b]:co[b + 1]].T, p.B)
+        worst = (max(worst[0], rel), max(worst[1], float(eta.max())))
+        assert rel <= tol_ld, (b, logdets[b], ldo)
+        assert eta.max() <= tol_eta, (b, eta)
+    return worst
+
+
+@pytest.mark.parametrize("count,nb", [(24, 64), (40, 32)])
+def test_batch_factor_solve_logdet(count, nb):
+    print(f"case batch count={count} nb={nb}", flush=True)
+    probs, mats, vals, Bt = _batch(count)
+    S = sc.BatchCholesky(mats, panel_width=nb)
+    cnt, co, no = S.batch_info()
+    F = S.factor(torch.tensor(vals, device="cuda"))
+    lds = F.logdet_batch().cpu().numpy()
+    X = F.solve(torch.tensor(Bt.T.copy(), device="cuda")).cpu().numpy().T  # (nrhs, N)
+    w = _check_per_matrix(probs, co, lds, X)
+    # the whole-batch logdet is the sum of the blocks'
+    assert abs(F.logdet() - lds.sum()) <= 1e-12 * max(1.0, abs(lds).sum())
+    print(f"  ok worst logdet {w[0]:.2e} eta {w[1]:.2e}", flush=True)
+
+
+def test_batch_single_matrix_segments():
+    """A plain (non-batch) factor has one segment: logdet_batch == logdet."""
+    p = gen.make_config(0)
+    S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm)
+    F = S.factor(torch.tensor(p.vals, device="cuda"))
+    l1 = F.logdet_batch().cpu().numpy()
+    assert l1.shape == (1,)
+    assert abs(l1[0] - F.logdet()) <= 1e-12 * abs(l1[0])
+
+
+def test_graph_replay_matches_eager():
+    print("case graph replay count=32", flush=True)
+    probs, mats, vals, Bt = _batch(32, nrhs=3)
+    S = sc.BatchCholesky(mats)
+    cnt, co, no = S.batch_info()
+    v = torch.tensor(vals, device="cuda")
+    F = S.factor(v)
+    eager_ld = F.logdet_batch().cpu().numpy()
+    B0 = torch.tensor(Bt, device="cuda")  # (nrhs, N) == column-major N x nrhs
+    Xe = B0.clone()
+    F.solve_(Xe)
+    Xe = Xe.cpu().numpy()
+
+    stream = torch.cuda.Stream()
+    Xg = torch.empty_like(B0)
+    with torch.cuda.stream(stream):
+        G = F.capture(v, Xg, stream=stream)
+    scale = [1.0, 2.0, 1.0, 0.5]
+    for r, s in enumerate(scale):
+        # eager work between replays: change values in place, touch other memory
+        with torch.cuda.stream(stream):
+            v.copy_(torch.tensor(vals * s, device="cuda"))
+            Xg.copy_(B0)
+            junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64).sum()
+            G.replay(stream)
+            lds = F.logdet_batch(stream=stream)
+            assert F.status(stream) == 0
+        stream.synchronize()
+        lds = lds.cpu().numpy()
+        Xr = Xg.cpu().numpy()
+        # logdet(sA) = logdet(A) + n log s; x(sA) = x(A)/s
+        ns = np.diff(co)
+        exp_ld = eager_ld + ns * math.log(s)
+        assert np.all(np.abs(lds - exp_ld) <= 1e-12 * np.maximum(np.abs(exp_ld), 1.0)), (r, lds - exp_ld)
+        ex = np.abs(Xr * s - Xe).max() / np.abs(Xe).max()
+        assert ex <= 1e-12, (r, ex)
+        torch.cuda.synchronize()
+        del junk
+    # the graph's result at scale 1 also passes the oracle gates
+    with torch.cuda.stream(stream):
+        v.copy_(torch.tensor(vals, device="cuda"))
+        Xg.copy_(B0)
+        G.replay(stream)
+    stream.synchronize()
+    _check_per_matrix(probs, co, F.logdet_batch().cpu().numpy(), Xg.cpu().numpy())
+    G.close()
+
+
+def test_graph_detects_not_spd():
+    p = gen.make_config(0)
+    S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm)
+    v = torch.tensor(p.vals, device="cuda")
+    F = S.factor(v)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        G = F.capture(v, stream=stream)
+        v.neg_()
+        G.replay(stream)
+        st = F.status(stream)
+        assert st >= 1
+        v.neg_()
+        G.replay(stream)
+        assert F.status(stream) == 0
+    G.close()
+
+
+def test_autotune_batch(tmp_path, monkeypatch):
+    from paper_2409_14009_amd import autotune
+    monkeypatch.setenv("SPCHOL_TUNE_CACHE", str(tmp_path / "tune.json"))
+    autotune._mem_cache.clear()
+    probs, mats, vals, Bt = _batch(16, nrhs=1)
+    v = torch.tensor(vals, device="cuda")
+    best, times = autotune.tune_batch(mats, v, reps=2)
+    assert best in autotune.CANDIDATES
+    assert all(math.isfinite(t) and t > 0 for t in times.values())
+    # cached: a second call returns the same choice without timing
+    best2, _ = autotune.tune_batch(mats, v, reps=2)
+    assert best2 == best
+    assert (tmp_path / "tune.json").exists()
