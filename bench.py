@@ -1,17 +1,26 @@
-"""Benchmark: numeric factorization (+ solve + logdet) of the 64^3 workload.
+"""Benchmark of the supernodal Cholesky hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1]
-                    [--no-cpu-baseline]
+                    [--no-cpu-baseline] [--no-extras] [--copy-probe MiB]
 
-One step = the whole hot path on inputs already resident in device memory:
-value scatter, leaves-to-root supernodal factorization (panel Cholesky,
-triangular solve, update + relative-index scatter), the forward and backward
-supernodal solves of the right-hand side, and logdet.  The symbolic analysis
-(host) runs once before timing.  Prints one JSON line.
+Headline (one step = the whole hot path on inputs already resident in device
+memory, 3D 7-point 64^3 workload): value scatter, leaves-to-root supernodal
+factorization (panel Cholesky, triangular solve, update + relative-index
+scatter), the forward and backward supernodal solves and logdet.  The
+symbolic analysis (host) runs once before timing.
 
 value = algorithmic factorization flops (sum_j c_j^2 over the true column
-counts) / mean factorization time measured with HIP events on the stream the
-kernels run on.
+counts) / mean factorization time, HIP events on the stream the kernels run
+on.  The same JSON line carries, measured in the same run:
+  mixed_ir  - 3D 27-point 3-dof 40^3, 8 RHS: fp64 factor+solve against
+              fp32-update factor + solve + iterative refinement to a
+              normwise backward error <= 1e-12 (per-RHS errors reported);
+  fwd_bwd   - 3D 48^3 random-field workload: forward (factor + solve +
+              logdet) and reverse (selected inversion + gradient) times;
+  batch     - 512 independent grids, factor + 4-RHS solve as one hipGraph.
+
+--copy-probe runs a plain device copy of the given size (the calibration
+run for the hardware byte counters) and nothing else.
 """
 from __future__ import annotations
 
@@ -29,6 +38,10 @@ sys.path.insert(0, ROOT)
 METRIC = "factor GFLOP/s, FP64 vs mixed+IR at backward err <=1e-12; fwd+bwd time"
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(p, z, ncols=32768):
@@ -50,27 +63,29 @@ def cpu_baseline(p, z, ncols=32768):
                        f"{dt:.1f} s on 1 thread")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=1)
-    ap.add_argument("--side", type=int, default=None)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the sharded design is described in DESIGN.md", file=sys.stderr)
-        sys.exit(2)
+def _timed_steps(steps, stream, phases):
+    """Run `steps` iterations of the callables in `phases` (list of
+    (name, fn)); an event is recorded on `stream` before and after each
+    phase.  Returns {name: mean ms}."""
+    import torch
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(phases) + 1)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    for k in range(steps):
+        evs[k][0].record(stream)
+        for i, (_, fn) in enumerate(phases):
+            fn()
+            evs[k][i + 1].record(stream)
+    torch.cuda.synchronize()
+    return {name: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
+            for i, (name, _) in enumerate(phases)}
 
+
+def headline(args, dev):
     import torch
     import gen
     import paper_2409_14009_amd as sc
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    print(f"bench: config {args.config} setup", file=sys.stderr, flush=True)
+    log(f"config {args.config} setup")
     p = gen.make_config(args.config, side=args.side)
     z = p.meta["amalg_z"]
     S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, p.meta["snode_mode"], z)
@@ -87,11 +102,12 @@ def main():
         F.solve_(Xt)
         F.logdet()
     torch.cuda.synchronize()
-    print(f"bench: warmup done, timing {args.steps} steps", file=sys.stderr, flush=True)
+    log(f"warmup done, timing {args.steps} steps")
 
     F.profile(True)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    logdet = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -111,12 +127,7 @@ def main():
     solve_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     gflops = info["flops_alg"] / (factor_ms * 1e-3) / 1e9
-
-    # correctness of the timed result: normwise backward error of the solve
-    import oracle
-    A = oracle.full_matrix(p.n, p.colptr, p.rowind, p.vals)
-    X = Xt.cpu().numpy().T
-    eta, _ = oracle.backward_error(A, X, p.B)
+    eta = F.berr_(vals, Bt, Xt)
 
     # dominant kernel of the factorization by summed event time
     fk = ["fill", "scatter_a", "factor", "update_int", "update_ext"]
@@ -133,44 +144,231 @@ def main():
     roof.update(kernel=dom, launches_per_step=d["launches"] / args.steps,
                 avg_launch_us=d["ms"] * 1e3 / max(d["launches"], 1),
                 flops_per_step=d["flops"] / args.steps, bytes_per_step=d["bytes"] / args.steps)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        print("bench: cpu baseline (oracle sample)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(p, z)
-
     kernels = {k: dict(launches=v["launches"] / args.steps, ms=v["ms"] / args.steps,
                        gflops=(v["flops"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 and v["flops"] else None,
                        gbs=(v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 and v["bytes"] else None)
                for k, v in prof.items() if v["launches"]}
+    cfg = {
+        "workload": p.meta["doc"],
+        "n": p.n, "nnz_l": info["nnz_l"], "storage": info["storage"], "nsuper": info["nsuper"],
+        "levels": info["nlevels"], "flops_alg": info["flops_alg"], "flops_exec": info["flops_exec"],
+        "amalg_max_zeros": z, "nrhs": int(p.B.shape[1]), "seed": p.meta["seed"],
+        "parallelism": "single GPU",
+    }
+    res = dict(value=gflops, ms_per_step=ms_per_step, factor_ms=factor_ms, solve_logdet_ms=solve_ms,
+               backward_error=max(eta), logdet=logdet, roofline=roof, kernels=kernels, config=cfg)
+    del F
+    return res, p, z
+
+
+def mixed_ir(args, dev):
+    """fp64 factor + solve vs fp32-update factor + solve + refinement."""
+    import torch
+    import gen
+    import paper_2409_14009_amd as sc
+
+    log("mixed precision setup (3D 27-point 3-dof 40^3, 8 RHS)")
+    p = gen.make_config(2)
+    S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, p.meta["snode_mode"], p.meta["amalg_z"])
+    info = S.info()
+    vals = torch.tensor(p.vals, device=dev)
+    Bt = torch.tensor(np.ascontiguousarray(p.B.T), device=dev)
+    Xt = torch.empty_like(Bt)
+    stream = torch.cuda.current_stream()
+    steps = max(2, args.steps // 2)
+
+    F = S.factor(vals)
+    for _ in range(args.warmup):
+        F.refactor(vals)
+        Xt.copy_(Bt)
+        F.solve_(Xt)
+    t64 = _timed_steps(steps, stream, [("factor", lambda: F.refactor(vals)),
+                                       ("solve", lambda: (Xt.copy_(Bt), F.solve_(Xt)))])
+    eta64 = F.berr_(vals, Bt, Xt)
+    del F
+    out = dict(workload=p.meta["doc"], n=p.n, nrhs=int(p.B.shape[1]), flops_alg=info["flops_alg"],
+               fp64=dict(factor_ms=t64["factor"], factor_solve_ms=t64["factor"] + t64["solve"],
+                         gflops=info["flops_alg"] / t64["factor"] * 1e-6, berr=eta64))
+    for prec in ("f32",):
+        Fm = S.factor(vals, precision=prec)
+        it_box = {}
+
+        def refine():
+            berr, it = Fm.refine_(vals, Bt, Xt, tol=1e-12, max_iter=10)
+            it_box["berr"], it_box["it"] = berr, it
+
+        for _ in range(args.warmup):
+            Fm.refactor(vals, precision=prec)
+            refine()
+        tm = _timed_steps(steps, stream, [("factor", lambda: Fm.refactor(vals, precision=prec)),
+                                          ("solve_ir", refine)])
+        total = tm["factor"] + tm["solve_ir"]
+        out[prec + "_ir"] = dict(factor_ms=tm["factor"], solve_ir_ms=tm["solve_ir"], total_ms=total,
+                                 gflops=info["flops_alg"] / tm["factor"] * 1e-6, iterations=it_box["it"],
+                                 berr=it_box["berr"], speedup_vs_fp64=out["fp64"]["factor_solve_ms"] / total)
+        del Fm
+    return out
+
+
+def fwd_bwd(args, dev):
+    """Forward (factor + solve + logdet) and reverse (gradients of logdet
+    and of x = A^-1 b w.r.t. A's values and b) on the 48^3 workload."""
+    import torch
+    import gen
+    import paper_2409_14009_amd as sc
+
+    log("reverse mode setup (3D 48^3 random field)")
+    p = gen.make_config(4)
+    S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, p.meta["snode_mode"], p.meta["amalg_z"])
+    info = S.info()
+    vals = torch.tensor(p.vals, device=dev)
+    Bt = torch.tensor(np.ascontiguousarray(p.B.T), device=dev)
+    Xt = torch.empty_like(Bt)
+    rng = np.random.default_rng(p.meta["seed"] + 1)
+    Xbar = torch.tensor(rng.standard_normal(p.n), device=dev)
+    stream = torch.cuda.current_stream()
+    steps = max(2, args.steps // 2)
+    F = S.factor(vals)
+    box = {}
+
+    def fwd():
+        F.refactor(vals)
+        Xt.copy_(Bt)
+        F.solve_(Xt)
+        box["ld"] = F.logdet()
+
+    def bwd():
+        box["g"] = F.backward(Xt.view(-1), Xbar, 1.0)
+
+    for _ in range(args.warmup):
+        fwd()
+        bwd()
+    t = _timed_steps(steps, stream, [("fwd", fwd), ("bwd", bwd)])
+    Abar, Bbar = box["g"]
+    ok = bool(torch.isfinite(Abar).all().item() and torch.isfinite(Bbar).all().item())
+    return dict(workload=p.meta["doc"], n=p.n, flops_alg=info["flops_alg"], fwd_ms=t["fwd"], bwd_ms=t["bwd"],
+                fwd_bwd_ms=t["fwd"] + t["bwd"], grads_finite=ok, logdet=box["ld"])
+
+
+def batch(args, dev):
+    """512 independent grids: factor + 4-RHS solve captured in one hipGraph."""
+    import torch
+    import gen
+    import scipy.sparse as sp
+    import paper_2409_14009_amd as sc
+
+    log("batch setup (512 grids)")
+    probs = gen.make_batch()
+    z = probs[0].meta["amalg_z"]
+    mats = [(q.n, q.colptr, q.rowind, q.perm) for q in probs]
+    S = sc.BatchCholesky(mats, amalg_max_zeros=z)
+    info = S.info()
+    cnt, co, _ = S.batch_info()
+    vals = torch.tensor(np.concatenate([q.vals for q in probs]), device=dev)
+    B0 = torch.tensor(np.ascontiguousarray(np.concatenate([q.B.T for q in probs], axis=1)), device=dev)
+    X = torch.empty_like(B0)
+    F = S.factor(vals)
+    gs = torch.cuda.Stream()
+    with torch.cuda.stream(gs):
+        G = F.capture(vals, X, stream=gs)
+        for _ in range(args.warmup + 1):
+            X.copy_(B0)
+            G.replay(gs)
+        steps = max(5, args.steps)
+        t = _timed_steps(steps, gs, [("reset", lambda: X.copy_(B0)), ("graph", lambda: G.replay(gs))])
+        status = F.status(gs)
+    gs.synchronize()
+    # per-matrix normwise backward error (fp64, host)
+    Xh = X.cpu().numpy()
+    worst = 0.0
+    for b, q in enumerate(probs):
+        A = sp.csc_matrix((q.vals, q.rowind, q.colptr), shape=(q.n, q.n))
+        A = A + sp.tril(A, -1).T
+        x = Xh[:, co[b]:co[b + 1]].T
+        r = q.B - A @ x
+        an = abs(A).sum(axis=1).max()
+        eta = np.abs(r).max(axis=0) / (an * np.abs(x).max(axis=0) + np.abs(q.B).max(axis=0))
+        worst = max(worst, float(eta.max()))
+    G.close()
+    return dict(workload=gen.CONFIG_DOC[3], matrices=cnt, n_total=int(info["n"]), nsuper=info["nsuper"],
+                levels=info["nlevels"], flops_alg=info["flops_alg"], graph_ms=t["graph"],
+                gflops=info["flops_alg"] / t["graph"] * 1e-6, matrices_per_s=cnt / (t["graph"] * 1e-3),
+                status=status, worst_berr=worst, amalg_max_zeros=z)
+
+
+def copy_probe(mib):
+    """A plain device copy of `mib` MiB, three times: the reference for the
+    hardware byte counters (read + write of the buffer per dispatch)."""
+    import torch
+    n = (mib << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--side", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding is a design, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+
+    res, p, z = headline(args, dev)
+    extras = {}
+    if not args.no_extras:
+        extras["mixed_ir"] = mixed_ir(args, dev)
+        torch.cuda.empty_cache()
+        extras["fwd_bwd"] = fwd_bwd(args, dev)
+        torch.cuda.empty_cache()
+        extras["batch"] = batch(args, dev)
+        torch.cuda.empty_cache()
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        cpu = cpu_baseline(p, z)
+
     out = {
         "metric": METRIC,
-        "value": gflops,
+        "value": res["value"],
         "unit": "GFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {
-            "workload": p.meta["doc"],
-            "n": p.n, "nnz_l": info["nnz_l"], "storage": info["storage"], "nsuper": info["nsuper"],
-            "levels": info["nlevels"], "flops_alg": info["flops_alg"], "flops_exec": info["flops_exec"],
-            "amalg_max_zeros": z, "nrhs": int(p.B.shape[1]), "seed": p.meta["seed"],
-            "parallelism": "single GPU",
-        },
-        "factor_ms": factor_ms,
-        "solve_logdet_ms": solve_ms,
-        "backward_error": float(eta.max()),
-        "logdet": logdet,
-        "roofline": roof,
+        "config": res["config"],
+        "factor_ms": res["factor_ms"],
+        "solve_logdet_ms": res["solve_logdet_ms"],
+        "backward_error": res["backward_error"],
+        "logdet": res["logdet"],
+        "roofline": res["roofline"],
         "cpu_baseline": cpu,
-        "kernels": kernels,
+        "kernels": res["kernels"],
     }
+    out.update(extras)
     print(json.dumps(out), flush=True)
 
 

@@ -323,11 +323,11 @@ CONFIG_DOC = {
     0: "2D 5-point Laplacian 32x32, w~U[0.5,1.5], shift 1e-2, ND, fundamental supernodes, 1 RHS",
     1: "3D 7-point Laplacian 64^3, w=10^U(-2,2), shift 1e-6, ND, amalgamation z=8, 1 RHS",
     2: "3D 27-point, 3 dofs, 40^3, rotated SPD 3x3 blocks (eig U[1,10]), delta 1e-2, ND, z=8, 8 RHS",
-    3: "batch of 512 2D/3D grid Laplacians (2D side U{12..48}, 3D side U{8..20}), as cfg 0, 4 RHS",
+    3: "batch of 512 2D/3D grid Laplacians (2D side U{12..48}, 3D side U{8..20}), weights as cfg 0, z=8, 4 RHS",
     4: "3D 7-point Laplacian 48^3, GRF log-conductivity (ell=4, std=1), shift 1e-2, ND, z=8, 1 RHS",
 }
 
-DEFAULT_AMALG = {0: 0, 1: 8, 2: 8, 3: 0, 4: 8}
+DEFAULT_AMALG = {0: 0, 1: 8, 2: 8, 3: 8, 4: 8}
 DEFAULT_SNODE_MODE = {0: 0, 1: 0, 2: 0, 3: 0, 4: 0}
 
 
@@ -390,6 +390,6 @@ def make_batch(count: int = 512, seed: int | None = None, nrhs: int = 4,
         B = rng.standard_normal((nrhs, n)).T.copy(order="F")
         perm = nested_dissection(shape)
         out.append(Problem(n, cp, ri, vv, perm, B,
-                           dict(config=3, index=t, shape=shape, seed=seed, amalg_z=0,
+                           dict(config=3, index=t, shape=shape, seed=seed, amalg_z=DEFAULT_AMALG[3],
                                 snode_mode=0)))
     return out

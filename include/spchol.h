@@ -222,6 +222,14 @@ spchol_status spchol_backward(spchol_num num, const double *X_dev, const double 
                               int64_t nrhs, int64_t ld, double gbar_logdet, double *Abar_dev,
                               double *Bbar_dev, void *stream);
 
+/* Normwise backward error of given solutions (Rigal-Gaches, infinity norm):
+ * berr_out[c] = ||b_c - A x_c|| / (||A|| ||x_c|| + ||b_c||), the residual in
+ * fp64 with the original A (values vals_dev in the pattern's entry order).
+ * B_dev, X_dev: n x nrhs column-major device blocks (leading dimensions ldb,
+ * ldx >= n); berr_out: host array of nrhs.  Synchronizes `stream`. */
+spchol_status spchol_berr(spchol_num num, const double *vals_dev, const double *B_dev, const double *X_dev,
+                          int64_t nrhs, int64_t ldb, int64_t ldx, void *stream, double *berr_out);
+
 /* Selected inverse Z = C^{-1} (C = P A P^T) on the supernodal pattern,
  * written to caller-owned device memory in the layout of the factor
  * (spchol_sym_storage); upper triangles of the diagonal blocks unspecified. */

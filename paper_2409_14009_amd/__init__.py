@@ -285,6 +285,15 @@ class Factor:
         _check(rc)
         return out
 
+    def berr_(self, vals, Bt, Xt, stream=None):
+        """Normwise backward error per right-hand side of the (nrhs, n)
+        contiguous solution block Xt for the block Bt (fp64, original A)."""
+        nrhs = Bt.shape[0] if Bt.dim() == 2 else 1
+        out = (C.c_double * max(nrhs, 1))()
+        _check(capi.lib().spchol_berr(self._h, _dev_f64(vals, "vals"), _dev_f64(Bt, "B"), _dev_f64(Xt, "X"), nrhs,
+                                      self.sym.n, self.sym.n, _stream_ptr(stream), out))
+        return [out[c] for c in range(nrhs)]
+
     def refine(self, vals, B, tol=1e-12, max_iter=10, stream=None, check=True):
         """X = A^{-1} B by iterative refinement with this factor; B of shape
         (n,) or (n, nrhs).  Returns (X, berr list, iterations)."""

@@ -256,6 +256,48 @@ static spchol_status enqueue_solve(spchol_num_s* num, double* y, double* B_dev, 
   return SPCHOL_OK;
 }
 
+// Residual and statistics buffers of the refinement (n x nrhs, 3 nrhs + 1).
+static spchol_status ensure_refine_work(spchol_num_s* num, int64_t nrhs) {
+  const int64_t n = num->sym->S.n;
+  if (num->rcap < n * nrhs) {
+    if (num->rwork) HIP_TRY(hipFree(num->rwork));
+    num->rwork = nullptr;
+    num->rcap = 0;
+    HIP_TRY(hipMalloc((void**)&num->rwork, (size_t)(n * nrhs) * sizeof(double)));
+    num->rcap = n * nrhs;
+  }
+  if (num->scap < 3 * nrhs + 1) {
+    if (num->stats) HIP_TRY(hipFree(num->stats));
+    num->stats = nullptr;
+    num->scap = 0;
+    HIP_TRY(hipMalloc((void**)&num->stats, (size_t)(3 * nrhs + 1) * sizeof(unsigned long long)));
+    num->scap = 3 * nrhs + 1;
+  }
+  return SPCHOL_OK;
+}
+
+// rwork <- B - A X (fp64, original A) and the normwise backward error per
+// column, eta = ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf); expects
+// stats[3 nrhs] to hold ||A||_inf.  Synchronizes st.
+static spchol_status residual_eta(spchol_num_s* num, const double* vals, const double* B, int64_t ldb,
+                                  const double* X, int64_t ldx, int64_t nrhs, hipStream_t st, double* eta) {
+  std::vector<unsigned long long> h(3 * nrhs + 1);
+  HIP_TRY(launch_residual(num->sym->dev, vals, B, ldb, X, ldx, nrhs, num->rwork, num->stats, st));
+  HIP_TRY(hipMemcpyAsync(h.data(), num->stats, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double an;
+  std::memcpy(&an, &h[3 * nrhs], sizeof(double));
+  for (int64_t c = 0; c < nrhs; ++c) {
+    double r, x, b;
+    std::memcpy(&r, &h[3 * c], sizeof(double));
+    std::memcpy(&x, &h[3 * c + 1], sizeof(double));
+    std::memcpy(&b, &h[3 * c + 2], sizeof(double));
+    const double den = an * x + b;
+    eta[c] = den > 0 ? r / den : (r > 0 ? INFINITY : 0.0);
+  }
+  return SPCHOL_OK;
+}
+
 static spchol_status run_factor(spchol_num_s* N, const double* vals, hipStream_t st, int64_t* info) {
   spchol_status s = enqueue_factor(N, vals, st);
   if (s) return s;
@@ -490,19 +532,9 @@ spchol_status spchol_refine(spchol_num num, const double* vals_dev, const double
   if (!vals_dev || !B_dev || !X_dev) return fail(SPCHOL_ERR_ARG, "null device pointer");
   hipStream_t st = (hipStream_t)stream;
   const DevSym& D = num->sym->dev;
-  if (num->rcap < S.n * nrhs) {
-    if (num->rwork) HIP_TRY(hipFree(num->rwork));
-    num->rwork = nullptr;
-    num->rcap = 0;
-    HIP_TRY(hipMalloc((void**)&num->rwork, (size_t)(S.n * nrhs) * sizeof(double)));
-    num->rcap = S.n * nrhs;
-  }
-  if (num->scap < 3 * nrhs + 1) {
-    if (num->stats) HIP_TRY(hipFree(num->stats));
-    num->stats = nullptr;
-    num->scap = 0;
-    HIP_TRY(hipMalloc((void**)&num->stats, (size_t)(3 * nrhs + 1) * sizeof(unsigned long long)));
-    num->scap = 3 * nrhs + 1;
+  {
+    spchol_status s = ensure_refine_work(num, nrhs);
+    if (s) return s;
   }
   unsigned long long* anorm = num->stats + 3 * nrhs;
   // x0 = A~^{-1} b
@@ -517,26 +549,17 @@ spchol_status spchol_refine(spchol_num num, const double* vals_dev, const double
     HIP_TRY(launch_copy_cols(X_dev, ldx, num->rwork, S.n, S.n, nrhs, st));
   }
   HIP_TRY(launch_anorm(D, vals_dev, anorm, st));
-  std::vector<unsigned long long> h(3 * nrhs + 1);
   std::vector<double> eta(nrhs, 0.0);
   int32_t it = 0;
   bool ok = false;
   for (;; ++it) {
-    HIP_TRY(launch_residual(D, vals_dev, B_dev, ldb, X_dev, ldx, nrhs, num->rwork, num->stats, st));
-    HIP_TRY(hipMemcpyAsync(h.data(), num->stats, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    double an;
-    std::memcpy(&an, &h[3 * nrhs], sizeof(double));
-    ok = true;
-    for (int64_t c = 0; c < nrhs; ++c) {
-      double r, x, b;
-      std::memcpy(&r, &h[3 * c], sizeof(double));
-      std::memcpy(&x, &h[3 * c + 1], sizeof(double));
-      std::memcpy(&b, &h[3 * c + 2], sizeof(double));
-      const double den = an * x + b;
-      eta[c] = den > 0 ? r / den : (r > 0 ? INFINITY : 0.0);
-      if (!(eta[c] <= tol)) ok = false;
+    {
+      spchol_status s = residual_eta(num, vals_dev, B_dev, ldb, X_dev, ldx, nrhs, st, eta.data());
+      if (s) return s;
     }
+    ok = true;
+    for (int64_t c = 0; c < nrhs; ++c)
+      if (!(eta[c] <= tol)) ok = false;
     if (ok || it >= max_iter) break;
     spchol_status s = spchol_solve(num, num->rwork, nrhs, S.n, stream);
     if (s) return s;
@@ -547,6 +570,23 @@ spchol_status spchol_refine(spchol_num num, const double* vals_dev, const double
   if (iters_out) *iters_out = it;
   if (!ok) return fail(SPCHOL_ERR_NOCONV, "iterative refinement did not reach the tolerance");
   return SPCHOL_OK;
+}
+
+spchol_status spchol_berr(spchol_num num, const double* vals_dev, const double* B_dev, const double* X_dev,
+                          int64_t nrhs, int64_t ldb, int64_t ldx, void* stream, double* berr_out) {
+  if (!num || !berr_out) return fail(SPCHOL_ERR_ARG, "null argument");
+  const Symbolic& S = num->sym->S;
+  if (nrhs < 0 || ldb < S.n || ldx < S.n || ldb < 1 || ldx < 1) return fail(SPCHOL_ERR_ARG, "bad nrhs or leading dimension");
+  if (nrhs == 0 || S.n == 0) {
+    for (int64_t c = 0; c < nrhs; ++c) berr_out[c] = 0.0;
+    return SPCHOL_OK;
+  }
+  if (!vals_dev || !B_dev || !X_dev) return fail(SPCHOL_ERR_ARG, "null device pointer");
+  hipStream_t st = (hipStream_t)stream;
+  spchol_status s = ensure_refine_work(num, nrhs);
+  if (s) return s;
+  HIP_TRY(launch_anorm(num->sym->dev, vals_dev, num->stats + 3 * nrhs, st));
+  return residual_eta(num, vals_dev, B_dev, ldb, X_dev, ldx, nrhs, st, berr_out);
 }
 
 static spchol_status run_selinv(spchol_num_s* N, hipStream_t st) {

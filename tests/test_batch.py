@@ -9,10 +9,11 @@ import oracle
 sc = pytest.importorskip("paper_2409_14009_amd")
 
 
-def test_batch_structure_matches_each_matrix():
+@pytest.mark.parametrize("z", [0, 8])
+def test_batch_structure_matches_each_matrix(z):
     probs = gen.make_batch(count=12, nrhs=2)
     mats = [(p.n, p.colptr, p.rowind, p.perm) for p in probs]
-    B = sc.BatchCholesky(mats)
+    B = sc.BatchCholesky(mats, amalg_max_zeros=z)
     cnt, co, no = B.batch_info()
     assert cnt == 12
     assert np.array_equal(np.diff(co), [p.n for p in probs])
@@ -22,7 +23,7 @@ def test_batch_structure_matches_each_matrix():
     tot_flops = 0.0
     sp_ = e["super_ptr"]
     for b, p in enumerate(probs):
-        o = oracle.Symbolic(p.n, p.colptr, p.rowind, p.perm, 0, 0)
+        o = oracle.Symbolic(p.n, p.colptr, p.rowind, p.perm, 0, z)
         tot_flops += o.flops()
         # supernodes of block b
         sel = (sp_[:-1] >= co[b]) & (sp_[:-1] < co[b + 1])
@@ -37,7 +38,7 @@ def test_batch_structure_matches_each_matrix():
         par = e["parent"][co[b]:co[b + 1]]
         assert np.all((par == -1) | ((par >= co[b]) & (par < co[b + 1])))
     assert inf["flops_alg"] == tot_flops
-    assert inf["nsuper"] == sum(oracle.Symbolic(p.n, p.colptr, p.rowind, p.perm, 0, 0).nsuper for p in probs)
+    assert inf["nsuper"] == sum(oracle.Symbolic(p.n, p.colptr, p.rowind, p.perm, 0, z).nsuper for p in probs)
 
 
 def test_batch_arguments():

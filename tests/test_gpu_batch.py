@@ -35,6 +35,7 @@ def _batch(count, seed=None, nrhs=2, side2=(12, 48), side3=(8, 20)):
 def _check_per_matrix(probs, co, logdets, X, tol_eta=1e-12, tol_ld=1e-12):
     worst = (0.0, 0.0)
     for b, p in enumerate(probs):
+        # the factor is unique: the oracle's supernode partition does not matter
         o = oracle.Symbolic(p.n, p.colptr, p.rowind, p.perm, 0, 0).factor(p.vals)
         assert o.info == 0
         ldo = o.logdet()
@@ -47,11 +48,11 @@ def _check_per_matrix(probs, co, logdets, X, tol_eta=1e-12, tol_ld=1e-12):
     return worst
 
 
-@pytest.mark.parametrize("count,nb", [(24, 64), (40, 32)])
-def test_batch_factor_solve_logdet(count, nb):
-    print(f"case batch count={count} nb={nb}", flush=True)
+@pytest.mark.parametrize("count,nb,z", [(24, 64, 0), (40, 32, 8), (64, 64, 8)])
+def test_batch_factor_solve_logdet(count, nb, z):
+    print(f"case batch count={count} nb={nb} z={z}", flush=True)
     probs, mats, vals, Bt = _batch(count)
-    S = sc.BatchCholesky(mats, panel_width=nb)
+    S = sc.BatchCholesky(mats, amalg_max_zeros=z, panel_width=nb)
     cnt, co, no = S.batch_info()
     F = S.factor(torch.tensor(vals, device="cuda"))
     lds = F.logdet_batch().cpu().numpy()
@@ -75,7 +76,7 @@ def test_batch_single_matrix_segments():
 def test_graph_replay_matches_eager():
     print("case graph replay count=32", flush=True)
     probs, mats, vals, Bt = _batch(32, nrhs=3)
-    S = sc.BatchCholesky(mats)
+    S = sc.BatchCholesky(mats, amalg_max_zeros=8)
     cnt, co, no = S.batch_info()
     v = torch.tensor(vals, device="cuda")
     F = S.factor(v)
