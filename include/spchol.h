@@ -272,14 +272,12 @@ enum {
   SPCHOL_KERNEL_FACTOR = 2,      /* panel Cholesky + triangular solve        */
   SPCHOL_KERNEL_UPDATE_INT = 3,  /* update of a supernode's own columns      */
   SPCHOL_KERNEL_UPDATE_EXT = 4,  /* update scattered into ancestors          */
-  SPCHOL_KERNEL_FWD_TRI = 5,
-  SPCHOL_KERNEL_FWD_GEMV = 6,
-  SPCHOL_KERNEL_BWD_GEMVT = 7,
-  SPCHOL_KERNEL_BWD_TRI = 8,
-  SPCHOL_KERNEL_PERM = 9,        /* solve permutation gather/scatter         */
-  SPCHOL_KERNEL_LOGDET = 10,
-  SPCHOL_KERNEL_SELINV = 11,     /* selected inversion (reverse mode)       */
-  SPCHOL_KERNEL_KINDS = 12
+  SPCHOL_KERNEL_FWD = 5,         /* forward solve rounds                     */
+  SPCHOL_KERNEL_BWD = 6,         /* backward solve rounds                    */
+  SPCHOL_KERNEL_PERM = 7,        /* solve permutation gather/scatter         */
+  SPCHOL_KERNEL_LOGDET = 8,
+  SPCHOL_KERNEL_SELINV = 9,      /* selected inversion (reverse mode)       */
+  SPCHOL_KERNEL_KINDS = 10
 };
 
 typedef struct {

@@ -30,8 +30,8 @@ class KernelStat(C.Structure):
     _fields_ = [("launches", i64), ("ms", f64), ("flops", f64), ("bytes", f64)]
 
 
-KERNEL_KINDS = ["fill", "scatter_a", "factor", "update_int", "update_ext", "fwd_tri", "fwd_gemv",
-                "bwd_gemvt", "bwd_tri", "perm", "logdet", "selinv"]
+KERNEL_KINDS = ["fill", "scatter_a", "factor", "update_int", "update_ext", "fwd", "bwd", "perm", "logdet",
+                "selinv"]
 
 # name -> (restype, argtypes)
 PROTOTYPES = {

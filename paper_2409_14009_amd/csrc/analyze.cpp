@@ -245,9 +245,12 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
     // storage offsets, sizes, executed flops
     S.loff.assign(ns + 1, 0);
     S.obase.assign(ns + 1, 0);
+    S.wbase.assign(ns + 1, 0);
     for (int64_t J = 0; J < ns; ++J) {
       int64_t k = S.sptr[J + 1] - S.sptr[J], m = S.rptr[J + 1] - S.rptr[J];
       S.loff[J + 1] = S.loff[J] + k * m;
+      // inverted diagonal blocks: full panels nb x nb, the last kp x kp
+      S.wbase[J + 1] = S.wbase[J] + (k / S.nb) * S.nb * S.nb + (k % S.nb) * (k % S.nb);
       S.obase[J + 1] = S.obase[J] + (m - k);
       S.max_k = std::max(S.max_k, k);
       S.max_m = std::max(S.max_m, m);
@@ -384,19 +387,26 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
           by += 8.0 * double(kk) * double((r1 - t.a) + (c1 - t.b)) + 16.0 * double(valid);
           break;
         }
-        case K_FWD_TRI:
-        case K_BWD_TRI: {
+        case K_FWD:
+        case K_BWD:
+        case K_BWD_FIN: {
+          // the rows of L below the panel that the task covers, read once;
+          // their entries of y / x; the panel's inverted diagonal block once
+          // per panel
           const int64_t kp = std::min<int64_t>(nb, k - int64_t(t.a) * nb);
-          fl += double(kp) * double(kp);
-          by += 8.0 * double(kp * (kp + 1) / 2) + 16.0 * double(kp);
-          break;
-        }
-        case K_FWD_GEMV:
-        case K_BWD_GEMVT: {
-          const int64_t kp = std::min<int64_t>(nb, k - int64_t(t.a) * nb);
-          const int64_t nr = std::min<int64_t>(t.b + kTile, m) - t.b;
-          fl += 2.0 * double(nr) * double(kp);
-          by += 8.0 * double(nr) * double(kp) + 16.0 * double(nr);
+          int64_t nr = 0;
+          bool once = false;
+          if (kind == K_FWD) {
+            nr = t.b < 0 ? 0 : std::min<int64_t>(t.b + kTile, m) - t.b;
+            once = t.c == 1;
+          } else if (kind == K_BWD) {
+            nr = t.c < 0 ? m - t.b : std::min<int64_t>(t.b + kTile, m) - t.b;
+            once = t.c < 0;
+          } else {
+            once = true;
+          }
+          fl += 2.0 * double(nr) * double(kp) + (once ? double(kp) * double(kp) : 0.0);
+          by += 8.0 * double(nr) * double(kp) + 16.0 * double(nr) + (once ? 8.0 * double(kp * (kp + 1) / 2) : 0.0);
           break;
         }
         default: break;
@@ -406,11 +416,19 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       Launch& L = plan.back();
       L.ntasks = (int32_t)((int64_t)S.tasks.size() - L.off);
       if (L.ntasks == 0) { plan.pop_back(); return; }
-      for (int64_t q = L.off; q < L.off + L.ntasks; ++q) cost(L.kind, S.tasks[q], L.flops, L.bytes);
+      for (int64_t q = L.off; q < L.off + L.ntasks; ++q) {
+        const int32_t kind = L.kind == K_FACTOR_LA ? (q - L.off < L.nfirst ? K_FACTOR : K_UPD_INT) : L.kind;
+        cost(kind, S.tasks[q], L.flops, L.bytes);
+      }
     };
     for (int64_t l = 0; l < S.nlevels; ++l) {
       int64_t maxp = 0;
       for (int32_t J : bylev[l]) maxp = std::max(maxp, npan(J));
+      // internal update tiles of panel p-1 deferred into the launch that
+      // factors panel p: the first column tile of the trailing part (which
+      // holds panel p) is updated before that launch, the other tiles touch
+      // only columns right of panel p and run beside its factorization
+      std::vector<Task> deferred;
       for (int64_t p = 0; p < maxp; ++p) {
         // the tile holding the diagonal block factors it and writes it back;
         // the other tiles of the panel run in a second launch that reads the
@@ -418,35 +436,56 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
         // diagonal task: Cholesky of the block, its inverse, the first
         // kTrsmRows rows below; a panel with more rows gets a scratch slot
         // for the inverse, read by the row-tile tasks
+        // How many rows below the block the diagonal task solves itself:
+        // with many tasks in the launch, up to kTrsmRows (parallelism comes
+        // from the tasks); with few, none, so that the rows go to the
+        // parallel row-tile launch and the diagonal task (the sequential
+        // part) stays short -- unless every panel of the launch has at most
+        // one tile of rows, when the row-tile launch is skipped altogether.
+        int64_t ntask = 0, maxrows = 0;
+        for (int32_t J : bylev[l])
+          if (npan(J) > p) {
+            ++ntask;
+            maxrows = std::max<int64_t>(maxrows, M(J) - (p * nb + kpan(J, p)));
+          }
+        const int64_t inl = ntask >= kInlineMinTasks ? kTrsmRows : (maxrows <= kTile ? kTile : 0);
         open(S.factor_plan, K_FACTOR, (int32_t)l, (int32_t)p);
-        std::vector<int32_t> slot_of;
-        int32_t nslot = 0;
         for (int32_t J : bylev[l]) {
           if (npan(J) <= p) continue;
           const int64_t rb = p * nb + kpan(J, p);
-          const int32_t slot = (M(J) > rb + kTrsmRows) ? nslot++ : -1;
-          slot_of.push_back(slot);
-          S.tasks.push_back({J, (int32_t)p, (int32_t)rb, slot});
+          // b: first row the task solves inline (== m: none)
+          S.tasks.push_back({J, (int32_t)p, (int32_t)(inl > 0 ? rb : M(J)), 0});
+        }
+        S.factor_plan.back().nfirst = (int32_t)((int64_t)S.tasks.size() - S.factor_plan.back().off);
+        if (!deferred.empty()) {
+          S.factor_plan.back().kind = K_FACTOR_LA;
+          S.tasks.insert(S.tasks.end(), deferred.begin(), deferred.end());
+          deferred.clear();
         }
         close(S.factor_plan);
-        S.max_slots = std::max<int64_t>(S.max_slots, nslot);
         open(S.factor_plan, K_TRSM, (int32_t)l, (int32_t)p);
-        {
-          size_t q = 0;
-          for (int32_t J : bylev[l]) {
-            if (npan(J) <= p) continue;
-            const int32_t slot = slot_of[q++];
-            for (int64_t r0 = p * nb + kpan(J, p) + kTrsmRows; r0 < M(J); r0 += kTile)
-              S.tasks.push_back({J, (int32_t)p, (int32_t)r0, slot});
-          }
+        for (int32_t J : bylev[l]) {
+          if (npan(J) <= p) continue;
+          for (int64_t r0 = p * nb + kpan(J, p) + inl; r0 < M(J); r0 += kTile)
+            S.tasks.push_back({J, (int32_t)p, (int32_t)r0, 0});
         }
         close(S.factor_plan);
         open(S.factor_plan, K_UPD_INT, (int32_t)l, (int32_t)p);
         for (int32_t J : bylev[l]) {
           if (npan(J) <= p + 1) continue;
           for (int64_t c0 = (p + 1) * nb; c0 < K(J); c0 += kTile)
-            for (int64_t r0 = c0; r0 < M(J); r0 += kTile) S.tasks.push_back({J, (int32_t)r0, (int32_t)c0, (int32_t)p});
+            for (int64_t r0 = c0; r0 < M(J); r0 += kTile) {
+              const Task t{J, (int32_t)r0, (int32_t)c0, (int32_t)p};
+              if (c0 == (p + 1) * nb) S.tasks.push_back(t);
+              else deferred.push_back(t);
+            }
         }
+        close(S.factor_plan);
+      }
+      if (!deferred.empty()) {  // (cannot happen: the last panels defer nothing)
+        open(S.factor_plan, K_UPD_INT, (int32_t)l, (int32_t)maxp);
+        S.tasks.insert(S.tasks.end(), deferred.begin(), deferred.end());
+        deferred.clear();
         close(S.factor_plan);
       }
       open(S.factor_plan, K_UPD_EXT, (int32_t)l, -1);
@@ -456,39 +495,49 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       }
       close(S.factor_plan);
     }
-    // forward solve: leaves to root, panels ascending
+    // forward solve: leaves to root, panels ascending; one launch per
+    // round, one task per 64-row tile below the panel (c = 1 on the first
+    // one, which also stores the panel's part of the solution); a panel
+    // with no rows below gets one task with b = -1
     for (int64_t l = 0; l < S.nlevels; ++l) {
       int64_t maxp = 0;
       for (int32_t J : bylev[l]) maxp = std::max(maxp, npan(J));
       for (int64_t p = 0; p < maxp; ++p) {
-        open(S.fwd_plan, K_FWD_TRI, (int32_t)l, (int32_t)p);
-        for (int32_t J : bylev[l])
-          if (npan(J) > p) S.tasks.push_back({J, (int32_t)p, 0, 0});
-        close(S.fwd_plan);
-        open(S.fwd_plan, K_FWD_GEMV, (int32_t)l, (int32_t)p);
+        open(S.fwd_plan, K_FWD, (int32_t)l, (int32_t)p);
         for (int32_t J : bylev[l]) {
           if (npan(J) <= p) continue;
-          int64_t below = std::min<int64_t>(K(J), (p + 1) * nb);
-          for (int64_t r0 = below; r0 < M(J); r0 += kTile) S.tasks.push_back({J, (int32_t)p, (int32_t)r0, 0});
+          const int64_t below = p * nb + kpan(J, p);
+          if (below >= M(J)) S.tasks.push_back({J, (int32_t)p, -1, 1});
+          for (int64_t r0 = below; r0 < M(J); r0 += kTile)
+            S.tasks.push_back({J, (int32_t)p, (int32_t)r0, r0 == below ? 1 : 0});
         }
         close(S.fwd_plan);
       }
     }
-    // backward solve: root to leaves, panels descending
+    // backward solve: root to leaves, panels descending.  A panel with at
+    // most kBwdRows rows below is done by one task (c = -1: gather, then the
+    // inverted diagonal block); a taller one by 64-row tiles (c = 0) that add
+    // their share into an accumulator, finished by a task of a second
+    // launch of the round (BWD_FIN)
     for (int64_t l = S.nlevels - 1; l >= 0; --l) {
       int64_t maxp = 0;
       for (int32_t J : bylev[l]) maxp = std::max(maxp, npan(J));
       for (int64_t p = maxp - 1; p >= 0; --p) {
-        open(S.bwd_plan, K_BWD_GEMVT, (int32_t)l, (int32_t)p);
+        std::vector<int32_t> split;
+        open(S.bwd_plan, K_BWD, (int32_t)l, (int32_t)p);
         for (int32_t J : bylev[l]) {
           if (npan(J) <= p) continue;
-          int64_t below = std::min<int64_t>(K(J), (p + 1) * nb);
-          for (int64_t r0 = below; r0 < M(J); r0 += kTile) S.tasks.push_back({J, (int32_t)p, (int32_t)r0, 0});
+          const int64_t below = p * nb + kpan(J, p);
+          if (M(J) - below <= kBwdRows) {
+            S.tasks.push_back({J, (int32_t)p, (int32_t)below, -1});
+          } else {
+            split.push_back(J);
+            for (int64_t r0 = below; r0 < M(J); r0 += kTile) S.tasks.push_back({J, (int32_t)p, (int32_t)r0, 0});
+          }
         }
         close(S.bwd_plan);
-        open(S.bwd_plan, K_BWD_TRI, (int32_t)l, (int32_t)p);
-        for (int32_t J : bylev[l])
-          if (npan(J) > p) S.tasks.push_back({J, (int32_t)p, 0, 0});
+        open(S.bwd_plan, K_BWD_FIN, (int32_t)l, (int32_t)p);
+        for (int32_t J : split) S.tasks.push_back({J, (int32_t)p, 0, 0});
         close(S.bwd_plan);
       }
     }

@@ -7,17 +7,21 @@
 namespace spchol {
 
 // Work item of a batched launch.  Meaning of the fields per launch kind:
-//   FACTOR     J, panel, first local row below the panel's diagonal block
-//              (the task also solves the 256 rows from there), scratch
-//              slot for the inverted diagonal block (-1: none needed)
-//   TRSM       J, panel, first local row of a further 64-row tile, slot
+//   FACTOR     J, panel, first local row the task solves itself (up to
+//              kTrsmRows rows from there; == m_J: none), -
+//   FACTOR_LA  the first `nfirst` tasks are FACTOR tasks, the others
+//              UPD_INT tiles of the previous panel that do not touch the
+//              panel being factored (one-panel lookahead)
+//   TRSM       J, panel, first local row of a further 64-row tile, -
 //   UPD_INT    J, first local row (target rows), first local col (target
 //              cols), panel (the K range)
 //   UPD_EXT    J, first local row, first local col, -1
-//   FWD_TRI    J, panel, -, -
-//   FWD_GEMV   J, panel, first local row, -
-//   BWD_GEMVT  J, panel, first local row, -
-//   BWD_TRI    J, panel, -, -
+//   FWD        J, panel, first local row of a 64-row tile below the panel
+//              (-1: the panel has no rows below), 1 on the panel's first task
+//   BWD        J, panel, first local row below the panel, -1 (the task
+//              does all rows and the diagonal block) or 0 (one 64-row tile,
+//              summed into the accumulator)
+//   BWD_FIN    J, panel, -, -  (the diagonal block of a tiled panel)
 struct Task {
   int32_t J, a, b, c;
 };
@@ -26,15 +30,15 @@ enum Kind : int32_t {
   K_FACTOR = 0,
   K_UPD_INT = 1,
   K_UPD_EXT = 2,
-  K_FWD_TRI = 3,
-  K_FWD_GEMV = 4,
-  K_BWD_GEMVT = 5,
-  K_BWD_TRI = 6,
+  K_FWD = 3,    // forward solve round: inverse-block product + panel update
+  K_BWD = 4,    // backward solve round: panel gather (+ inverse-block product)
+  K_BWD_FIN = 5,  // backward solve: inverse-block product of split panels
   K_TRSM = 7,
   K_SI_W = 8,   // selected inversion: inverse of the panel's diagonal block
   K_SI_Y = 9,   // Y = Z_BB L_Bp tiles
   K_SI_ZB = 10, // Z_Bp = -Y W tiles (+ T)
   K_SI_ZD = 11, // Z_pp = (W^T - T) W
+  K_FACTOR_LA = 12,
 };
 
 struct Launch {
@@ -46,10 +50,13 @@ struct Launch {
   double flops = 0;  // algorithmic flops of the launch (stored structure)
   double bytes = 0;  // algorithmic HBM bytes of the launch
   int64_t slot_base = 0;  // selected inversion: first entry of si_yoff for this round
+  int32_t nfirst = 0;     // FACTOR_LA: number of leading FACTOR tasks
 };
 
 constexpr int kTile = 64;      // rows (and cols) of an update tile
 constexpr int kTrsmRows = 256; // rows solved by the diagonal-block workgroup
+constexpr int kInlineMinTasks = 128;  // launches with fewer diagonal tasks solve no rows inline
+constexpr int kBwdRows = 512;  // backward solve: taller panels are split into row tiles
 constexpr int kMaxPanel = 64;  // largest panel width
 
 struct Symbolic {
@@ -77,7 +84,11 @@ struct Symbolic {
   std::vector<int32_t> a_col;
   int64_t nlevels = 0;
   int64_t max_k = 0, max_m = 0;
-  int64_t max_slots = 0;  // inverted diagonal blocks held at once (scratch)
+  // inverted diagonal blocks of all panels (written by the factorization,
+  // read by its row tiles and the solves): panel p of J at
+  // wbase[J] + p * nb * nb, kp x kp column-major
+  std::vector<int64_t> wbase;  // ns+1
+
   double flops_alg = 0, flops_exec = 0;
   // schedule
   std::vector<Task> tasks;

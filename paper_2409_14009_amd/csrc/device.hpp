@@ -33,6 +33,7 @@ struct DevSym {
   const int64_t* a_vidx;  // index of each entry in the stored lower values
   const int32_t* e_row;   // nnzA: row of each stored lower entry of A (original)
   const int32_t* e_col;   // nnzA: its column
+  const int64_t* wbase;   // ns+1: offsets of the panels' inverted diagonal blocks
   int64_t n, ns, nnzA, storage;
   int32_t nb;
 };
@@ -42,9 +43,11 @@ hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t st);
 hipError_t launch_status_init(unsigned long long* status, hipStream_t st);
 hipError_t launch_scatter_values(const DevSym& S, const double* vals, double* L, hipStream_t st);
 hipError_t launch_factor_panel(const DevSym& S, double* L, int64_t off, int32_t ntasks,
-                               unsigned long long* status, double* scratch, bool diag, hipStream_t st);
+                               unsigned long long* status, double* winv, bool diag, hipStream_t st);
 hipError_t launch_update(const DevSym& S, double* L, int32_t kind, int64_t off, int32_t ntasks,
                          int32_t prec, hipStream_t st);
+hipError_t launch_factor_la(const DevSym& S, double* L, int64_t off, int32_t nfirst, int32_t ntasks,
+                            unsigned long long* status, double* winv, int32_t prec, hipStream_t st);
 hipError_t launch_si(const DevSym& S, int32_t kind, int64_t off, int32_t ntasks, const double* L, double* Z,
                      const int64_t* yoff, double* ybuf, double* wbuf, double* tbuf, hipStream_t st);
 hipError_t launch_abar(const DevSym& S, const double* Z, double g, const double* X, const double* lam, int64_t ld,
@@ -59,8 +62,8 @@ hipError_t launch_perm_gather(const DevSym& S, const double* B, int64_t ldb, int
                               hipStream_t st);
 hipError_t launch_perm_scatter(const DevSym& S, const double* y, int64_t nrhs, double* B, int64_t ldb,
                                hipStream_t st);
-hipError_t launch_solve_step(const DevSym& S, const double* L, int32_t kind, int64_t off,
-                             int32_t ntasks, double* y, int64_t nrhs, hipStream_t st);
+hipError_t launch_solve_step(const DevSym& S, const double* L, const double* winv, int32_t kind, int64_t off,
+                             int32_t ntasks, double* y, double* x, double* acc, int64_t nrhs, hipStream_t st);
 hipError_t launch_logdet(const DevSym& S, const double* L, double* partial, int32_t npartial,
                          double* out, hipStream_t st);
 int32_t logdet_partials(int64_t n);

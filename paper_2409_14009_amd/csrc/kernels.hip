@@ -68,12 +68,14 @@ constexpr int MB = 16;          // micro-block width
 
 // Columns of the block past kp are padded with an identity (unit
 // diagonal, zero off-diagonal), so they factor to themselves and the sweep
-// needs no per-column branch.  The pivot comes from its lane with readlane;
-// the scaled column goes through LDS (colb, one wavefront) and is read back
-// as a broadcast.  Like LAPACK's unblocked Cholesky, the column is scaled
-// by the reciprocal of the pivot's square root.
-__device__ __forceinline__ void potrf16(double (&r)[MB], int lane, int j0, double* __restrict__ colb,
-                                        unsigned long long* __restrict__ status, int64_t col0) {
+// needs no per-column branch.  The pivot and the entries of the scaled
+// column that the other rows need (rows j0+c, c > q, one per lane) come
+// straight from their lanes' registers with readlane (scalar operands of
+// the row update), so the sweep never touches memory.  Like LAPACK's
+// unblocked Cholesky, the column is scaled by the reciprocal of the pivot's
+// square root.
+__device__ __forceinline__ void potrf16(double (&r)[MB], int lane, int j0, unsigned long long* __restrict__ status,
+                                        int64_t col0) {
 #pragma unroll
   for (int q = 0; q < MB; ++q) {
     double piv = readlane_d(r[q], j0 + q);
@@ -85,15 +87,13 @@ __device__ __forceinline__ void potrf16(double (&r)[MB], int lane, int j0, doubl
     const double rinv = 1.0 / ljj;
     const double lq = (lane == j0 + q) ? ljj : (lane > j0 + q ? r[q] * rinv : 0.0);
     r[q] = lq;
-    colb[lane] = lq;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // one broadcast at a time: hoisted, the broadcasts would pile up in
+    // scalar registers and spill
 #pragma unroll
-    for (int c = q + 1; c < MB; ++c) r[c] = fma(-lq, colb[j0 + c], r[c]);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int c = q + 1; c < MB; ++c) {
+      r[c] = fma(-lq, readlane_d(lq, j0 + c), r[c]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 }
 
@@ -170,13 +170,17 @@ __device__ __forceinline__ void invert_diag_block(const double* __restrict__ Dc,
   //     computes column l of inv(L_ww)
   if (w < nblk && lane < MB) {
     const int b0 = MB * w;
-    double x[MB];
+    double x[MB], rd[MB];
+    // the reciprocals are independent of each other (no division on the
+    // substitution's dependency chain)
+#pragma unroll
+    for (int i = 0; i < MB; ++i) rd[i] = 1.0 / Dc[(b0 + i) * DLD + b0 + i];
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
       double s = (i == lane) ? 1.0 : 0.0;
 #pragma unroll
       for (int q = 0; q < i; ++q) s = fma(-Dc[(b0 + q) * DLD + b0 + i], x[q], s);
-      x[i] = s / Dc[(b0 + i) * DLD + b0 + i];
+      x[i] = s * rd[i];
     }
 #pragma unroll
     for (int i = 0; i < MB; ++i) Wc[(b0 + lane) * DLD + b0 + i] = x[i];
@@ -217,16 +221,15 @@ __device__ __forceinline__ void invert_diag_block(const double* __restrict__ Dc,
 //      matrix cores;
 //   3. the next 256 rows of the panel: X = B W^T (triangular solve as a
 //      product with the inverted diagonal block);
-//   4. when the panel has more rows (slot >= 0), W goes to scratch for the
-//      row-tile launch.
-__global__ __launch_bounds__(256) void k_panel(DevSym S, double* __restrict__ L, int64_t off,
-                                               unsigned long long* __restrict__ status,
-                                               double* __restrict__ scratch) {
-  __shared__ __attribute__((aligned(16))) double Dc[NBMAX * DLD];
-  __shared__ __attribute__((aligned(16))) double Wc[NBMAX * DLD];
-  __shared__ __attribute__((aligned(16))) double colb[NBMAX];
-  const DevTask t = S.tasks[off + blockIdx.x];
-  const int J = t.J, p = t.a, rb = t.b, slot = t.c;
+//   4. W is stored (winv) for the row-tile launch and the solves.
+constexpr int PANEL_SMEM = 2 * NBMAX * DLD;  // doubles: Dc, Wc
+
+__device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__ L, const DevTask t,
+                                           unsigned long long* __restrict__ status, double* __restrict__ winv,
+                                           double* __restrict__ smem) {
+  double* __restrict__ Dc = smem;
+  double* __restrict__ Wc = smem + NBMAX * DLD;
+  const int J = t.J, p = t.a, rb = t.b;
   const int m = S.sm[J], k = S.sk[J];
   const int c0 = p * S.nb;
   const int kp = min(S.nb, k - c0);
@@ -268,7 +271,7 @@ __global__ __launch_bounds__(256) void k_panel(DevSym S, double* __restrict__ L,
       for (int q = 0; q < MB; ++q) xb[q] = (lane >= j0) ? Dc[(j0 + q) * DLD + lane] : 0.0;
       // the sweep factors the 16 x 16 block (its lanes) and, on the lanes
       // below it, solves those rows against it
-      potrf16(xb, lane, j0, colb, status, (int64_t)S.sfirst[J] + c0 + j0);
+      potrf16(xb, lane, j0, status, (int64_t)S.sfirst[J] + c0 + j0);
       if (mine) {
 #pragma unroll
         for (int q = 0; q < MB; ++q)
@@ -310,10 +313,14 @@ __global__ __launch_bounds__(256) void k_panel(DevSym S, double* __restrict__ L,
   invert_diag_block(Dc, Wc, nblk, lane, w);
   __syncthreads();
 
-  // 4. W for the row-tile launch, row-major: scratch[slot][r * 64 + c] = W_rc
-  if (slot >= 0) {
-    double* dst = scratch + (int64_t)slot * NBMAX * NBMAX;
-    for (int idx = tid; idx < NBMAX * NBMAX; idx += 256) dst[idx] = Wc[(idx & 63) * DLD + (idx >> 6)];
+  // 4. W, kp x kp column-major (zeros above the diagonal), for the row-tile
+  //    launch and the solves
+  {
+    double* dst = winv + S.wbase[J] + (int64_t)p * S.nb * S.nb;
+    for (int idx = tid; idx < kp * kp; idx += 256) {
+      const int c = idx / kp, r = idx - c * kp;
+      dst[idx] = r >= c ? Wc[c * DLD + r] : 0.0;
+    }
   }
   // 3. rows rb .. rb + 255
   for (int R0 = rb; R0 < min(rb + 4 * 64, m); R0 += 64) {
@@ -324,28 +331,40 @@ __global__ __launch_bounds__(256) void k_panel(DevSym S, double* __restrict__ L,
   }
 }
 
-// Panel step, row tiles below the first 256 rows: X = B W^T with W from the
-// scratch slot the diagonal task wrote (256 threads, one 64-row tile each).
+__global__ __launch_bounds__(256) void k_panel(DevSym S, double* __restrict__ L, int64_t off,
+                                               unsigned long long* __restrict__ status,
+                                               double* __restrict__ winv) {
+  __shared__ __attribute__((aligned(16))) double smem[PANEL_SMEM];
+  panel_body(S, L, S.tasks[off + blockIdx.x], status, winv, smem);
+}
+
+// Panel step, row tiles not solved by the diagonal task: X = B W^T with the
+// inverted diagonal block W the diagonal task stored (256 threads, one
+// 64-row tile each).
 __global__ __launch_bounds__(256) void k_panel_rows(DevSym S, double* __restrict__ L, int64_t off,
-                                                    const double* __restrict__ scratch) {
+                                                    const double* __restrict__ winv) {
   __shared__ __attribute__((aligned(16))) double As[NBMAX * DLD];
   __shared__ __attribute__((aligned(16))) double Wc[NBMAX * DLD];
   const DevTask t = S.tasks[off + blockIdx.x];
-  const int J = t.J, p = t.a, R0 = t.b, slot = t.c;
+  const int J = t.J, p = t.a, R0 = t.b;
   const int m = S.sm[J], k = S.sk[J];
   const int c0 = p * S.nb;
   const int kp = min(S.nb, k - c0);
   double* __restrict__ Lp = L + S.loff[J] + (int64_t)c0 * m;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const double* src = scratch + (int64_t)slot * NBMAX * NBMAX;
+  const double* __restrict__ src = winv + S.wbase[J] + (int64_t)p * S.nb * S.nb;
   for (int base = 0; base < NBMAX * NBMAX; base += 16 * 256) {
     double v[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = src[base + u * 256 + tid];
+    for (int u = 0; u < 16; ++u) {
+      const int idx = base + u * 256 + tid;  // idx = c * 64 + r
+      const int c = idx >> 6, r = idx & 63;
+      v[u] = (r < kp && c < kp) ? src[c * kp + r] : 0.0;
+    }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int idx = base + u * 256 + tid;  // idx = r * 64 + c
-      Wc[(idx & 63) * DLD + (idx >> 6)] = v[u];
+      const int idx = base + u * 256 + tid;
+      Wc[(idx >> 6) * DLD + (idx & 63)] = v[u];
     }
   }
   stage_rows(As, Lp, m, kp, R0, tid, 256);
@@ -394,14 +413,18 @@ template <> struct UpdPrec<1> {
 };
 
 constexpr int ALD = TILE + 2;
+constexpr int CLD = TILE + 1;  // column stride of the epilogue tile
+
+constexpr int UPD_SMEM = TILE * CLD + 2 * KC * ALD;  // doubles: Cs, then As and Bs (T each)
 
 template <int P>
-__global__ __launch_bounds__(256) void k_update(DevSym S, double* __restrict__ L, int32_t kind, int64_t off) {
+__device__ __forceinline__ void update_body(const DevSym& S, double* __restrict__ L, int32_t kind, const DevTask t,
+                                            double* __restrict__ smem) {
   using Pr = UpdPrec<P>;
   using T = typename Pr::T;
-  __shared__ T As[KC * ALD];
-  __shared__ T Bs[KC * ALD];
-  const DevTask t = S.tasks[off + blockIdx.x];
+  double* __restrict__ Cs = smem;
+  T* __restrict__ As = reinterpret_cast<T*>(smem + TILE * CLD);
+  T* __restrict__ Bs = As + KC * ALD;
   const int J = t.J, row0 = t.a, col0 = t.b;
   const int m = S.sm[J], k = S.sk[J];
   int kb, ke, colEnd;
@@ -460,38 +483,56 @@ __global__ __launch_bounds__(256) void k_update(DevSym S, double* __restrict__ L
     __syncthreads();
   }
 
+  // Epilogue: the tile goes through LDS so that each wavefront then owns
+  // whole tile columns, one row per lane: the target addresses of a column
+  // are row runs of the ancestor's storage, so the read-modify-writes (and
+  // the atomics) are coalesced instead of touching 16 columns per access.
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Cs[(wc + 16 * bj + li) * CLD + wr + 16 * bi + Pr::row(v, lk)] = (double)acc[bi][bj][v];
+  __syncthreads();
+  const int gr = row0 + lane;
+  const int cmax = min(TILE, colEnd - col0);
   if (kind == 1) {
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      const int gc = col0 + wc + 16 * bj + li;
-      if (gc >= colEnd) continue;
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int gr = row0 + wr + 16 * bi + Pr::row(v, lk);
-          if (gr < m && gr >= gc) Lj[(int64_t)gc * m + gr] -= (double)acc[bi][bj][v];
-        }
+    for (int cc = w; cc < cmax; cc += 4) {
+      const int gc = col0 + cc;
+      if (gr < m && gr >= gc) Lj[(int64_t)gc * m + gr] -= Cs[cc * CLD + lane];
     }
   } else {
     const int64_t ob = S.obase[J];
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      const int gc = col0 + wc + 16 * bj + li;
-      if (gc >= colEnd) continue;
+    const bool rowok = gr < m;
+    for (int cc = w; cc < cmax; cc += 4) {
+      const int gc = col0 + cc;
       const int b = gc - k;
       const int pair = S.opair[ob + b];
       const int64_t cbase = S.ocbase[ob + b];
       const int32_t* __restrict__ tp = S.tpos + S.relptr[pair] - S.pa0[pair] - k;
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int gr = row0 + wr + 16 * bi + Pr::row(v, lk);
-          if (gr < m && gr >= gc) atomicAdd(L + cbase + tp[gr], -(double)acc[bi][bj][v]);
-        }
+      if (rowok && gr >= gc) atomicAdd(L + cbase + tp[gr], -Cs[cc * CLD + lane]);
     }
   }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_update(DevSym S, double* __restrict__ L, int32_t kind, int64_t off) {
+  __shared__ __attribute__((aligned(16))) double smem[UPD_SMEM];
+  update_body<P>(S, L, kind, S.tasks[off + blockIdx.x], smem);
+}
+
+// One-panel lookahead: workgroups below nfirst factor panel p (panel_body),
+// the others apply internal update tiles of panel p-1 to columns right of
+// panel p.  The two sets touch disjoint columns.
+template <int P>
+__global__ __launch_bounds__(256) void k_panel_la(DevSym S, double* __restrict__ L, int64_t off, int32_t nfirst,
+                                                  unsigned long long* __restrict__ status,
+                                                  double* __restrict__ winv) {
+  __shared__ __attribute__((aligned(16))) double smem[PANEL_SMEM > UPD_SMEM ? PANEL_SMEM : UPD_SMEM];
+  const DevTask t = S.tasks[off + blockIdx.x];
+  if ((int)blockIdx.x < nfirst) panel_body(S, L, t, status, winv, smem);
+  else update_body<P>(S, L, 1, t, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -521,145 +562,175 @@ __global__ void k_perm_scatter(const int64_t* __restrict__ perm, int64_t n, cons
 // forward: y_p <- D_p^{-1} y_p, one wavefront per (J, panel); lane i owns
 // row i, column sweep: y_j is final, broadcast with readlane, subtracted
 // from the rows below
-__global__ __launch_bounds__(64) void k_fwd_tri(DevSym S, const double* __restrict__ L, int64_t off,
-                                                double* __restrict__ y, int64_t nrhs) {
-  __shared__ double Dc[NBMAX * DLD];  // column-major: Dc[c * DLD + i] = D_ic
-  __shared__ double rinv[NBMAX];
-  const DevTask t = S.tasks[off + blockIdx.x];
-  const int J = t.J, p = t.a;
-  const int m = S.sm[J], k = S.sk[J];
-  const int c0 = p * S.nb, kp = min(S.nb, k - c0);
-  const double* __restrict__ src = L + S.loff[J] + (int64_t)c0 * m + c0;
-  const int lane = threadIdx.x;
-  for (int cb = 0; cb < kp; cb += 16) {
-    double v[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int c = cb + u;
-      v[u] = (c < kp && lane < kp && c <= lane) ? src[(int64_t)c * m + lane] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 16; ++u) Dc[(cb + u) * DLD + lane] = v[u];
-  }
-  __syncthreads();
-  if (lane < kp) rinv[lane] = 1.0 / Dc[lane * DLD + lane];
-  __syncthreads();
-  const int64_t g = S.sfirst[J] + c0 + lane;
-  for (int64_t c = 0; c < nrhs; ++c) {
-    double v = lane < kp ? y[g + c * S.n] : 0.0;
-    for (int j = 0; j < kp; ++j) {
-      const double vj = readlane_d(v, j) * rinv[j];
-      if (lane == j) v = vj;
-      else if (lane > j) v = fma(-Dc[j * DLD + lane], vj, v);
-    }
-    if (lane < kp) y[g + c * S.n] = v;
-  }
-}
-
-// forward: y[rows below the panel] -= L[rows, panel] y_p
-__global__ __launch_bounds__(256) void k_fwd_gemv(DevSym S, const double* __restrict__ L, int64_t off,
-                                                  double* __restrict__ y, int64_t nrhs) {
-  __shared__ double yp[NBMAX][4];
+// Forward round, one task per 64-row tile below a panel (Sec. II: the
+// supernodal forward substitution).  Every task forms z_p = W_p y_p with the
+// stored inverse of the panel's diagonal block (y_p is final: all panels and
+// supernodes that update it were processed in earlier rounds), the first
+// task stores z_p into x, and the tile's rows get y_R -= L_Rp z_p: plain
+// updates for rows of the supernode's own later columns (one writer),
+// atomics for ancestor rows (several supernodes of a level may share one).
+// Both products split the panel's columns over the four wavefronts (16
+// each) and sum the partial results in LDS; right-hand sides go four at a
+// time, so L and W are read once per four.
+__global__ __launch_bounds__(256) void k_fwd(DevSym S, const double* __restrict__ L, const double* __restrict__ winv,
+                                             int64_t off, double* __restrict__ y, double* __restrict__ x,
+                                             int64_t nrhs) {
+  __shared__ double ys[4][NBMAX];
+  __shared__ double zs[4][NBMAX];
+  __shared__ double part[4][4][NBMAX];
   const DevTask t = S.tasks[off + blockIdx.x];
   const int J = t.J, p = t.a, r0 = t.b;
+  const bool first = t.c == 1;
   const int m = S.sm[J], k = S.sk[J];
   const int c0 = p * S.nb, kp = min(S.nb, k - c0);
   const double* __restrict__ Lj = L + S.loff[J];
+  const double* __restrict__ W = winv + S.wbase[J] + (int64_t)p * S.nb * S.nb;
   const int32_t* __restrict__ R = S.rows + S.rptr[J];
-  const int64_t first = S.sfirst[J];
-  const int tid = threadIdx.x;
-  const int row = r0 + (tid % 64);
-  const int cs = tid / 64;
+  const int64_t fcol = S.sfirst[J] + c0;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int t0 = 16 * w, t1 = min(kp, t0 + 16);
+  const int row = r0 + lane;
+  const bool rowok = r0 >= 0 && row < m;
   for (int64_t cb = 0; cb < nrhs; cb += 4) {
-    __syncthreads();
-    for (int idx = tid; idx < kp * 4; idx += 256) {
-      const int tt = idx % kp, cc = idx / kp;
-      yp[tt][cc] = (cb + cc < nrhs) ? y[first + c0 + tt + (cb + cc) * S.n] : 0.0;
+    {
+      const int64_t c = cb + w;  // thread (lane, w) loads entry lane of RHS cb + w
+      ys[w][lane] = (lane < kp && c < nrhs) ? y[fcol + lane + c * S.n] : 0.0;
     }
     __syncthreads();
-    const int64_t c = cb + cs;
-    if (row < m && c < nrhs) {
-      double s = 0.0;
-      for (int tt = 0; tt < kp; ++tt) s = fma(Lj[(int64_t)(c0 + tt) * m + row], yp[tt][cs], s);
-      double* dst = y + R[row] + c * S.n;
-      if (row < k) *dst -= s;
-      else atomicAdd(dst, -s);
+    double z[4] = {0.0, 0.0, 0.0, 0.0};
+    if (lane < kp)
+      for (int tt = t0; tt < t1; ++tt) {
+        const double wv = W[(int64_t)tt * kp + lane];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) z[q] = fma(wv, ys[q][tt], z[q]);
+      }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[w][q][lane] = z[q];
+    __syncthreads();
+    {
+      const int q = w, i = lane;  // thread (lane, w) sums entry lane of RHS cb + w
+      const double v = (part[0][q][i] + part[1][q][i]) + (part[2][q][i] + part[3][q][i]);
+      zs[q][i] = v;
+      if (first && i < kp && cb + q < nrhs) x[fcol + i + (cb + q) * S.n] = v;
     }
+    __syncthreads();
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    if (rowok)
+      for (int tt = t0; tt < t1; ++tt) {
+        const double lv = Lj[(int64_t)(c0 + tt) * m + row];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = fma(lv, zs[q][tt], a[q]);
+      }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[w][q][lane] = a[q];
+    __syncthreads();
+    {
+      const int q = w, i = lane;
+      const int64_t c = cb + q;
+      if (r0 >= 0 && r0 + i < m && c < nrhs) {
+        const double v = (part[0][q][i] + part[1][q][i]) + (part[2][q][i] + part[3][q][i]);
+        double* dst = y + R[r0 + i] + c * S.n;
+        if (r0 + i < k) *dst -= v;
+        else atomicAdd(dst, -v);
+      }
+    }
+    __syncthreads();
   }
 }
 
-// backward: y_p -= L[rows below, panel]^T y[rows below]
-__global__ __launch_bounds__(256) void k_bwd_gemvt(DevSym S, const double* __restrict__ L, int64_t off,
-                                                   double* __restrict__ y, int64_t nrhs) {
+// x_p <- W_p^T v for the panel's kp entries v in vs (LDS), by the block's
+// first 64 threads; column i of W is contiguous.
+__device__ __forceinline__ double apply_wt(const double* __restrict__ W, int kp, const double* __restrict__ vs,
+                                           int i) {
+  const double* __restrict__ Wi = W + (int64_t)i * kp;
+  double z = 0.0;
+  for (int tt = i; tt < kp; ++tt) z = fma(Wi[tt], vs[tt], z);
+  return z;
+}
+
+// Backward round (Sec. II: the supernodal back substitution).  c = -1: the
+// task gathers L_Rp^T x_R over all rows below the panel (x_R is final:
+// later panels and ancestors were done in earlier rounds), then forms
+// x_p = W_p^T (x_p - L_Rp^T x_R).  c = 0: the task adds the share of one
+// 64-row tile into acc_p; a BWD_FIN task of the next launch finishes the
+// panel.  Each 64-row chunk of L is staged in LDS (coalesced) once per four
+// right-hand sides; thread (lane, w) sums column lane over rows 16w..16w+15.
+__global__ __launch_bounds__(256) void k_bwd(DevSym S, const double* __restrict__ L, const double* __restrict__ winv,
+                                             int64_t off, double* __restrict__ x, double* __restrict__ acc,
+                                             int64_t nrhs) {
   __shared__ double Ls[TILE][NBMAX + 1];
-  __shared__ double ys[TILE];
-  __shared__ double red[4][NBMAX];
+  __shared__ double xs[4][TILE];
+  __shared__ double red[4][4][NBMAX];
+  __shared__ double vs[4][NBMAX];
   const DevTask t = S.tasks[off + blockIdx.x];
-  const int J = t.J, p = t.a, r0 = t.b;
+  const int J = t.J, p = t.a, rb = t.b;
+  const bool whole = t.c < 0;
   const int m = S.sm[J], k = S.sk[J];
   const int c0 = p * S.nb, kp = min(S.nb, k - c0);
   const double* __restrict__ Lj = L + S.loff[J];
   const int32_t* __restrict__ R = S.rows + S.rptr[J];
-  const int64_t first = S.sfirst[J];
-  const int tid = threadIdx.x;
-  const int nr = min(TILE, m - r0);
-  for (int idx = tid; idx < nr * kp; idx += 256) {
-    const int r = idx % nr, tt = idx / nr;
-    Ls[r][tt] = Lj[(int64_t)(c0 + tt) * m + r0 + r];
-  }
-  const int tt = tid % 64, rg = tid / 64;
-  for (int64_t c = 0; c < nrhs; ++c) {
-    __syncthreads();
-    for (int r = tid; r < nr; r += 256) ys[r] = y[R[r0 + r] + c * S.n];
-    __syncthreads();
-    double s = 0.0;
-    if (tt < kp) {
-      const int rend = min(nr, rg * 16 + 16);
-      for (int r = rg * 16; r < rend; ++r) s = fma(Ls[r][tt], ys[r], s);
+  const int64_t fcol = S.sfirst[J] + c0;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int re = whole ? m : min(m, rb + TILE);
+  for (int64_t cb = 0; cb < nrhs; cb += 4) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r0 = rb; r0 < re; r0 += TILE) {
+      const int nr = min(TILE, re - r0);
+      __syncthreads();
+      for (int idx = tid; idx < TILE * kp; idx += 256) {
+        const int r = idx & (TILE - 1), tt = idx / TILE;
+        Ls[r][tt] = r < nr ? Lj[(int64_t)(c0 + tt) * m + r0 + r] : 0.0;
+      }
+      {
+        const int64_t c = cb + w;  // thread (lane, w) loads row lane for RHS cb + w
+        xs[w][lane] = (lane < nr && c < nrhs) ? x[R[r0 + lane] + c * S.n] : 0.0;
+      }
+      __syncthreads();
+      if (lane < kp)
+        for (int r = 16 * w; r < 16 * w + 16; ++r) {
+          const double lv = Ls[r][lane];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) a[q] = fma(lv, xs[q][r], a[q]);
+        }
     }
-    red[rg][tt] = s;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[w][q][lane] = a[q];
     __syncthreads();
-    if (tid < kp) {
-      const double v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-      atomicAdd(y + first + c0 + tid + c * S.n, -v);
+    {
+      const int q = w, i = lane;  // thread (lane, w): entry lane of RHS cb + w
+      const int64_t c = cb + q;
+      const double v = (red[0][q][i] + red[1][q][i]) + (red[2][q][i] + red[3][q][i]);
+      if (whole) vs[q][i] = (i < kp && c < nrhs) ? x[fcol + i + c * S.n] - v : 0.0;
+      else if (i < kp && c < nrhs) atomicAdd(acc + fcol + i + c * S.n, v);
     }
+    __syncthreads();
+    if (whole && lane < kp && cb + w < nrhs)
+      x[fcol + lane + (cb + w) * S.n] = apply_wt(winv + S.wbase[J] + (int64_t)p * S.nb * S.nb, kp, vs[w], lane);
   }
 }
 
-// backward: y_p <- D_p^{-T} y_p; row sweep from the bottom, the block kept
-// row-major (Dr[j * DLD + i] = D_ji) so lane i reads D_ji contiguously
-__global__ __launch_bounds__(64) void k_bwd_tri(DevSym S, const double* __restrict__ L, int64_t off,
-                                                double* __restrict__ y, int64_t nrhs) {
-  __shared__ double Dr[NBMAX * DLD];
-  __shared__ double rinv[NBMAX];
+// Backward, second launch of a round: x_p = W_p^T (x_p - acc_p) for the
+// panels split into tiles; acc_p is left at zero for the next solve.
+__global__ __launch_bounds__(64) void k_bwd_fin(DevSym S, const double* __restrict__ winv, int64_t off,
+                                                double* __restrict__ x, double* __restrict__ acc, int64_t nrhs) {
+  __shared__ double vs[NBMAX];
   const DevTask t = S.tasks[off + blockIdx.x];
   const int J = t.J, p = t.a;
-  const int m = S.sm[J], k = S.sk[J];
+  const int k = S.sk[J];
   const int c0 = p * S.nb, kp = min(S.nb, k - c0);
-  const double* __restrict__ src = L + S.loff[J] + (int64_t)c0 * m + c0;
+  const int64_t fcol = S.sfirst[J] + c0;
   const int lane = threadIdx.x;
-  for (int ib = 0; ib < kp; ib += 16) {  // lane = row j of the block, column i
-    double v[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int i = ib + u;
-      v[u] = (i < kp && lane < kp && i <= lane) ? src[(int64_t)i * m + lane] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 16; ++u) Dr[lane * DLD + ib + u] = v[u];
-  }
-  __syncthreads();
-  if (lane < kp) rinv[lane] = 1.0 / Dr[lane * DLD + lane];
-  __syncthreads();
-  const int64_t g = S.sfirst[J] + c0 + lane;
   for (int64_t c = 0; c < nrhs; ++c) {
-    double v = lane < kp ? y[g + c * S.n] : 0.0;
-    for (int j = kp - 1; j >= 0; --j) {
-      const double vj = readlane_d(v, j) * rinv[j];
-      if (lane == j) v = vj;
-      else if (lane < j) v = fma(-Dr[j * DLD + lane], vj, v);
+    if (lane < kp) {
+      double* ap = acc + fcol + lane + c * S.n;
+      vs[lane] = x[fcol + lane + c * S.n] - *ap;
+      *ap = 0.0;
+    } else {
+      vs[lane] = 0.0;
     }
-    if (lane < kp) y[g + c * S.n] = v;
+    __syncthreads();
+    if (lane < kp) x[fcol + lane + c * S.n] = apply_wt(winv + S.wbase[J] + (int64_t)p * S.nb * S.nb, kp, vs, lane);
+    __syncthreads();
   }
 }
 
@@ -1016,10 +1087,18 @@ hipError_t launch_scatter_values(const DevSym& S, const double* vals, double* L,
 }
 
 hipError_t launch_factor_panel(const DevSym& S, double* L, int64_t off, int32_t ntasks,
-                               unsigned long long* status, double* scratch, bool diag, hipStream_t st) {
+                               unsigned long long* status, double* winv, bool diag, hipStream_t st) {
   if (ntasks <= 0) return hipSuccess;
-  if (diag) k_panel<<<ntasks, 256, 0, st>>>(S, L, off, status, scratch);
-  else k_panel_rows<<<ntasks, 256, 0, st>>>(S, L, off, scratch);
+  if (diag) k_panel<<<ntasks, 256, 0, st>>>(S, L, off, status, winv);
+  else k_panel_rows<<<ntasks, 256, 0, st>>>(S, L, off, winv);
+  return hipGetLastError();
+}
+
+hipError_t launch_factor_la(const DevSym& S, double* L, int64_t off, int32_t nfirst, int32_t ntasks,
+                            unsigned long long* status, double* winv, int32_t prec, hipStream_t st) {
+  if (ntasks <= 0) return hipSuccess;
+  if (prec == 1) k_panel_la<1><<<ntasks, 256, 0, st>>>(S, L, off, nfirst, status, winv);
+  else k_panel_la<0><<<ntasks, 256, 0, st>>>(S, L, off, nfirst, status, winv);
   return hipGetLastError();
 }
 
@@ -1045,16 +1124,12 @@ hipError_t launch_perm_scatter(const DevSym& S, const double* y, int64_t nrhs, d
   return hipGetLastError();
 }
 
-hipError_t launch_solve_step(const DevSym& S, const double* L, int32_t kind, int64_t off, int32_t ntasks,
-                             double* y, int64_t nrhs, hipStream_t st) {
+hipError_t launch_solve_step(const DevSym& S, const double* L, const double* winv, int32_t kind, int64_t off,
+                             int32_t ntasks, double* y, double* x, double* acc, int64_t nrhs, hipStream_t st) {
   if (ntasks <= 0) return hipSuccess;
-  switch (kind) {
-    case 3: k_fwd_tri<<<ntasks, 64, 0, st>>>(S, L, off, y, nrhs); break;
-    case 4: k_fwd_gemv<<<ntasks, 256, 0, st>>>(S, L, off, y, nrhs); break;
-    case 5: k_bwd_gemvt<<<ntasks, 256, 0, st>>>(S, L, off, y, nrhs); break;
-    case 6: k_bwd_tri<<<ntasks, 64, 0, st>>>(S, L, off, y, nrhs); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (kind == 3) k_fwd<<<ntasks, 256, 0, st>>>(S, L, winv, off, y, x, nrhs);
+  else if (kind == 4) k_bwd<<<ntasks, 256, 0, st>>>(S, L, winv, off, x, acc, nrhs);
+  else k_bwd_fin<<<ntasks, 64, 0, st>>>(S, winv, off, x, acc, nrhs);
   return hipGetLastError();
 }
 

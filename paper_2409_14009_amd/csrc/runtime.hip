@@ -106,6 +106,7 @@ struct spchol_sym_s {
     HIP_TRY(up(&dev.a_vidx, S.a_vidx));
     HIP_TRY(up(&dev.e_row, S.e_row));
     HIP_TRY(up(&dev.e_col, S.e_col));
+    HIP_TRY(up(&dev.wbase, S.wbase));
     HIP_TRY(up(&si_yoff, S.si_yoff));
     {
       std::vector<int64_t> bo = batch_off;
@@ -150,14 +151,49 @@ struct Profiler {
   }
 };
 
+// Work vectors of a solve: the permuted right-hand sides y, the forward
+// result x (solved in place by the backward sweep) and the backward sweep's
+// per-column accumulators of split panels (zero between solves: the
+// kernels leave them cleared).
+struct SolveWork {
+  double* y = nullptr;
+  double* x = nullptr;
+  double* acc = nullptr;
+  int64_t cap = 0;  // entries of y, x and acc (n x nrhs)
+  void release() {
+    if (y) (void)hipFree(y);
+    if (x) (void)hipFree(x);
+    if (acc) (void)hipFree(acc);
+    y = x = acc = nullptr;
+    cap = 0;
+  }
+  ~SolveWork() { release(); }
+  // allocates (and clears acc); synchronous, never inside a capture
+  hipError_t ensure(int64_t n, int64_t nrhs) {
+    if (cap >= n * nrhs && acc) return hipSuccess;
+    release();
+    const size_t v = (size_t)(n * nrhs > 0 ? n * nrhs : 1) * sizeof(double);
+    hipError_t e = hipMalloc((void**)&y, v);
+    if (e == hipSuccess) e = hipMalloc((void**)&x, v);
+    if (e == hipSuccess) e = hipMalloc((void**)&acc, v);
+    if (e == hipSuccess) e = hipMemset(acc, 0, v);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      release();
+      return e;
+    }
+    cap = n * nrhs;
+    return hipSuccess;
+  }
+};
+
 struct spchol_num_s {
   spchol_sym_s* sym = nullptr;
   double* L = nullptr;
   unsigned long long* status = nullptr;
-  double* y = nullptr;
-  int64_t ycap = 0;
+  SolveWork sw;
   double* red = nullptr;  // logdet partials + result
-  double* scratch = nullptr;  // inverted diagonal blocks of the panels of one launch
+  double* winv = nullptr;  // inverted diagonal blocks of all panels
   int32_t prec = 0;           // update precision of the last factorization
   double* rwork = nullptr;    // refinement residual / correction, n x nrhs
   int64_t rcap = 0;
@@ -175,9 +211,8 @@ struct spchol_num_s {
     if (rwork) (void)hipFree(rwork);
     if (stats) (void)hipFree(stats);
     if (L) (void)hipFree(L);
-    if (scratch) (void)hipFree(scratch);
+    if (winv) (void)hipFree(winv);
     if (status) (void)hipFree(status);
-    if (y) (void)hipFree(y);
     if (red) (void)hipFree(red);
   }
 };
@@ -210,10 +245,14 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
   HIP_TRY(timed(N, SPCHOL_KERNEL_SCATTER_A, 0.0, 24.0 * D.nnzA, st,
                 [&] { return launch_scatter_values(D, vals, N->L, st); }));
   for (const Launch& l : S.factor_plan) {
-    if (l.kind == K_FACTOR || l.kind == K_TRSM) {
+    if (l.kind == K_FACTOR_LA) {
+      HIP_TRY(timed(N, SPCHOL_KERNEL_FACTOR, l.flops, l.bytes, st, [&] {
+        return launch_factor_la(D, N->L, l.off, l.nfirst, l.ntasks, N->status, N->winv, prec, st);
+      }));
+    } else if (l.kind == K_FACTOR || l.kind == K_TRSM) {
       const bool diag = l.kind == K_FACTOR;
       HIP_TRY(timed(N, SPCHOL_KERNEL_FACTOR, l.flops, l.bytes, st,
-                    [&] { return launch_factor_panel(D, N->L, l.off, l.ntasks, N->status, N->scratch, diag, st); }));
+                    [&] { return launch_factor_panel(D, N->L, l.off, l.ntasks, N->status, N->winv, diag, st); }));
     } else {
       HIP_TRY(timed(N, l.kind == K_UPD_INT ? SPCHOL_KERNEL_UPDATE_INT : SPCHOL_KERNEL_UPDATE_EXT, l.flops,
                     l.bytes, st, [&] { return launch_update(D, N->L, l.kind, l.off, l.ntasks, prec, st); }));
@@ -234,25 +273,26 @@ static spchol_status read_info(spchol_num_s* N, hipStream_t st, int64_t* info) {
 }
 
 // Permute, forward and backward supernodal solves, permute back, with the
-// work vector y (n x nrhs).
-static spchol_status enqueue_solve(spchol_num_s* num, double* y, double* B_dev, int64_t nrhs, int64_t ldb,
+// work vectors of w (allocated for n x nrhs).
+static spchol_status enqueue_solve(spchol_num_s* num, SolveWork& w, double* B_dev, int64_t nrhs, int64_t ldb,
                                    hipStream_t st) {
   const Symbolic& S = num->sym->S;
   const DevSym& D = num->sym->dev;
   const double pbytes = 24.0 * double(S.n) * double(nrhs);
   HIP_TRY(timed(num, SPCHOL_KERNEL_PERM, 0.0, pbytes, st,
-                [&] { return launch_perm_gather(D, B_dev, ldb, nrhs, y, st); }));
+                [&] { return launch_perm_gather(D, B_dev, ldb, nrhs, w.y, st); }));
   auto step = [&](const Launch& l) {
     // solve flops/bytes were counted for one right-hand side; L is read once
     const double fl = l.flops * double(nrhs);
     const double by = l.bytes;
-    return timed(num, l.kind + 2, fl, by, st,
-                 [&] { return launch_solve_step(D, num->L, l.kind, l.off, l.ntasks, y, nrhs, st); });
+    return timed(num, l.kind == K_FWD ? SPCHOL_KERNEL_FWD : SPCHOL_KERNEL_BWD, fl, by, st, [&] {
+      return launch_solve_step(D, num->L, num->winv, l.kind, l.off, l.ntasks, w.y, w.x, w.acc, nrhs, st);
+    });
   };
   for (const Launch& l : S.fwd_plan) HIP_TRY(step(l));
   for (const Launch& l : S.bwd_plan) HIP_TRY(step(l));
   HIP_TRY(timed(num, SPCHOL_KERNEL_PERM, 0.0, pbytes, st,
-                [&] { return launch_perm_scatter(D, y, nrhs, B_dev, ldb, st); }));
+                [&] { return launch_perm_scatter(D, w.x, nrhs, B_dev, ldb, st); }));
   return SPCHOL_OK;
 }
 
@@ -470,7 +510,7 @@ spchol_status spchol_factor_prec(spchol_sym sym, const double* vals_dev, int32_t
   if (e == hipSuccess) e = hipMalloc((void**)&N->status, sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMalloc((void**)&N->red, (size_t)(logdet_partials(sym->S.n) + 1) * sizeof(double));
   if (e == hipSuccess)
-    e = hipMalloc((void**)&N->scratch, (size_t)(sym->S.max_slots > 0 ? sym->S.max_slots : 1) * 64 * 64 * sizeof(double));
+    e = hipMalloc((void**)&N->winv, (size_t)(sym->S.wbase[sym->S.ns] > 0 ? sym->S.wbase[sym->S.ns] : 1) * sizeof(double));
   if (e != hipSuccess) {
     delete N;
     return fail(e == hipErrorOutOfMemory ? SPCHOL_ERR_OOM : SPCHOL_ERR_HIP,
@@ -506,14 +546,8 @@ spchol_status spchol_solve(spchol_num num, double* B_dev, int64_t nrhs, int64_t 
   if (nrhs == 0 || S.n == 0) return SPCHOL_OK;
   if (!B_dev) return fail(SPCHOL_ERR_ARG, "null right-hand side");
   hipStream_t st = (hipStream_t)stream;
-  if (num->ycap < S.n * nrhs) {
-    if (num->y) HIP_TRY(hipFree(num->y));
-    num->y = nullptr;
-    num->ycap = 0;
-    HIP_TRY(hipMalloc((void**)&num->y, (size_t)(S.n * nrhs) * sizeof(double)));
-    num->ycap = S.n * nrhs;
-  }
-  return enqueue_solve(num, num->y, B_dev, nrhs, ldb, st);
+  HIP_TRY(num->sw.ensure(S.n, nrhs));
+  return enqueue_solve(num, num->sw, B_dev, nrhs, ldb, st);
 }
 
 spchol_status spchol_refine(spchol_num num, const double* vals_dev, const double* B_dev, double* X_dev,
@@ -699,11 +733,10 @@ spchol_status spchol_info(spchol_num num, int64_t* info, void* stream) {
 struct spchol_graph_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  double* y = nullptr;  // the captured solve's own work vector
+  SolveWork sw;  // the captured solve's own work vectors
   ~spchol_graph_s() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    if (y) (void)hipFree(y);
   }
 };
 
@@ -721,10 +754,10 @@ spchol_status spchol_graph_create(spchol_num num, const double* vals_dev, double
   // buffers the captured work uses must exist before the capture; the graph
   // owns its solve vector so that later eager solves cannot move it
   if (nrhs > 0 && S.n > 0) {
-    hipError_t ea = hipMalloc((void**)&G->y, (size_t)(S.n * nrhs) * sizeof(double));
+    hipError_t ea = G->sw.ensure(S.n, nrhs);
     if (ea != hipSuccess) {
       delete G;
-      return fail(SPCHOL_ERR_OOM, std::string("graph work vector: ") + hipGetErrorString(ea));
+      return fail(SPCHOL_ERR_OOM, std::string("graph work vectors: ") + hipGetErrorString(ea));
     }
   }
   const bool prof = num->prof.on;
@@ -733,7 +766,7 @@ spchol_status spchol_graph_create(spchol_num num, const double* vals_dev, double
   spchol_status s = SPCHOL_OK;
   if (e == hipSuccess) {
     s = enqueue_factor(num, vals_dev, st);
-    if (!s && nrhs > 0 && S.n > 0) s = enqueue_solve(num, G->y, B_dev, nrhs, ldb, st);
+    if (!s && nrhs > 0 && S.n > 0) s = enqueue_solve(num, G->sw, B_dev, nrhs, ldb, st);
     hipError_t e2 = hipStreamEndCapture(st, &G->graph);
     if (!s && e2 != hipSuccess) e = e2;
   }

@@ -1,0 +1,277 @@
+// Host checker of the launch schedules built by the symbolic analysis.
+//
+// Reads a pattern (text: n nnz, colptr, rowind, perm) and the options from
+// the command line, runs the analysis and replays the factorization, forward
+// and backward plans at the granularity of single entries:
+//   * every entry of L receives exactly the update contributions the
+//     right-looking method defines (one per earlier panel of its own
+//     supernode, one per pair of off-diagonal rows of each descendant whose
+//     target it is, Sec. II-A), counted independently by brute force;
+//   * an entry is read by a panel factorization / triangular solve only
+//     once all its contributions are in, and an update reads only solved
+//     columns;
+//   * inside one launch no entry is written by two tasks (unless both are
+//     atomic adds) or written by one task and read by another;
+//   * the solves read each panel's right-hand side only when complete and
+//     never race on x.
+// Prints "ok" and exits 0, or prints the first violation and exits 1.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
+#include <vector>
+
+#include "../paper_2409_14009_amd/csrc/analyze.hpp"
+
+using namespace spchol;
+
+namespace {
+
+struct Access {
+  // per entry: launch and task of the last writer / reader seen
+  std::vector<int64_t> wl, rl;
+  std::vector<int32_t> wt, rt;
+  std::vector<char> wa;
+  explicit Access(int64_t n) : wl(n, -1), rl(n, -1), wt(n, -1), rt(n, -1), wa(n, 0) {}
+};
+
+int64_t g_launch = 0;
+std::string g_err;
+
+bool fail(const std::string& m) {
+  if (g_err.empty()) g_err = m;
+  return false;
+}
+
+bool on_read(Access& A, int64_t e, int32_t task) {
+  if (A.wl[e] == g_launch && A.wt[e] != task) return fail("read of an entry another task of the launch writes");
+  if (A.rl[e] == g_launch && A.rt[e] != task) A.rt[e] = -2;
+  else if (A.rl[e] != g_launch) { A.rl[e] = g_launch; A.rt[e] = task; }
+  return true;
+}
+
+bool on_write(Access& A, int64_t e, int32_t task, bool atomic) {
+  if (A.rl[e] == g_launch && A.rt[e] != task) return fail("write of an entry another task of the launch reads");
+  if (A.wl[e] == g_launch && A.wt[e] != task && !(atomic && A.wa[e])) return fail("two writers in one launch");
+  A.wl[e] = g_launch; A.wt[e] = task; A.wa[e] = atomic;
+  return true;
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  if (argc < 5) {
+    std::fprintf(stderr, "usage: plan_check pattern.txt snode_mode amalg_z panel_width\n");
+    return 2;
+  }
+  FILE* f = std::fopen(argv[1], "r");
+  if (!f) return 2;
+  long long n, nz;
+  if (std::fscanf(f, "%lld %lld", &n, &nz) != 2) return 2;
+  std::vector<int64_t> cp(n + 1), ri(nz), pm(n);
+  for (auto& v : cp) { long long x; if (std::fscanf(f, "%lld", &x) != 1) return 2; v = x; }
+  for (auto& v : ri) { long long x; if (std::fscanf(f, "%lld", &x) != 1) return 2; v = x; }
+  for (auto& v : pm) { long long x; if (std::fscanf(f, "%lld", &x) != 1) return 2; v = x; }
+  std::fclose(f);
+  Symbolic S;
+  std::string err;
+  if (analyze(n, cp.data(), ri.data(), pm.data(), std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]), S,
+              err)) {
+    std::printf("analyze failed: %s\n", err.c_str());
+    return 1;
+  }
+  const int64_t ns = S.ns, nb = S.nb, storage = S.loff[ns];
+  auto K = [&](int64_t J) { return S.sptr[J + 1] - S.sptr[J]; };
+  auto M = [&](int64_t J) { return S.rptr[J + 1] - S.rptr[J]; };
+  auto pos_in = [&](int64_t P, int64_t row) {
+    const int32_t* b = S.rows.data() + S.rptr[P];
+    const int32_t* e = S.rows.data() + S.rptr[P + 1];
+    const int32_t* it = std::lower_bound(b, e, (int32_t)row);
+    return (it != e && *it == row) ? (int64_t)(it - b) : (int64_t)-1;
+  };
+  auto idx = [&](int64_t J, int64_t c, int64_t r) { return S.loff[J] + c * M(J) + r; };
+  // external target of the pair (row a, row b) of J's row list, a <= b
+  auto target = [&](int64_t J, int64_t a, int64_t b) -> int64_t {
+    const int64_t ga = S.rows[S.rptr[J] + a], gb = S.rows[S.rptr[J] + b];
+    const int64_t P = S.snode_of[ga];
+    const int64_t q = pos_in(P, gb);
+    if (q < 0) return -1;
+    return idx(P, ga - S.sptr[P], q);
+  };
+
+  // expected contributions per entry (brute force over the definition)
+  std::vector<int32_t> expect(storage, 0), got(storage, 0);
+  std::vector<char> solved(storage, 0);
+  for (int64_t J = 0; J < ns; ++J) {
+    const int64_t k = K(J), m = M(J);
+    for (int64_t c = 0; c < k; ++c)
+      for (int64_t r = c; r < m; ++r) expect[idx(J, c, r)] += (int32_t)(c / nb);
+    for (int64_t a = k; a < m; ++a)
+      for (int64_t b = a; b < m; ++b) {
+        const int64_t e = target(J, a, b);
+        if (e < 0) { std::printf("row of a descendant missing in its ancestor\n"); return 1; }
+        expect[e] += 1;
+      }
+  }
+
+  Access acc(storage);
+  auto need_complete = [&](int64_t e, int32_t t) {
+    if (got[e] != expect[e]) return fail("entry factored before all its updates arrived");
+    return on_read(acc, e, t);
+  };
+  auto solve_entry = [&](int64_t e, int32_t t) {
+    if (solved[e]) return fail("entry solved twice");
+    solved[e] = 1;
+    return on_write(acc, e, t, false);
+  };
+  auto need_solved = [&](int64_t e, int32_t t) {
+    if (!solved[e]) return fail("update reads a column that is not solved yet");
+    return on_read(acc, e, t);
+  };
+
+  bool ok = true;
+  for (const Launch& L : S.factor_plan) {
+    ++g_launch;
+    for (int32_t q = 0; q < L.ntasks && ok; ++q) {
+      const Task& t = S.tasks[L.off + q];
+      int32_t kind = L.kind;
+      if (kind == K_FACTOR_LA) kind = q < L.nfirst ? K_FACTOR : K_UPD_INT;
+      const int64_t J = t.J, k = K(J), m = M(J);
+      if (kind == K_FACTOR || kind == K_TRSM) {
+        const int64_t c0 = int64_t(t.a) * nb, kp = std::min<int64_t>(nb, k - c0);
+        if (kind == K_FACTOR) {
+          for (int64_t c = c0; c < c0 + kp && ok; ++c)
+            for (int64_t r = c; r < c0 + kp && ok; ++r) ok = need_complete(idx(J, c, r), q) && solve_entry(idx(J, c, r), q);
+          const int64_t re = std::min<int64_t>(int64_t(t.b) + kTrsmRows, m);
+          for (int64_t c = c0; c < c0 + kp && ok; ++c)
+            for (int64_t r = t.b; r < re && ok; ++r) ok = need_complete(idx(J, c, r), q) && solve_entry(idx(J, c, r), q);
+        } else {
+          for (int64_t c = c0; c < c0 + kp && ok; ++c)
+            for (int64_t r = c; r < c0 + kp && ok; ++r) ok = need_solved(idx(J, c, r), q);
+          const int64_t re = std::min<int64_t>(int64_t(t.b) + kTile, m);
+          for (int64_t c = c0; c < c0 + kp && ok; ++c)
+            for (int64_t r = t.b; r < re && ok; ++r) ok = need_complete(idx(J, c, r), q) && solve_entry(idx(J, c, r), q);
+        }
+      } else if (kind == K_UPD_INT || kind == K_UPD_EXT) {
+        const bool ext = kind == K_UPD_EXT;
+        const int64_t kb = ext ? 0 : int64_t(t.c) * nb, ke = ext ? k : std::min<int64_t>(k, kb + nb);
+        const int64_t colEnd = ext ? m : k;
+        const int64_t r1 = std::min<int64_t>(int64_t(t.a) + kTile, m), c1 = std::min<int64_t>(int64_t(t.b) + kTile, colEnd);
+        for (int64_t c = t.b; c < c1 && ok; ++c)
+          for (int64_t r = std::max<int64_t>(t.a, c); r < r1 && ok; ++r) {
+            for (int64_t s = kb; s < ke && ok; ++s) ok = need_solved(idx(J, s, r), q) && need_solved(idx(J, s, c), q);
+            if (!ok) break;
+            const int64_t e = ext ? target(J, c, r) : idx(J, c, r);
+            ok = on_write(acc, e, q, ext);
+            if (ok && solved[e]) ok = fail("update of an entry that is already solved");
+            got[e] += 1;
+          }
+      } else {
+        ok = fail("unknown launch kind in the factorization plan");
+      }
+    }
+    if (!ok) break;
+  }
+  if (ok)
+    for (int64_t e = 0; e < storage && ok; ++e)
+      if (got[e] != expect[e]) ok = fail("an entry did not receive all its updates");
+  for (int64_t J = 0; J < ns && ok; ++J)
+    for (int64_t c = 0; c < K(J) && ok; ++c)
+      for (int64_t r = c; r < M(J) && ok; ++r)
+        if (!solved[idx(J, c, r)]) ok = fail("an entry of L was never solved");
+
+  // forward: y[row] receives one contribution per panel whose rows below
+  // contain it; a panel reads its own rows of y only when complete
+  if (ok) {
+    const int64_t N = S.n;
+    std::vector<int32_t> ye(N, 0), yg(N, 0);
+    std::vector<char> xdone(N, 0);
+    for (int64_t J = 0; J < ns; ++J)
+      for (int64_t p = 0; p * nb < K(J); ++p) {
+        const int64_t below = p * nb + std::min<int64_t>(nb, K(J) - p * nb);
+        for (int64_t r = below; r < M(J); ++r) ye[S.rows[S.rptr[J] + r]] += 1;
+      }
+    Access ya(N), xa(N);
+    for (const Launch& L : S.fwd_plan) {
+      ++g_launch;
+      for (int32_t q = 0; q < L.ntasks && ok; ++q) {
+        const Task& t = S.tasks[L.off + q];
+        const int64_t J = t.J, c0 = int64_t(t.a) * nb, kp = std::min<int64_t>(nb, K(J) - c0);
+        const int64_t f0 = S.sptr[J] + c0;
+        for (int64_t i = 0; i < kp && ok; ++i) {
+          if (yg[f0 + i] != ye[f0 + i]) ok = fail("forward solve reads an incomplete right-hand side");
+          else ok = on_read(ya, f0 + i, q);
+          if (ok && t.c == 1) {
+            if (xdone[f0 + i]) ok = fail("forward solution written twice");
+            xdone[f0 + i] = 1;
+            ok = ok && on_write(xa, f0 + i, q, false);
+          }
+        }
+        if (t.b >= 0)
+          for (int64_t r = t.b; r < std::min<int64_t>(int64_t(t.b) + kTile, M(J)) && ok; ++r) {
+            const int64_t g = S.rows[S.rptr[J] + r];
+            ok = on_write(ya, g, q, r >= K(J));
+            yg[g] += 1;
+          }
+      }
+      if (!ok) break;
+    }
+    for (int64_t i = 0; i < N && ok; ++i)
+      if (!xdone[i] || yg[i] != ye[i]) ok = fail("forward solve incomplete");
+    // backward: a panel is done by its single task (c = -1) or, when split
+    // into row tiles (c = 0), by its finishing task of the next launch once
+    // every tile ran; tasks read x below the panel, which must be done, and
+    // not in the same launch
+    std::vector<char> bdone(N, 0);
+    std::vector<int64_t> fin_launch(N, -1), tiles_seen(N, 0), tiles_need(N, 0);
+    for (int64_t J = 0; J < ns; ++J)
+      for (int64_t p = 0; p * nb < K(J); ++p) {
+        const int64_t below = p * nb + std::min<int64_t>(nb, K(J) - p * nb);
+        tiles_need[S.sptr[J] + p * nb] = (M(J) - below + kTile - 1) / kTile;
+      }
+    for (const Launch& L : S.bwd_plan) {
+      ++g_launch;
+      for (int32_t q = 0; q < L.ntasks && ok; ++q) {
+        const Task& t = S.tasks[L.off + q];
+        const int64_t J = t.J, c0 = int64_t(t.a) * nb, kp = std::min<int64_t>(nb, K(J) - c0);
+        const int64_t f0 = S.sptr[J] + c0, below = c0 + kp;
+        auto finish = [&]() {
+          for (int64_t i = 0; i < kp && ok; ++i) {
+            if (bdone[f0 + i]) ok = fail("backward solution written twice");
+            bdone[f0 + i] = 1;
+            fin_launch[f0 + i] = g_launch;
+          }
+        };
+        auto read_rows = [&](int64_t r0, int64_t r1) {
+          for (int64_t r = r0; r < r1 && ok; ++r) {
+            const int64_t g = S.rows[S.rptr[J] + r];
+            if (!bdone[g]) ok = fail("backward solve reads a row that is not solved");
+            else if (fin_launch[g] == g_launch) ok = fail("backward solve reads a row solved in the same launch");
+          }
+        };
+        if (L.kind == K_BWD && t.c < 0) {
+          if (t.b != below) ok = fail("whole-panel task does not start below the panel");
+          read_rows(t.b, M(J));
+          finish();
+        } else if (L.kind == K_BWD) {
+          read_rows(t.b, std::min<int64_t>(int64_t(t.b) + kTile, M(J)));
+          tiles_seen[f0] += 1;
+        } else if (L.kind == K_BWD_FIN) {
+          if (tiles_seen[f0] != tiles_need[f0]) ok = fail("panel finished before all its row tiles");
+          finish();
+        } else {
+          ok = fail("unknown launch kind in the backward plan");
+        }
+      }
+      if (!ok) break;
+    }
+    for (int64_t i = 0; i < N && ok; ++i)
+      if (!bdone[i]) ok = fail("backward solve incomplete");
+  }
+  if (!ok) {
+    std::printf("violation (launch %lld): %s\n", (long long)g_launch, g_err.c_str());
+    return 1;
+  }
+  std::printf("ok launches=%zu+%zu+%zu\n", S.factor_plan.size(), S.fwd_plan.size(), S.bwd_plan.size());
+  return 0;
+}

@@ -1,0 +1,84 @@
+"""The launch schedules of the symbolic analysis, replayed entry by entry on
+the host (tests/plan_check.cpp): every entry of L gets exactly the update
+contributions the right-looking method defines before it is factored, no
+two tasks of one launch conflict, and the solve rounds respect their
+dependencies.  Covers the one-panel lookahead, the inline / row-tile split
+of the panel solve, every panel width and amalgamation."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import gen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def checker(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("plan") / "plan_check")
+    src = [os.path.join(ROOT, "tests", "plan_check.cpp"),
+           os.path.join(ROOT, "paper_2409_14009_amd", "csrc", "analyze.cpp")]
+    subprocess.run(["g++", "-O2", "-std=c++17", *src, "-o", exe], check=True)
+    return exe
+
+
+def _run(checker, tmp_path, n, cp, ri, perm, mode, z, nb):
+    f = tmp_path / "pat.txt"
+    perm = np.arange(n) if perm is None else perm
+    with open(f, "w") as fh:
+        fh.write(f"{n} {len(ri)}\n")
+        fh.write(" ".join(map(str, cp)) + "\n")
+        fh.write(" ".join(map(str, ri)) + "\n")
+        fh.write(" ".join(map(str, perm)) + "\n")
+    r = subprocess.run([checker, str(f), str(mode), str(z), str(nb)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    return r.stdout
+
+
+@pytest.mark.parametrize("nb", [16, 32, 48, 64])
+def test_grid2d(checker, tmp_path, nb):
+    p = gen.make_config(0)
+    _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, 0, nb)
+
+
+@pytest.mark.parametrize("side,z,nb", [(10, 8, 64), (12, 8, 32), (9, 0, 48), (11, 30, 16)])
+def test_grid3d(checker, tmp_path, side, z, nb):
+    p = gen.make_config(1, side=side)
+    _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, z, nb)
+
+
+def test_elasticity(checker, tmp_path):
+    p = gen.make_config(2, side=5)
+    _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, 8, 16)
+
+
+@pytest.mark.parametrize("n,nb", [(150, 64), (150, 16), (65, 64), (1, 64)])
+def test_dense(checker, tmp_path, n, nb):
+    cp = np.concatenate([[0], np.cumsum(np.arange(n, 0, -1))]).astype(np.int64)
+    ri = np.concatenate([np.arange(j, n) for j in range(n)]).astype(np.int64)
+    _run(checker, tmp_path, n, cp, ri, None, 0, 0, nb)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_random_patterns(checker, tmp_path, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(60, 300))
+    n2, cp, ri, vv = gen.random_spd(n, rng.uniform(0.01, 0.08), rng)
+    _run(checker, tmp_path, n2, cp, ri, rng.permutation(n2), int(rng.integers(0, 2)), int(rng.integers(0, 20)),
+         int(rng.choice([16, 32, 48, 64])))
+
+
+def test_batch_union(checker, tmp_path):
+    probs = gen.make_batch(count=6, nrhs=1)
+    # block-diagonal union, as the batch analysis forms it
+    cps, ris, pms, off, nzoff = [], [], [], 0, 0
+    for p in probs:
+        cps.append(p.colptr[:-1] + nzoff)
+        ris.append(p.rowind + off)
+        pms.append(p.perm + off)
+        off += p.n
+        nzoff += p.nnz
+    cp = np.concatenate(cps + [[nzoff]]).astype(np.int64)
+    _run(checker, tmp_path, off, cp, np.concatenate(ris), np.concatenate(pms), 0, 8, 64)
