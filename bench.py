@@ -13,8 +13,9 @@ value = algorithmic factorization flops (sum_j c_j^2 over the true column
 counts) / mean factorization time, HIP events on the stream the kernels run
 on.  The same JSON line carries, measured in the same run:
   mixed_ir  - 3D 27-point 3-dof 40^3, 8 RHS: fp64 factor+solve against
-              fp32-update factor + solve + iterative refinement to a
-              normwise backward error <= 1e-12 (per-RHS errors reported);
+              fp32- and bf16-update factor + solve + iterative refinement
+              to a normwise backward error <= 1e-12 (per-RHS errors and
+              whether refinement converged within 10 iterations);
   fwd_bwd   - 3D 48^3 random-field workload: forward (factor + solve +
               logdet) and reverse (selected inversion + gradient) times;
   batch     - 512 independent grids, factor + 4-RHS solve as one hipGraph.
@@ -39,6 +40,13 @@ METRIC = "factor GFLOP/s, FP64 vs mixed+IR at backward err <=1e-12; fwd+bwd time
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel from the hardware counters
+# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, scales from a plain 1 GiB copy;
+# profiles/update_ext_grid3d_64.md), valid for the kernel source they were
+# taken with: reported only while the source hash matches.
+MEASURED_TRAFFIC = {"kernel": "update_ext", "bytes_per_launch": 785753751,
+                    "kernels_sha256_16": "f5c5946c85672fac"}
+
 
 def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
@@ -61,6 +69,18 @@ def cpu_baseline(p, z, ncols=32768):
                 sample=f"left-looking factorization of the first {t} columns (a complete ND subtree, "
                        f"{fl:.3e} of {s.flops():.3e} algorithmic flops) of the same matrix and ordering, "
                        f"{dt:.1f} s on 1 thread")
+
+
+def measured_traffic(kernel):
+    """Counter-measured HBM bytes per launch of `kernel`, or None when the
+    kernels changed since the counters were taken."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2409_14009_amd", "csrc", "kernels.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    t = MEASURED_TRAFFIC
+    if kernel != t["kernel"] or sha != t["kernels_sha256_16"]:
+        return None
+    return t["bytes_per_launch"]
 
 
 def _timed_steps(steps, stream, phases):
@@ -141,6 +161,7 @@ def headline(args, dev):
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=achieved / PEAK_HBM_GBS, traffic=None)
+    roof["traffic"] = measured_traffic(dom)
     roof.update(kernel=dom, launches_per_step=d["launches"] / args.steps,
                 avg_launch_us=d["ms"] * 1e3 / max(d["launches"], 1),
                 flops_per_step=d["flops"] / args.steps, bytes_per_step=d["bytes"] / args.steps)
@@ -189,12 +210,12 @@ def mixed_ir(args, dev):
     out = dict(workload=p.meta["doc"], n=p.n, nrhs=int(p.B.shape[1]), flops_alg=info["flops_alg"],
                fp64=dict(factor_ms=t64["factor"], factor_solve_ms=t64["factor"] + t64["solve"],
                          gflops=info["flops_alg"] / t64["factor"] * 1e-6, berr=eta64))
-    for prec in ("f32",):
+    for prec in ("f32", "bf16"):
         Fm = S.factor(vals, precision=prec)
         it_box = {}
 
         def refine():
-            berr, it = Fm.refine_(vals, Bt, Xt, tol=1e-12, max_iter=10)
+            berr, it = Fm.refine_(vals, Bt, Xt, tol=1e-12, max_iter=10, check=False)
             it_box["berr"], it_box["it"] = berr, it
 
         for _ in range(args.warmup):
@@ -203,9 +224,11 @@ def mixed_ir(args, dev):
         tm = _timed_steps(steps, stream, [("factor", lambda: Fm.refactor(vals, precision=prec)),
                                           ("solve_ir", refine)])
         total = tm["factor"] + tm["solve_ir"]
+        ok = bool(max(it_box["berr"]) <= 1e-12)
         out[prec + "_ir"] = dict(factor_ms=tm["factor"], solve_ir_ms=tm["solve_ir"], total_ms=total,
                                  gflops=info["flops_alg"] / tm["factor"] * 1e-6, iterations=it_box["it"],
-                                 berr=it_box["berr"], speedup_vs_fp64=out["fp64"]["factor_solve_ms"] / total)
+                                 converged=ok, berr=it_box["berr"],
+                                 speedup_vs_fp64=out["fp64"]["factor_solve_ms"] / total if ok else None)
         del Fm
     return out
 

@@ -170,11 +170,11 @@ spchol_status spchol_refactor(spchol_num num, const double *vals_dev, void *stre
 
 /* Precision of the update products (SYRK/GEMM of the panels, Sec. II-A).
  * The diagonal-block Cholesky, the triangular solves and the factor storage
- * stay fp64 in every mode; F32 rounds the update operands to fp32 and
- * accumulates in fp32 on the matrix cores, then adds the result into the
- * fp64 factor.  The factor is then that of a nearby matrix: pair it with
- * spchol_refine to recover fp64 accuracy. */
-enum { SPCHOL_UPD_F64 = 0, SPCHOL_UPD_F32 = 1 };
+ * stay fp64 in every mode; F32 (BF16) rounds the update operands to fp32
+ * (bf16, round to nearest even) and accumulates in fp32 on the matrix
+ * cores, then adds the result into the fp64 factor.  The factor is then that
+ * of a nearby matrix: pair it with spchol_refine to recover fp64 accuracy. */
+enum { SPCHOL_UPD_F64 = 0, SPCHOL_UPD_F32 = 1, SPCHOL_UPD_BF16 = 2 };
 
 /* spchol_factor / spchol_refactor with an update precision (SPCHOL_UPD_*);
  * SPCHOL_ERR_ARG for an unsupported value. */

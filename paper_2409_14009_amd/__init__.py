@@ -71,7 +71,7 @@ def _dev_f64(t, what):
     return C.c_void_p(t.data_ptr())
 
 
-PRECISIONS = {"f64": 0, "f32": 1}
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
 
 
 def _precision(p):
@@ -148,8 +148,8 @@ class SparseCholesky:
 
     def factor(self, vals, stream=None, check=True, precision="f64") -> "Factor":
         """Numeric factorization of the values `vals` (float64 CUDA tensor in
-        the pattern's entry order).  precision: "f64" or "f32" for the update
-        products (the diagonal-block Cholesky and the solves stay fp64).
+        the pattern's entry order).  precision: "f64", "f32" or "bf16" for the
+        update products (the diagonal-block Cholesky and the solves stay fp64).
         Raises NotPositiveDefinite (with .info, the 1-based permuted column)
         when check is set."""
         if vals.numel() != self.nnz_a:

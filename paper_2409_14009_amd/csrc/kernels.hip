@@ -382,8 +382,9 @@ __global__ __launch_bounds__(256) void k_panel_rows(DevSym S, double* __restrict
 //                      through the relative indices; atomic adds because
 //                      several supernodes of a level may hit one ancestor.
 // Precision P: 0 = fp64 operands and accumulation; 1 = operands rounded to
-// fp32 while staging into LDS, fp32 accumulation (the mixed-precision
-// form); the scatter is always fp64.
+// fp32 while staging into LDS, fp32 accumulation; 2 = operands rounded to
+// bf16, fp32 accumulation on the 16x16x16 bf16 MFMA (the mixed-precision
+// forms); the scatter is always fp64.
 // MFMA operand layout (one wavefront, 16x16x4, checked on gfx950): lane l
 // supplies A[l % 16][l / 16] and B[l / 16][l % 16]; fp64 accumulator
 // element v holds D[4 v + l / 16][l % 16], fp32 element v holds
@@ -411,24 +412,42 @@ template <> struct UpdPrec<1> {
   }
   static __device__ __forceinline__ int row(int v, int lk) { return 4 * lk + v; }
 };
+// bf16 operands, fp32 accumulation: one 16x16x16 MFMA per K chunk of 16;
+// staged row-major, four consecutive k of a row packed in 8 bytes
+typedef short s4 __attribute__((ext_vector_type(4)));
+template <> struct UpdPrec<2> {
+  using T = s4;
+  using Acc = f4;
+  static __device__ __forceinline__ Acc zero() { return f4{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ int row(int v, int lk) { return 4 * lk + v; }
+};
+
+// fp64 -> bf16, round to nearest even (through fp32; finite inputs)
+__device__ __forceinline__ unsigned short to_bf16(double x) {
+  unsigned u = __float_as_uint((float)x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
 
 constexpr int ALD = TILE + 2;
+constexpr int G2 = 5;  // bf16 staging: 8-byte groups per row (4 used, 1 pad)
 constexpr int CLD = TILE + 1;  // column stride of the epilogue tile
 
 constexpr int UPD_SMEM = TILE * CLD + 2 * KC * ALD;  // doubles: Cs, then As and Bs (T each)
+static_assert(TILE * G2 * sizeof(s4) <= KC * ALD * sizeof(double), "bf16 staging fits the operand area");
 
-template <int P>
-__device__ __forceinline__ void update_body(const DevSym& S, double* __restrict__ L, int32_t kind, const DevTask t,
+template <int P, int kind>
+__device__ __forceinline__ void update_body(const DevSym& S, double* __restrict__ L, const DevTask t,
                                             double* __restrict__ smem) {
   using Pr = UpdPrec<P>;
   using T = typename Pr::T;
   double* __restrict__ Cs = smem;
   T* __restrict__ As = reinterpret_cast<T*>(smem + TILE * CLD);
-  T* __restrict__ Bs = As + KC * ALD;
+  T* __restrict__ Bs = reinterpret_cast<T*>(smem + TILE * CLD + KC * ALD);
   const int J = t.J, row0 = t.a, col0 = t.b;
   const int m = S.sm[J], k = S.sk[J];
   int kb, ke, colEnd;
-  if (kind == 1) {
+  if constexpr (kind == 1) {
     kb = t.c * S.nb;
     ke = min(k, kb + S.nb);
     colEnd = k;
@@ -448,6 +467,7 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
     for (int j = 0; j < 2; ++j) acc[i][j] = Pr::zero();
 
   // staging: thread loads rows (tid & 63) of chunk columns (tid >> 6) + 4q
+  // (bf16: columns 4 (tid >> 6) + q, packed into one 8-byte group)
   const int sr = tid & 63, sc = tid >> 6;
   const bool va = row0 + sr < m, vb = col0 + sr < colEnd;
   const double* pa = Lj + row0 + sr;
@@ -456,12 +476,28 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
   auto fetch = [&](int kk) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int gc = kk + sc + 4 * q;
+      const int gc = P == 2 ? kk + 4 * sc + q : kk + sc + 4 * q;
       ra[q] = (va && gc < ke) ? pa[(int64_t)gc * m] : 0.0;
       rb[q] = (vb && gc < ke) ? pb[(int64_t)gc * m] : 0.0;
     }
   };
   fetch(kb);
+  if constexpr (P == 2) {
+    for (int kk = kb; kk < ke; kk += KC) {
+      As[sr * G2 + sc] = s4{(short)to_bf16(ra[0]), (short)to_bf16(ra[1]), (short)to_bf16(ra[2]), (short)to_bf16(ra[3])};
+      Bs[sr * G2 + sc] = s4{(short)to_bf16(rb[0]), (short)to_bf16(rb[1]), (short)to_bf16(rb[2]), (short)to_bf16(rb[3])};
+      __syncthreads();
+      if (kk + KC < ke) fetch(kk + KC);
+      // lane (li, lk): A[row li][k = 4 lk .. 4 lk + 3], B likewise
+      const s4 a0 = As[(wr + li) * G2 + lk], a1 = As[(wr + 16 + li) * G2 + lk];
+      const s4 b0 = Bs[(wc + li) * G2 + lk], b1 = Bs[(wc + 16 + li) * G2 + lk];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][1], 0, 0, 0);
+      __syncthreads();
+    }
+  } else
   for (int kk = kb; kk < ke; kk += KC) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -497,29 +533,44 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
   __syncthreads();
   const int gr = row0 + lane;
   const int cmax = min(TILE, colEnd - col0);
-  if (kind == 1) {
+  if constexpr (kind == 1) {
     for (int cc = w; cc < cmax; cc += 4) {
       const int gc = col0 + cc;
       if (gr < m && gr >= gc) Lj[(int64_t)gc * m + gr] -= Cs[cc * CLD + lane];
     }
   } else {
+    // target of entry (gr, gc): the ancestor column of row gc at storage
+    // offset ocbase, row position tpos[relptr[pair] + gr - k - pa0[pair]]
+    // with pair = (J, ancestor).  Lane l fetches the column data of tile
+    // column l up front; the row positions depend only on the pair, which
+    // consecutive columns share, so they are reloaded only when it changes.
     const int64_t ob = S.obase[J];
     const bool rowok = gr < m;
+    const int lc = min(col0 + lane, colEnd - 1) - k;
+    const int pair_l = S.opair[ob + lc];
+    const int64_t cbase_l = S.ocbase[ob + lc];
+    int cur = -1, tpv = 0;
     for (int cc = w; cc < cmax; cc += 4) {
       const int gc = col0 + cc;
-      const int b = gc - k;
-      const int pair = S.opair[ob + b];
-      const int64_t cbase = S.ocbase[ob + b];
-      const int32_t* __restrict__ tp = S.tpos + S.relptr[pair] - S.pa0[pair] - k;
-      if (rowok && gr >= gc) atomicAdd(L + cbase + tp[gr], -Cs[cc * CLD + lane]);
+      const int pair = __builtin_amdgcn_readlane(pair_l, cc);
+      const int64_t cbase = ((int64_t)__builtin_amdgcn_readlane((int)(cbase_l >> 32), cc) << 32) |
+                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)cbase_l, cc);
+      if (pair != cur) {
+        cur = pair;
+        const int a0 = S.pa0[pair];
+        const int64_t base = S.relptr[pair] - a0 - k;
+        tpv = (rowok && gr - k >= a0) ? S.tpos[base + gr] : 0;
+      }
+      if (rowok && gr >= gc) atomicAdd(L + cbase + tpv, -Cs[cc * CLD + lane]);
     }
   }
 }
 
-template <int P>
-__global__ __launch_bounds__(256) void k_update(DevSym S, double* __restrict__ L, int32_t kind, int64_t off) {
+// kind 1: internal update tiles, kind 2: external (scattered) update tiles
+template <int P, int kind>
+__global__ __launch_bounds__(256) void k_update(DevSym S, double* __restrict__ L, int64_t off) {
   __shared__ __attribute__((aligned(16))) double smem[UPD_SMEM];
-  update_body<P>(S, L, kind, S.tasks[off + blockIdx.x], smem);
+  update_body<P, kind>(S, L, S.tasks[off + blockIdx.x], smem);
 }
 
 // One-panel lookahead: workgroups below nfirst factor panel p (panel_body),
@@ -532,7 +583,7 @@ __global__ __launch_bounds__(256) void k_panel_la(DevSym S, double* __restrict__
   __shared__ __attribute__((aligned(16))) double smem[PANEL_SMEM > UPD_SMEM ? PANEL_SMEM : UPD_SMEM];
   const DevTask t = S.tasks[off + blockIdx.x];
   if ((int)blockIdx.x < nfirst) panel_body(S, L, t, status, winv, smem);
-  else update_body<P>(S, L, 1, t, smem);
+  else update_body<P, 1>(S, L, t, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -597,13 +648,19 @@ __global__ __launch_bounds__(256) void k_fwd(DevSym S, const double* __restrict_
       ys[w][lane] = (lane < kp && c < nrhs) ? y[fcol + lane + c * S.n] : 0.0;
     }
     __syncthreads();
+    // 16 independent loads per thread (clamped in bounds, zero past kp)
     double z[4] = {0.0, 0.0, 0.0, 0.0};
-    if (lane < kp)
-      for (int tt = t0; tt < t1; ++tt) {
-        const double wv = W[(int64_t)tt * kp + lane];
+    {
+      const int il = min(lane, kp - 1);
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int tt = t0 + u;
+        const double wv0 = W[(int64_t)min(tt, kp - 1) * kp + il];
+        const double wv = (tt < t1 && lane < kp) ? wv0 : 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) z[q] = fma(wv, ys[q][tt], z[q]);
       }
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) part[w][q][lane] = z[q];
     __syncthreads();
@@ -615,12 +672,17 @@ __global__ __launch_bounds__(256) void k_fwd(DevSym S, const double* __restrict_
     }
     __syncthreads();
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    if (rowok)
-      for (int tt = t0; tt < t1; ++tt) {
-        const double lv = Lj[(int64_t)(c0 + tt) * m + row];
+    {
+      const int rl = rowok ? row : 0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int tt = t0 + u;
+        const double lv0 = Lj[(int64_t)(c0 + min(tt, kp - 1)) * m + rl];
+        const double lv = (tt < t1 && rowok) ? lv0 : 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) a[q] = fma(lv, zs[q][tt], a[q]);
       }
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) part[w][q][lane] = a[q];
     __syncthreads();
@@ -638,13 +700,22 @@ __global__ __launch_bounds__(256) void k_fwd(DevSym S, const double* __restrict_
   }
 }
 
-// x_p <- W_p^T v for the panel's kp entries v in vs (LDS), by the block's
-// first 64 threads; column i of W is contiguous.
-__device__ __forceinline__ double apply_wt(const double* __restrict__ W, int kp, const double* __restrict__ vs,
-                                           int i) {
-  const double* __restrict__ Wi = W + (int64_t)i * kp;
+// The panel's inverted diagonal block (kp x kp, column-major) into LDS,
+// Ws[c][r] = W_rc, zero past kp; coalesced.
+__device__ __forceinline__ void stage_w(const double* __restrict__ W, int kp, double (*Ws)[NBMAX + 1], int tid,
+                                        int nthr) {
+  for (int idx = tid; idx < NBMAX * NBMAX; idx += nthr) {
+    const int c = idx >> 6, r = idx & 63;
+    Ws[c][r] = (c < kp && r < kp) ? W[c * kp + r] : 0.0;
+  }
+}
+
+// (W^T v)_i = sum_tt W_tt,i v_tt = sum_tt Ws[i][tt] vs[tt] (W lower
+// triangular, zero padded: the full sum is exact)
+__device__ __forceinline__ double apply_wt(double (*Ws)[NBMAX + 1], const double* __restrict__ vs, int i) {
   double z = 0.0;
-  for (int tt = i; tt < kp; ++tt) z = fma(Wi[tt], vs[tt], z);
+#pragma unroll 16
+  for (int tt = 0; tt < NBMAX; ++tt) z = fma(Ws[i][tt], vs[tt], z);
   return z;
 }
 
@@ -704,32 +775,38 @@ __global__ __launch_bounds__(256) void k_bwd(DevSym S, const double* __restrict_
       else if (i < kp && c < nrhs) atomicAdd(acc + fcol + i + c * S.n, v);
     }
     __syncthreads();
-    if (whole && lane < kp && cb + w < nrhs)
-      x[fcol + lane + (cb + w) * S.n] = apply_wt(winv + S.wbase[J] + (int64_t)p * S.nb * S.nb, kp, vs[w], lane);
+    if (whole) {
+      stage_w(winv + S.wbase[J] + (int64_t)p * S.nb * S.nb, kp, Ls, tid, 256);
+      __syncthreads();
+      if (lane < kp && cb + w < nrhs) x[fcol + lane + (cb + w) * S.n] = apply_wt(Ls, vs[w], lane);
+    }
   }
 }
 
 // Backward, second launch of a round: x_p = W_p^T (x_p - acc_p) for the
 // panels split into tiles; acc_p is left at zero for the next solve.
-__global__ __launch_bounds__(64) void k_bwd_fin(DevSym S, const double* __restrict__ winv, int64_t off,
-                                                double* __restrict__ x, double* __restrict__ acc, int64_t nrhs) {
-  __shared__ double vs[NBMAX];
+__global__ __launch_bounds__(256) void k_bwd_fin(DevSym S, const double* __restrict__ winv, int64_t off,
+                                                 double* __restrict__ x, double* __restrict__ acc, int64_t nrhs) {
+  __shared__ double Ws[NBMAX][NBMAX + 1];
+  __shared__ double vs[4][NBMAX];
   const DevTask t = S.tasks[off + blockIdx.x];
   const int J = t.J, p = t.a;
   const int k = S.sk[J];
   const int c0 = p * S.nb, kp = min(S.nb, k - c0);
   const int64_t fcol = S.sfirst[J] + c0;
-  const int lane = threadIdx.x;
-  for (int64_t c = 0; c < nrhs; ++c) {
-    if (lane < kp) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  stage_w(winv + S.wbase[J] + (int64_t)p * S.nb * S.nb, kp, Ws, tid, 256);
+  for (int64_t cb = 0; cb < nrhs; cb += 4) {
+    const int64_t c = cb + w;  // thread (lane, w): entry lane of RHS cb + w
+    if (lane < kp && c < nrhs) {
       double* ap = acc + fcol + lane + c * S.n;
-      vs[lane] = x[fcol + lane + c * S.n] - *ap;
+      vs[w][lane] = x[fcol + lane + c * S.n] - *ap;
       *ap = 0.0;
     } else {
-      vs[lane] = 0.0;
+      vs[w][lane] = 0.0;
     }
     __syncthreads();
-    if (lane < kp) x[fcol + lane + c * S.n] = apply_wt(winv + S.wbase[J] + (int64_t)p * S.nb * S.nb, kp, vs, lane);
+    if (lane < kp && c < nrhs) x[fcol + lane + c * S.n] = apply_wt(Ws, vs[w], lane);
     __syncthreads();
   }
 }
@@ -1097,7 +1174,8 @@ hipError_t launch_factor_panel(const DevSym& S, double* L, int64_t off, int32_t 
 hipError_t launch_factor_la(const DevSym& S, double* L, int64_t off, int32_t nfirst, int32_t ntasks,
                             unsigned long long* status, double* winv, int32_t prec, hipStream_t st) {
   if (ntasks <= 0) return hipSuccess;
-  if (prec == 1) k_panel_la<1><<<ntasks, 256, 0, st>>>(S, L, off, nfirst, status, winv);
+  if (prec == 2) k_panel_la<2><<<ntasks, 256, 0, st>>>(S, L, off, nfirst, status, winv);
+  else if (prec == 1) k_panel_la<1><<<ntasks, 256, 0, st>>>(S, L, off, nfirst, status, winv);
   else k_panel_la<0><<<ntasks, 256, 0, st>>>(S, L, off, nfirst, status, winv);
   return hipGetLastError();
 }
@@ -1105,8 +1183,15 @@ hipError_t launch_factor_la(const DevSym& S, double* L, int64_t off, int32_t nfi
 hipError_t launch_update(const DevSym& S, double* L, int32_t kind, int64_t off, int32_t ntasks,
                          int32_t prec, hipStream_t st) {
   if (ntasks <= 0) return hipSuccess;
-  if (prec == 1) k_update<1><<<ntasks, 256, 0, st>>>(S, L, kind, off);
-  else k_update<0><<<ntasks, 256, 0, st>>>(S, L, kind, off);
+  if (kind == 1) {
+    if (prec == 2) k_update<2, 1><<<ntasks, 256, 0, st>>>(S, L, off);
+    else if (prec == 1) k_update<1, 1><<<ntasks, 256, 0, st>>>(S, L, off);
+    else k_update<0, 1><<<ntasks, 256, 0, st>>>(S, L, off);
+  } else {
+    if (prec == 2) k_update<2, 2><<<ntasks, 256, 0, st>>>(S, L, off);
+    else if (prec == 1) k_update<1, 2><<<ntasks, 256, 0, st>>>(S, L, off);
+    else k_update<0, 2><<<ntasks, 256, 0, st>>>(S, L, off);
+  }
   return hipGetLastError();
 }
 
@@ -1129,7 +1214,7 @@ hipError_t launch_solve_step(const DevSym& S, const double* L, const double* win
   if (ntasks <= 0) return hipSuccess;
   if (kind == 3) k_fwd<<<ntasks, 256, 0, st>>>(S, L, winv, off, y, x, nrhs);
   else if (kind == 4) k_bwd<<<ntasks, 256, 0, st>>>(S, L, winv, off, x, acc, nrhs);
-  else k_bwd_fin<<<ntasks, 64, 0, st>>>(S, winv, off, x, acc, nrhs);
+  else k_bwd_fin<<<ntasks, 256, 0, st>>>(S, winv, off, x, acc, nrhs);
   return hipGetLastError();
 }
 

@@ -495,7 +495,7 @@ spchol_status spchol_factor(spchol_sym sym, const double* vals_dev, void* stream
 spchol_status spchol_factor_prec(spchol_sym sym, const double* vals_dev, int32_t update_precision, void* stream,
                                  spchol_num* out, int64_t* info) {
   if (!sym || !out) return fail(SPCHOL_ERR_ARG, "null argument");
-  if (update_precision != SPCHOL_UPD_F64 && update_precision != SPCHOL_UPD_F32)
+  if (update_precision != SPCHOL_UPD_F64 && update_precision != SPCHOL_UPD_F32 && update_precision != SPCHOL_UPD_BF16)
     return fail(SPCHOL_ERR_ARG, "unsupported update precision");
   if (!vals_dev && sym->S.nnzA > 0) return fail(SPCHOL_ERR_ARG, "null values");
   *out = nullptr;
@@ -529,7 +529,7 @@ spchol_status spchol_refactor(spchol_num num, const double* vals_dev, void* stre
 spchol_status spchol_refactor_prec(spchol_num num, const double* vals_dev, int32_t update_precision, void* stream,
                                    int64_t* info) {
   if (!num) return fail(SPCHOL_ERR_ARG, "null handle");
-  if (update_precision != SPCHOL_UPD_F64 && update_precision != SPCHOL_UPD_F32)
+  if (update_precision != SPCHOL_UPD_F64 && update_precision != SPCHOL_UPD_F32 && update_precision != SPCHOL_UPD_BF16)
     return fail(SPCHOL_ERR_ARG, "unsupported update precision");
   num->prec = update_precision;
   if (!vals_dev && num->sym->S.nnzA > 0) return fail(SPCHOL_ERR_ARG, "null values");

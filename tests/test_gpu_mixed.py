@@ -73,3 +73,48 @@ def test_mixed_solution_matches_oracle():
     X, berr, it = F.refine(vals, torch.tensor(p.B, device="cuda"))
     xo = oracle.Symbolic(p.n, p.colptr, p.rowind, p.perm, 0, 0).factor(p.vals).solve(p.B)
     assert np.abs(X.cpu().numpy() - xo).max() <= 1e-10 * np.abs(xo).max()
+
+
+def _grid_shifted(side, shift, seed):
+    rng = np.random.default_rng(seed)
+    n, cp, ri, vv = gen.grid_laplacian((side, side), rng, "uniform", 0.5, 1.5, shift)
+    perm = gen.nested_dissection((side, side))
+    B = rng.standard_normal((n, 2))
+    return n, cp, ri, vv, perm, B
+
+
+@pytest.mark.parametrize("side,shift", [(24, 1.0), (40, 0.5)])
+def test_bf16_updates_refined_on_well_conditioned(side, shift):
+    """bf16 update operands perturb the factor by ~2^-8 relative; on a
+    matrix with kappa * 2^-8 << 1 refinement still reaches 1e-12."""
+    n, cp, ri, vv, perm, B = _grid_shifted(side, shift, 7)
+    print(f"bf16 case side={side} shift={shift}", flush=True)
+    S = sc.SparseCholesky(n, cp, ri, perm, 0, 0)
+    vals = torch.tensor(vv, device="cuda")
+    F = S.factor(vals, precision="bf16")
+    X, berr, it = F.refine(vals, torch.tensor(B, device="cuda"), tol=1e-12, max_iter=30)
+    A = oracle.full_matrix(n, cp, ri, vv)
+    eta, _ = oracle.backward_error(A, X.cpu().numpy(), B)
+    print(f"  iterations {it} eta {eta.max():.2e}", flush=True)
+    assert eta.max() <= 1e-12 and max(berr) <= 1e-12
+    # bf16 rounding really happened: the factor is further from the fp64
+    # one than the fp32-update factor is
+    L64 = S.factor(vals).storage()
+    d16 = (F.storage() - L64).abs().max().item()
+    d32 = (S.factor(vals, precision="f32").storage() - L64).abs().max().item()
+    assert d16 > 10 * d32 > 0
+    assert it >= 2
+
+
+def test_bf16_update_error_size():
+    """The bf16-update factor is the exact factor of a matrix within about
+    2^-8 (relative, normwise) of A: ||P A P^T - L L^T||_F / ||A||_F sits
+    between 1e-5 and 2e-2."""
+    from gpu_util import permuted_matrix, residual_rel, storage_to_csc
+    n, cp, ri, vv, perm, B = _grid_shifted(20, 1e-2, 3)
+    S = sc.SparseCholesky(n, cp, ri, perm, 0, 0)
+    F = S.factor(torch.tensor(vv, device="cuda"), precision="bf16")
+    Lg, _ = storage_to_csc(S.export(), S.storage_offsets(), F.storage().cpu().numpy(), n)
+    r = residual_rel(permuted_matrix(oracle.full_matrix(n, cp, ri, vv), perm), Lg)
+    print(f"  bf16 residual {r:.2e}", flush=True)
+    assert 1e-5 <= r <= 2e-2
