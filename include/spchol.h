@@ -248,13 +248,15 @@ spchol_status spchol_logdet_batch(spchol_num num, double *out_dev, void *stream)
  * replay, which does not read it back. */
 spchol_status spchol_info(spchol_num num, int64_t *info, void *stream);
 
-/* Capture the whole numeric factorization of `num` (values from vals_dev)
- * and, when nrhs > 0, the solve of B_dev in place, as one hipGraph on the
- * (non-null) stream; spchol_graph_launch replays it as a single launch.  The
- * pointers are fixed in the graph: update the contents of vals_dev and
- * B_dev between replays.  The graph contains no host synchronization and no
- * memset nodes (buffers are cleared by kernels); read the pivot status with
- * spchol_info.  Destroy the graph before `num`. */
+/* Capture the whole numeric factorization of `num` (values from vals_dev;
+ * vals_dev = NULL: no factorization, the graph only solves with the current
+ * factor) and, when nrhs > 0, the solve of B_dev in place, as one hipGraph
+ * on the (non-null) stream; spchol_graph_launch replays it as a single
+ * launch.  The pointers are fixed in the graph: update the contents of
+ * vals_dev and B_dev between replays.  The graph contains no host
+ * synchronization and no memset nodes (buffers are cleared by kernels); read
+ * the pivot status with spchol_info.  SPCHOL_ERR_ARG if there is nothing to
+ * capture (no values and nrhs = 0).  Destroy the graph before `num`. */
 spchol_status spchol_graph_create(spchol_num num, const double *vals_dev, double *B_dev, int64_t nrhs,
                                   int64_t ldb, void *stream, spchol_graph *out);
 spchol_status spchol_graph_launch(spchol_graph graph, void *stream);

@@ -344,13 +344,14 @@ class Factor:
         return int(info.value)
 
     def capture(self, vals, Bt=None, stream=None) -> Graph:
-        """Capture factorization (+ in-place solve of the (nrhs, n) tensor Bt)
-        as a hipGraph on `stream` (default: torch's current stream, which
-        must not be the null stream)."""
+        """Capture factorization (vals None: none) + in-place solve of the
+        (nrhs, n) tensor Bt (None: none) as a hipGraph on `stream` (default:
+        torch's current stream, which must not be the null stream)."""
         h = C.c_void_p()
         nrhs = 0 if Bt is None else (Bt.shape[0] if Bt.dim() == 2 else 1)
         bp = None if Bt is None else _dev_f64(Bt, "B")
-        _check(capi.lib().spchol_graph_create(self._h, _dev_f64(vals, "vals"), bp, nrhs, max(self.sym.n, 1),
+        vp = None if vals is None else _dev_f64(vals, "vals")
+        _check(capi.lib().spchol_graph_create(self._h, vp, bp, nrhs, max(self.sym.n, 1),
                                               _stream_ptr(stream), C.byref(h)))
         return Graph(self, h)
 

@@ -66,35 +66,47 @@ __device__ inline double readlane_d(double x, int l) {
 constexpr int DLD = NBMAX + 2;  // even: 16-byte aligned columns
 constexpr int MB = 16;          // micro-block width
 
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps
+// for the inverse square root, y <- y + (y/2)(1 - x y^2) (each step doubles
+// the correct bits of the estimate); a few ulps from the rounded value, on
+// a much shorter dependency chain than a rounded sqrt and division.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 // Columns of the block past kp are padded with an identity (unit
 // diagonal, zero off-diagonal), so they factor to themselves and the sweep
 // needs no per-column branch.  The pivot and the entries of the scaled
 // column that the other rows need (rows j0+c, c > q, one per lane) come
 // straight from their lanes' registers with readlane (scalar operands of
-// the row update), so the sweep never touches memory.  Like LAPACK's
-// unblocked Cholesky, the column is scaled by the reciprocal of the pivot's
-// square root.
+// the row update), so the sweep never touches memory.  As in LAPACK's
+// unblocked Cholesky the column is scaled by the reciprocal of the pivot's
+// square root; here both come from one inverse square root,
+// L_jj = d * (1/sqrt(d)).  A non-positive (or NaN) pivot is replaced by 1 so
+// the sweep runs on, and the first such column is reported after it.
 __device__ __forceinline__ void potrf16(double (&r)[MB], int lane, int j0, unsigned long long* __restrict__ status,
                                         int64_t col0) {
+  int bad = MB;
 #pragma unroll
   for (int q = 0; q < MB; ++q) {
     double piv = readlane_d(r[q], j0 + q);
-    if (!(piv > 0.0)) {
-      if (lane == j0 + q) atomicMin(status, (unsigned long long)(col0 + q));
-      piv = 1.0;
-    }
-    const double ljj = sqrt(piv);
-    const double rinv = 1.0 / ljj;
+    const bool ok = piv > 0.0;
+    bad = (!ok && bad == MB) ? q : bad;
+    piv = ok ? piv : 1.0;
+    const double rinv = rsqrt_nr(piv);
+    const double ljj = piv * rinv;
     const double lq = (lane == j0 + q) ? ljj : (lane > j0 + q ? r[q] * rinv : 0.0);
     r[q] = lq;
-    // one broadcast at a time: hoisted, the broadcasts would pile up in
-    // scalar registers and spill
 #pragma unroll
-    for (int c = q + 1; c < MB; ++c) {
-      r[c] = fma(-lq, readlane_d(lq, j0 + c), r[c]);
-      __builtin_amdgcn_sched_barrier(0);
-    }
+    for (int c = q + 1; c < MB; ++c) r[c] = fma(-lq, readlane_d(lq, j0 + c), r[c]);
   }
+  if (bad < MB && lane == 0) atomicMin(status, (unsigned long long)(col0 + bad));
 }
 
 // One wavefront's share of X = A V^T for a 64-row tile (A staged in LDS
@@ -302,11 +314,11 @@ __device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__
     }
     __syncthreads();
   }
-  if (w == 0 && lane < kp) {
-    double* dst = Lp + c0 + lane;
-#pragma unroll 16
-    for (int c = 0; c < NBMAX; ++c)
-      if (c < kp && c <= lane) dst[(int64_t)c * m] = Dc[c * DLD + lane];
+  // write the factored block back (lower part), all threads, coalesced
+#pragma unroll
+  for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+    const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;
+    if (r < kp && c <= r) Lp[(int64_t)c * m + c0 + r] = Dc[c * DLD + r];
   }
 
   // 2. W = L_pp^{-1}
@@ -317,9 +329,10 @@ __device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__
   //    launch and the solves
   {
     double* dst = winv + S.wbase[J] + (int64_t)p * S.nb * S.nb;
-    for (int idx = tid; idx < kp * kp; idx += 256) {
-      const int c = idx / kp, r = idx - c * kp;
-      dst[idx] = r >= c ? Wc[c * DLD + r] : 0.0;
+#pragma unroll
+    for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+      const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;
+      if (r < kp && c < kp) dst[c * kp + r] = r >= c ? Wc[c * DLD + r] : 0.0;
     }
   }
   // 3. rows rb .. rb + 255

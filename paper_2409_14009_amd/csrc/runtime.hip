@@ -746,7 +746,7 @@ spchol_status spchol_graph_create(spchol_num num, const double* vals_dev, double
   *out = nullptr;
   const Symbolic& S = num->sym->S;
   if (nrhs < 0 || (nrhs > 0 && (!B_dev || ldb < S.n || ldb < 1))) return fail(SPCHOL_ERR_ARG, "bad right-hand side");
-  if (!vals_dev && S.nnzA > 0) return fail(SPCHOL_ERR_ARG, "null values");
+  if (!vals_dev && nrhs == 0) return fail(SPCHOL_ERR_ARG, "nothing to capture");
   hipStream_t st = (hipStream_t)stream;
   if (!st) return fail(SPCHOL_ERR_ARG, "graph capture needs a non-null stream");
   spchol_graph_s* G = new (std::nothrow) spchol_graph_s();
@@ -765,7 +765,7 @@ spchol_status spchol_graph_create(spchol_num num, const double* vals_dev, double
   hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
   spchol_status s = SPCHOL_OK;
   if (e == hipSuccess) {
-    s = enqueue_factor(num, vals_dev, st);
+    if (vals_dev || S.nnzA == 0) s = enqueue_factor(num, vals_dev, st);
     if (!s && nrhs > 0 && S.n > 0) s = enqueue_solve(num, G->sw, B_dev, nrhs, ldb, st);
     hipError_t e2 = hipStreamEndCapture(st, &G->graph);
     if (!s && e2 != hipSuccess) e = e2;

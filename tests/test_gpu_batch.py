@@ -152,3 +152,29 @@ def test_autotune_batch(tmp_path, monkeypatch):
     best2, _ = autotune.tune_batch(mats, v, reps=2)
     assert best2 == best
     assert (tmp_path / "tune.json").exists()
+
+
+def test_solve_only_graph():
+    """A graph holding only the solve reuses the current factor; replays
+    after an eager refactorization with new values see the new factor."""
+    p = gen.make_config(0)
+    S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm)
+    v = torch.tensor(p.vals, device="cuda")
+    F = S.factor(v)
+    Bt = torch.tensor(np.ascontiguousarray(p.B.T), device="cuda")
+    X = torch.empty_like(Bt)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        G = F.capture(None, X, stream=stream)
+        for s in (1.0, 4.0, 1.0):
+            F.refactor(v * s if s != 1.0 else v, stream=stream)
+            X.copy_(Bt)
+            G.replay(stream)
+            stream.synchronize()
+            x = X.cpu().numpy().T * s
+            A = oracle.full_matrix(p.n, p.colptr, p.rowind, p.vals)
+            eta, _ = oracle.backward_error(A, x, p.B)
+            assert eta.max() <= 1e-12, (s, eta)
+    G.close()
+    with pytest.raises(sc.SpcholError):
+        F.capture(None, None, stream=stream)
