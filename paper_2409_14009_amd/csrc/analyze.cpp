@@ -558,21 +558,28 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
         }
         S.si_max_slots = std::max<int64_t>(S.si_max_slots, (int64_t)js.size());
         S.si_max_y = std::max(S.si_max_y, yo);
-        const int32_t kinds[4] = {K_SI_W, K_SI_Y, K_SI_ZB, K_SI_ZD};
+        // (the inverted diagonal blocks come from the factorization)
+        const int32_t kinds[3] = {K_SI_Y, K_SI_ZB, K_SI_ZD};
         for (int32_t kind : kinds) {
           open(S.si_plan, kind, (int32_t)l, (int32_t)p);
           S.si_plan.back().slot_base = base;
           for (size_t s = 0; s < js.size(); ++s) {
             const int32_t J = js[s];
-            if (kind == K_SI_Y || kind == K_SI_ZB) {
-              for (int64_t a0 = p * nb + kpan(J, p); a0 < M(J); a0 += kTile)
+            const int64_t rb = p * nb + kpan(J, p);
+            if (kind == K_SI_Y) {
+              // split K: segments of kSiSeg rows of B per task (a = panel |
+              // segment << 16), summed into the Y blocks (zero on entry:
+              // their readers leave them cleared)
+              for (int64_t a0 = rb; a0 < M(J); a0 += kTile)
+                for (int64_t sg = 0; rb + sg * kSiSeg < M(J); ++sg)
+                  S.tasks.push_back({J, (int32_t)(p | (sg << 16)), (int32_t)a0, (int32_t)s});
+            } else if (kind == K_SI_ZB) {
+              for (int64_t a0 = rb; a0 < M(J); a0 += kTile)
                 S.tasks.push_back({J, (int32_t)p, (int32_t)a0, (int32_t)s});
             } else {
               S.tasks.push_back({J, (int32_t)p, 0, (int32_t)s});
             }
           }
-          // keep the launch even when empty for K_SI_W (it carries the
-          // round's slot count for the T reset)
           Launch& Lb = S.si_plan.back();
           Lb.ntasks = (int32_t)((int64_t)S.tasks.size() - Lb.off);
           if (Lb.ntasks == 0) S.si_plan.pop_back();

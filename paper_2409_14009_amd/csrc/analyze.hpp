@@ -4,6 +4,8 @@
 #include <string>
 #include <vector>
 
+#include "consts.hpp"
+
 namespace spchol {
 
 // Work item of a batched launch.  Meaning of the fields per launch kind:
@@ -34,7 +36,7 @@ enum Kind : int32_t {
   K_BWD = 4,    // backward solve round: panel gather (+ inverse-block product)
   K_BWD_FIN = 5,  // backward solve: inverse-block product of split panels
   K_TRSM = 7,
-  K_SI_W = 8,   // selected inversion: inverse of the panel's diagonal block
+  K_SI_W = 8,   // (unused: the factorization stores the inverted diagonal blocks)
   K_SI_Y = 9,   // Y = Z_BB L_Bp tiles
   K_SI_ZB = 10, // Z_Bp = -Y W tiles (+ T)
   K_SI_ZD = 11, // Z_pp = (W^T - T) W

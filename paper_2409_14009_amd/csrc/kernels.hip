@@ -8,6 +8,7 @@
 // array (Sec. II-A), leading dimension m_J.
 #include <climits>
 
+#include "consts.hpp"
 #include "device.hpp"
 
 namespace spchol {
@@ -387,7 +388,9 @@ __global__ __launch_bounds__(256) void k_panel_rows(DevSym S, double* __restrict
 
 // ---------------------------------------------------------------------------
 // update: C[i, c] -= sum_t L[i, t] L[c, t] over a 64 x 64 tile, lower part,
-// on the matrix cores (16x16x4 MFMA, four wavefronts of 32 x 32).
+// on the matrix cores (16x16x4 MFMA, four wavefronts of 32 x 32, K in
+// chunks of 32 staged through LDS with the next chunk prefetched into
+// registers).
 //   kind 1 (internal): the remaining columns of J itself, K = one panel;
 //                      plain read-modify-write (one writer per entry).
 //   kind 2 (external): the update matrix L_RJ L_RJ^T (Sec. II-A, Fig. 2),
@@ -443,11 +446,15 @@ __device__ __forceinline__ unsigned short to_bf16(double x) {
 }
 
 constexpr int ALD = TILE + 2;
-constexpr int G2 = 5;  // bf16 staging: 8-byte groups per row (4 used, 1 pad)
+constexpr int UKC = 32;  // K chunk of the update GEMM
+constexpr int G2 = UKC / 4 + 1;  // bf16 staging: 8-byte groups per row (UKC / 4 used, 1 pad)
 constexpr int CLD = TILE + 1;  // column stride of the epilogue tile
 
-constexpr int UPD_SMEM = TILE * CLD + 2 * KC * ALD;  // doubles: Cs, then As and Bs (T each)
-static_assert(TILE * G2 * sizeof(s4) <= KC * ALD * sizeof(double), "bf16 staging fits the operand area");
+// LDS of an update tile: the operand chunks As, Bs (UKC x ALD doubles each;
+// fp32 and bf16 use part of their slot) during the K loop, then the
+// epilogue tile Cs (TILE x CLD doubles) in the same space.
+constexpr int UPD_SMEM = (2 * UKC * ALD > TILE * CLD) ? 2 * UKC * ALD : TILE * CLD;
+static_assert(TILE * G2 * sizeof(s4) <= UKC * ALD * sizeof(double), "bf16 staging fits the operand area");
 
 template <int P, int kind>
 __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict__ L, const DevTask t,
@@ -455,8 +462,8 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
   using Pr = UpdPrec<P>;
   using T = typename Pr::T;
   double* __restrict__ Cs = smem;
-  T* __restrict__ As = reinterpret_cast<T*>(smem + TILE * CLD);
-  T* __restrict__ Bs = reinterpret_cast<T*>(smem + TILE * CLD + KC * ALD);
+  T* __restrict__ As = reinterpret_cast<T*>(smem);
+  T* __restrict__ Bs = reinterpret_cast<T*>(smem + UKC * ALD);
   const int J = t.J, row0 = t.a, col0 = t.b;
   const int m = S.sm[J], k = S.sk[J];
   int kb, ke, colEnd;
@@ -480,47 +487,56 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
     for (int j = 0; j < 2; ++j) acc[i][j] = Pr::zero();
 
   // staging: thread loads rows (tid & 63) of chunk columns (tid >> 6) + 4q
-  // (bf16: columns 4 (tid >> 6) + q, packed into one 8-byte group)
+  // (bf16: columns 8 (tid >> 6) + q, packed into two 8-byte groups)
   const int sr = tid & 63, sc = tid >> 6;
   const bool va = row0 + sr < m, vb = col0 + sr < colEnd;
   const double* pa = Lj + row0 + sr;
   const double* pb = Lj + col0 + sr;
-  double ra[4], rb[4];
+  double ra[UKC / 4], rb[UKC / 4];
   auto fetch = [&](int kk) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int gc = P == 2 ? kk + 4 * sc + q : kk + sc + 4 * q;
+    for (int q = 0; q < UKC / 4; ++q) {
+      const int gc = P == 2 ? kk + (UKC / 4) * sc + q : kk + sc + 4 * q;
       ra[q] = (va && gc < ke) ? pa[(int64_t)gc * m] : 0.0;
       rb[q] = (vb && gc < ke) ? pb[(int64_t)gc * m] : 0.0;
     }
   };
   fetch(kb);
   if constexpr (P == 2) {
-    for (int kk = kb; kk < ke; kk += KC) {
-      As[sr * G2 + sc] = s4{(short)to_bf16(ra[0]), (short)to_bf16(ra[1]), (short)to_bf16(ra[2]), (short)to_bf16(ra[3])};
-      Bs[sr * G2 + sc] = s4{(short)to_bf16(rb[0]), (short)to_bf16(rb[1]), (short)to_bf16(rb[2]), (short)to_bf16(rb[3])};
+    for (int kk = kb; kk < ke; kk += UKC) {
+#pragma unroll
+      for (int g = 0; g < UKC / 16; ++g) {
+        As[sr * G2 + (UKC / 16) * sc + g] = s4{(short)to_bf16(ra[4 * g]), (short)to_bf16(ra[4 * g + 1]),
+                                                (short)to_bf16(ra[4 * g + 2]), (short)to_bf16(ra[4 * g + 3])};
+        Bs[sr * G2 + (UKC / 16) * sc + g] = s4{(short)to_bf16(rb[4 * g]), (short)to_bf16(rb[4 * g + 1]),
+                                                (short)to_bf16(rb[4 * g + 2]), (short)to_bf16(rb[4 * g + 3])};
+      }
       __syncthreads();
-      if (kk + KC < ke) fetch(kk + KC);
-      // lane (li, lk): A[row li][k = 4 lk .. 4 lk + 3], B likewise
-      const s4 a0 = As[(wr + li) * G2 + lk], a1 = As[(wr + 16 + li) * G2 + lk];
-      const s4 b0 = Bs[(wc + li) * G2 + lk], b1 = Bs[(wc + 16 + li) * G2 + lk];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][1], 0, 0, 0);
+      if (kk + UKC < ke) fetch(kk + UKC);
+      // k half h: lane (li, lk) holds A[row li][k = 16 h + 4 lk .. + 3],
+      // group 4 h + lk of its row; B likewise
+#pragma unroll
+      for (int h = 0; h < UKC / 16; ++h) {
+        const s4 a0 = As[(wr + li) * G2 + 4 * h + lk], a1 = As[(wr + 16 + li) * G2 + 4 * h + lk];
+        const s4 b0 = Bs[(wc + li) * G2 + 4 * h + lk], b1 = Bs[(wc + 16 + li) * G2 + 4 * h + lk];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][1], 0, 0, 0);
+      }
       __syncthreads();
     }
   } else
-  for (int kk = kb; kk < ke; kk += KC) {
+  for (int kk = kb; kk < ke; kk += UKC) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < UKC / 4; ++q) {
       As[(sc + 4 * q) * ALD + sr] = (T)ra[q];
       Bs[(sc + 4 * q) * ALD + sr] = (T)rb[q];
     }
     __syncthreads();
-    if (kk + KC < ke) fetch(kk + KC);
+    if (kk + UKC < ke) fetch(kk + UKC);
 #pragma unroll
-    for (int ks = 0; ks < KC; ks += 4) {
+    for (int ks = 0; ks < UKC; ks += 4) {
       const int kr = (ks + lk) * ALD;
       const T a0 = As[kr + wr + li], a1 = As[kr + wr + 16 + li];
       const T b0 = Bs[kr + wc + li], b1 = Bs[kr + wc + 16 + li];
@@ -874,55 +890,54 @@ __global__ __launch_bounds__(256) void k_logdet_final(const double* __restrict__
 // with W = L_pp^{-1}.  Panels are visited root to leaves and, inside a
 // supernode, last panel first, so Z_BB (later columns of J, then ancestors
 // reached through the relative indices) is final when needed.  Per panel:
-//   k_si_w   W into scratch (row-major, slot s);
-//   k_si_y   Y = Z_BB L_Bp, 64-row tiles, Z_BB gathered (symmetric);
+//   k_si_y   Y = Z_BB L_Bp, 64-row tiles, Z_BB gathered (symmetric), split
+//            over segments of B and summed into Y;
 //   k_si_zb  Z_Bp = -Y W per tile, and T += Z_Bp^T L_Bp (atomic);
 //   k_si_zd  Z_pp = (W^T - T) W, lower part.
-// Task fields: J, panel, first local row of the tile, slot in the launch.
+// W is the inverted diagonal block the factorization stored.  Y and T are
+// zero on entry to a round: k_si_zb clears the Y rows it read, k_si_zd the
+// T it read.  Task fields: J, panel, first local row of the tile, slot in
+// the round.
 // ---------------------------------------------------------------------------
 
 // offset in Z (layout of L) of the symmetric entry at local rows (a, b) of
 // J, both at or below J's first column
-__device__ __forceinline__ int64_t zsym_off(const DevSym& S, int J, int k, int m, int64_t ob, int a, int b) {
-  const int lo = min(a, b), hi = max(a, b);
-  if (lo < k) return S.loff[J] + (int64_t)lo * m + hi;
+// Where Z(lo, hi) (lo <= hi, local rows of J) lives: the column of row lo
+// is either J's own (lo < k) or an ancestor's, whose storage column starts
+// at colbase; the entry of row hi in it is at colbase + hi (lo < k) or
+// colbase + tpos[tb + hi - k] (the relative index of hi in the ancestor).
+struct ZCol {
+  int64_t colbase;
+  int64_t tb;  // relptr[pair] - pa0[pair], or -1 for J's own columns
+};
+
+__device__ __forceinline__ ZCol zcol(const DevSym& S, int J, int k, int m, int64_t ob, int lo) {
+  if (lo < k) return ZCol{S.loff[J] + (int64_t)lo * m, -1};
   const int pair = S.opair[ob + lo - k];
-  return S.ocbase[ob + lo - k] + S.tpos[S.relptr[pair] - S.pa0[pair] + (hi - k)];
+  return ZCol{S.ocbase[ob + lo - k], S.relptr[pair] - S.pa0[pair]};
 }
 
-__global__ __launch_bounds__(256) void k_si_w(DevSym S, const double* __restrict__ L, int64_t off,
-                                              double* __restrict__ wbuf) {
-  __shared__ __attribute__((aligned(16))) double Dc[NBMAX * DLD];
-  __shared__ __attribute__((aligned(16))) double Wc[NBMAX * DLD];
-  const DevTask t = S.tasks[off + blockIdx.x];
-  const int J = t.J, p = t.a, slot = t.c;
-  const int m = S.sm[J], k = S.sk[J];
-  const int c0 = p * S.nb, kp = min(S.nb, k - c0);
-  const double* __restrict__ Lp = L + S.loff[J] + (int64_t)c0 * m;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int idx = tid; idx < NBMAX * NBMAX; idx += 256) {
-    const int i = idx & 63, c = idx >> 6;
-    Dc[c * DLD + i] = (i < kp && c <= i) ? Lp[(int64_t)c * m + c0 + i] : (i == c ? 1.0 : 0.0);
-    Wc[c * DLD + i] = 0.0;
-  }
-  __syncthreads();
-  invert_diag_block(Dc, Wc, (kp + MB - 1) / MB, lane, w);
-  __syncthreads();
-  double* dst = wbuf + (int64_t)slot * NBMAX * NBMAX;
-  for (int idx = tid; idx < NBMAX * NBMAX; idx += 256) dst[idx] = Wc[(idx & 63) * DLD + (idx >> 6)];
+__device__ __forceinline__ int64_t zat(const DevSym& S, ZCol c, int k, int hi) {
+  return c.colbase + (c.tb < 0 ? (int64_t)hi : (int64_t)S.tpos[c.tb + hi - k]);
 }
 
-// Y[a][t] = sum_{b in B} Z(a, b) L[b][c0 + t] for a in [a0, a0 + 64)
+// Y[a][t] = sum_{b in B} Z(a, b) L[b][c0 + t] for a in [a0, a0 + 64), each
+// task over one segment of kSiSeg rows b of B (Y zeroed beforehand).  The
+// column data of the tile's rows a is fetched once; that of each K chunk's
+// 16 rows b once per chunk into LDS, so an entry of Z costs one relative
+// index load and the entry itself.
 __global__ __launch_bounds__(256) void k_si_y(DevSym S, const double* __restrict__ L, const double* __restrict__ Z,
                                               int64_t off, const int64_t* __restrict__ yoff,
                                               double* __restrict__ ybuf) {
   __shared__ double As[KC * ALD];
   __shared__ double Bs[KC * ALD];
+  __shared__ ZCol colb[KC];
   const DevTask t = S.tasks[off + blockIdx.x];
-  const int J = t.J, p = t.a, a0 = t.b, slot = t.c;
+  const int J = t.J, p = t.a & 0xFFFF, seg = t.a >> 16, a0 = t.b, slot = t.c;
   const int m = S.sm[J], k = S.sk[J];
   const int c0 = p * S.nb, kp = min(S.nb, k - c0);
   const int rb = c0 + kp;
+  const int bs = rb + seg * kSiSeg, be = min(m, bs + kSiSeg);  // this task's rows of B
   const double* __restrict__ Lj = L + S.loff[J];
   const int64_t ob = S.obase[J];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -935,19 +950,48 @@ __global__ __launch_bounds__(256) void k_si_y(DevSym S, const double* __restrict
     for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
   const int sr = tid & 63, sc = tid >> 6;
   const int a = a0 + sr;
-  for (int b0 = rb; b0 < m; b0 += KC) {
+  // Z is stored by columns (lower part): Z(a, b) with a >= b is read down
+  // column b (consecutive a contiguous), with a < b down column a
+  // (consecutive b contiguous).  Chunks entirely above the tile's diagonal
+  // therefore use a transposed thread mapping (16 lanes along b).
+  __shared__ ZCol cola[TILE];
+  if (tid < TILE) cola[tid] = a0 + tid < m ? zcol(S, J, k, m, ob, a0 + tid) : ZCol{0, -1};
+  const ZCol ca = a < m ? zcol(S, J, k, m, ob, a) : ZCol{0, -1};
+  for (int b0 = bs; b0 < be; b0 += KC) {
+    if (tid < KC) colb[tid] = b0 + tid < be ? zcol(S, J, k, m, ob, b0 + tid) : ZCol{0, -1};
+    __syncthreads();
     double ra[4], rbv[4];
+    const bool above = b0 >= a0 + TILE - 1;  // every b of the chunk > every a of the tile
+    if (above) {
+      const int bi = tid & (KC - 1), b = b0 + bi;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ai = (tid >> 4) + 16 * q, aa = a0 + ai;
+        ra[q] = (aa < m && b < be) ? Z[zat(S, cola[ai], k, b)] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int bi = sc + 4 * q, b = b0 + bi;
+        double z = 0.0;
+        if (a < m && b < be) z = Z[a >= b ? zat(S, colb[bi], k, a) : zat(S, ca, k, b)];
+        ra[q] = z;
+      }
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int b = b0 + sc + 4 * q;
-      ra[q] = (a < m && b < m) ? Z[zsym_off(S, J, k, m, ob, a, b)] : 0.0;
-      rbv[q] = (b < m && sr < kp) ? Lj[(int64_t)(c0 + sr) * m + b] : 0.0;
+      rbv[q] = (b < be && sr < kp) ? Lj[(int64_t)(c0 + sr) * m + b] : 0.0;
+    }
+    if (above) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) As[(tid & (KC - 1)) * ALD + (tid >> 4) + 16 * q] = ra[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) As[(sc + 4 * q) * ALD + sr] = ra[q];  // As[kb][a - a0]
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      As[(sc + 4 * q) * ALD + sr] = ra[q];   // As[kb][a - a0]
-      Bs[(sc + 4 * q) * ALD + sr] = rbv[q];  // Bs[kb][t]
-    }
+    for (int q = 0; q < 4; ++q) Bs[(sc + 4 * q) * ALD + sr] = rbv[q];  // Bs[kb][t]
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < KC; ks += 4) {
@@ -970,16 +1014,15 @@ __global__ __launch_bounds__(256) void k_si_y(DevSym S, const double* __restrict
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int ar = a0 + wr + 16 * bi + 4 * v + lk;
-        if (ar < m && tc < kp) Y[(int64_t)(ar - rb) * NBMAX + tc] = acc[bi][bj][v];
+        if (ar < m && tc < kp) atomicAdd(Y + (int64_t)(ar - rb) * NBMAX + tc, acc[bi][bj][v]);
       }
   }
 }
 
 // Z_Bp = -Y W on rows [a0, a0 + 64), and T += Z_Bp^T L_Bp
-__global__ __launch_bounds__(256) void k_si_zb(DevSym S, const double* __restrict__ L, double* __restrict__ Z,
-                                               int64_t off, const int64_t* __restrict__ yoff,
-                                               const double* __restrict__ ybuf, const double* __restrict__ wbuf,
-                                               double* __restrict__ tbuf) {
+__global__ __launch_bounds__(256) void k_si_zb(DevSym S, const double* __restrict__ L, const double* __restrict__ winv,
+                                               double* __restrict__ Z, int64_t off, const int64_t* __restrict__ yoff,
+                                               double* __restrict__ ybuf, double* __restrict__ tbuf) {
   __shared__ __attribute__((aligned(16))) double As[NBMAX * DLD];
   __shared__ __attribute__((aligned(16))) double Wc[NBMAX * DLD];
   const DevTask t = S.tasks[off + blockIdx.x];
@@ -988,13 +1031,16 @@ __global__ __launch_bounds__(256) void k_si_zb(DevSym S, const double* __restric
   const int c0 = p * S.nb, kp = min(S.nb, k - c0);
   const int rb = c0 + kp;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const double* __restrict__ Y = ybuf + yoff[slot];
-  const double* __restrict__ W = wbuf + (int64_t)slot * NBMAX * NBMAX;
+  double* __restrict__ Y = ybuf + yoff[slot];
+  const double* __restrict__ W = winv + S.wbase[J] + (int64_t)p * S.nb * S.nb;  // kp x kp, column-major
   for (int idx = tid; idx < NBMAX * NBMAX; idx += 256) {
-    const int r = idx >> 6, c = idx & 63;  // Y row-major, W row-major
-    As[c * DLD + r] = (a0 + r < m && c < kp) ? Y[(int64_t)(a0 + r - rb) * NBMAX + c] : 0.0;
-    // V = W^T column-major: Wc[c * DLD + i] = V_ic = W_ci
-    Wc[r * DLD + c] = W[idx];
+    const int r = idx >> 6, c = idx & 63;  // Y row-major
+    const bool iny = a0 + r < m;
+    double* yp = Y + (int64_t)(a0 + r - rb) * NBMAX + c;
+    As[c * DLD + r] = (iny && c < kp) ? *yp : 0.0;
+    if (iny) *yp = 0.0;  // leave Y cleared for the next round
+    // V = W^T column-major: Wc[c * DLD + i] = V_ic = W_ci, i.e. Wc[r * DLD + c] = W_rc
+    Wc[r * DLD + c] = (r < kp && c < kp) ? W[c * kp + r] : 0.0;
   }
   __syncthreads();
   double* __restrict__ Zp = Z + S.loff[J] + (int64_t)c0 * m;
@@ -1038,8 +1084,8 @@ __global__ __launch_bounds__(256) void k_si_zb(DevSym S, const double* __restric
 }
 
 // Z_pp = (W^T - T) W, lower part
-__global__ __launch_bounds__(256) void k_si_zd(DevSym S, double* __restrict__ Z, int64_t off,
-                                               const double* __restrict__ wbuf, const double* __restrict__ tbuf) {
+__global__ __launch_bounds__(256) void k_si_zd(DevSym S, const double* __restrict__ winv, double* __restrict__ Z,
+                                               int64_t off, double* __restrict__ tbuf) {
   __shared__ __attribute__((aligned(16))) double As[NBMAX * DLD];
   __shared__ __attribute__((aligned(16))) double Wc[NBMAX * DLD];
   const DevTask t = S.tasks[off + blockIdx.x];
@@ -1047,13 +1093,15 @@ __global__ __launch_bounds__(256) void k_si_zd(DevSym S, double* __restrict__ Z,
   const int m = S.sm[J], k = S.sk[J];
   const int c0 = p * S.nb, kp = min(S.nb, k - c0);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const double* __restrict__ W = wbuf + (int64_t)slot * NBMAX * NBMAX;
-  const double* __restrict__ T = tbuf + (int64_t)slot * NBMAX * NBMAX;
+  const double* __restrict__ W = winv + S.wbase[J] + (int64_t)p * S.nb * S.nb;  // kp x kp, column-major
+  double* __restrict__ T = tbuf + (int64_t)slot * NBMAX * NBMAX;
   for (int idx = tid; idx < NBMAX * NBMAX; idx += 256) {
     const int r = idx >> 6, c = idx & 63;
+    const bool in = r < kp && c < kp;
     // M = W^T - T column-major: As[c * DLD + r] = W[c][r] - T[r][c]
-    As[c * DLD + r] = W[c * NBMAX + r] - T[idx];
-    Wc[r * DLD + c] = W[idx];  // V = W^T column-major
+    As[c * DLD + r] = (in ? W[r * kp + c] : 0.0) - T[idx];
+    T[idx] = 0.0;  // leave T cleared for the next round
+    Wc[r * DLD + c] = in ? W[c * kp + r] : 0.0;  // V = W^T column-major: Wc[r * DLD + c] = W_rc
   }
   __syncthreads();
   double* __restrict__ Zp = Z + S.loff[J] + (int64_t)c0 * m;
@@ -1278,14 +1326,13 @@ hipError_t launch_copy_cols(double* Y, int64_t ldy, const double* B, int64_t ldb
 
 namespace spchol {
 
-hipError_t launch_si(const DevSym& S, int32_t kind, int64_t off, int32_t ntasks, const double* L, double* Z,
-                     const int64_t* yoff, double* ybuf, double* wbuf, double* tbuf, hipStream_t st) {
+hipError_t launch_si(const DevSym& S, int32_t kind, int64_t off, int32_t ntasks, const double* L, const double* winv,
+                     double* Z, const int64_t* yoff, double* ybuf, double* tbuf, hipStream_t st) {
   if (ntasks <= 0) return hipSuccess;
   switch (kind) {
-    case 8: k_si_w<<<ntasks, 256, 0, st>>>(S, L, off, wbuf); break;
     case 9: k_si_y<<<ntasks, 256, 0, st>>>(S, L, Z, off, yoff, ybuf); break;
-    case 10: k_si_zb<<<ntasks, 256, 0, st>>>(S, L, Z, off, yoff, ybuf, wbuf, tbuf); break;
-    case 11: k_si_zd<<<ntasks, 256, 0, st>>>(S, Z, off, wbuf, tbuf); break;
+    case 10: k_si_zb<<<ntasks, 256, 0, st>>>(S, L, winv, Z, off, yoff, ybuf, tbuf); break;
+    case 11: k_si_zd<<<ntasks, 256, 0, st>>>(S, winv, Z, off, tbuf); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

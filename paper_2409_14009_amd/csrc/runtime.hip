@@ -628,19 +628,20 @@ static spchol_status run_selinv(spchol_num_s* N, hipStream_t st) {
   const DevSym& D = N->sym->dev;
   const int64_t storage = S.loff[S.ns];
   const int64_t blk = (int64_t)kMaxPanel * kMaxPanel;
+  const int64_t ws = S.si_max_y + S.si_max_slots * blk;
   if (!N->Z) {
     HIP_TRY(hipMalloc((void**)&N->Z, (size_t)(storage > 0 ? storage : 1) * sizeof(double)));
-    const int64_t ws = S.si_max_y + 2 * S.si_max_slots * blk;
+    // Y blocks and T accumulators: zero here, and left zero by their readers
     HIP_TRY(hipMalloc((void**)&N->sibuf, (size_t)(ws > 0 ? ws : 1) * sizeof(double)));
+    HIP_TRY(hipMemset(N->sibuf, 0, (size_t)(ws > 0 ? ws : 1) * sizeof(double)));
+    HIP_TRY(hipDeviceSynchronize());
   }
   double* ybuf = N->sibuf;
-  double* wbuf = ybuf + S.si_max_y;
-  double* tbuf = wbuf + S.si_max_slots * blk;
+  double* tbuf = ybuf + S.si_max_y;
   for (const Launch& l : S.si_plan) {
-    if (l.kind == K_SI_W) HIP_TRY(launch_fill(tbuf, (int64_t)l.ntasks * blk, 0.0, st));
     const int64_t* yoff = N->sym->si_yoff + l.slot_base;
     HIP_TRY(timed(N, SPCHOL_KERNEL_SELINV, 0.0, 0.0, st, [&] {
-      return launch_si(D, l.kind, l.off, l.ntasks, N->L, N->Z, yoff, ybuf, wbuf, tbuf, st);
+      return launch_si(D, l.kind, l.off, l.ntasks, N->L, N->winv, N->Z, yoff, ybuf, tbuf, st);
     }));
   }
   return SPCHOL_OK;
