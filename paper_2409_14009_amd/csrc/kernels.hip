@@ -931,7 +931,6 @@ __global__ __launch_bounds__(256) void k_si_y(DevSym S, const double* __restrict
                                               double* __restrict__ ybuf) {
   __shared__ double As[KC * ALD];
   __shared__ double Bs[KC * ALD];
-  __shared__ ZCol colb[KC];
   const DevTask t = S.tasks[off + blockIdx.x];
   const int J = t.J, p = t.a & 0xFFFF, seg = t.a >> 16, a0 = t.b, slot = t.c;
   const int m = S.sm[J], k = S.sk[J];
@@ -953,16 +952,19 @@ __global__ __launch_bounds__(256) void k_si_y(DevSym S, const double* __restrict
   // Z is stored by columns (lower part): Z(a, b) with a >= b is read down
   // column b (consecutive a contiguous), with a < b down column a
   // (consecutive b contiguous).  Chunks entirely above the tile's diagonal
-  // therefore use a transposed thread mapping (16 lanes along b).
+  // therefore use a transposed thread mapping (16 lanes along b).  The
+  // column data of the tile's rows and of all rows of the segment are
+  // fetched once; the next chunk's entries are loaded into registers while
+  // the current one is multiplied.
   __shared__ ZCol cola[TILE];
+  __shared__ ZCol colseg[kSiSeg];
   if (tid < TILE) cola[tid] = a0 + tid < m ? zcol(S, J, k, m, ob, a0 + tid) : ZCol{0, -1};
-  const ZCol ca = a < m ? zcol(S, J, k, m, ob, a) : ZCol{0, -1};
-  for (int b0 = bs; b0 < be; b0 += KC) {
-    if (tid < KC) colb[tid] = b0 + tid < be ? zcol(S, J, k, m, ob, b0 + tid) : ZCol{0, -1};
-    __syncthreads();
-    double ra[4], rbv[4];
-    const bool above = b0 >= a0 + TILE - 1;  // every b of the chunk > every a of the tile
-    if (above) {
+  for (int i = tid; i < kSiSeg; i += 256) colseg[i] = bs + i < be ? zcol(S, J, k, m, ob, bs + i) : ZCol{0, -1};
+  __syncthreads();
+  const ZCol ca = a < m ? cola[sr] : ZCol{0, -1};
+  double ra[4], rbv[4];
+  auto fetch = [&](int b0) {
+    if (b0 >= a0 + TILE - 1) {  // every b of the chunk >= every a of the tile
       const int bi = tid & (KC - 1), b = b0 + bi;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -974,7 +976,7 @@ __global__ __launch_bounds__(256) void k_si_y(DevSym S, const double* __restrict
       for (int q = 0; q < 4; ++q) {
         const int bi = sc + 4 * q, b = b0 + bi;
         double z = 0.0;
-        if (a < m && b < be) z = Z[a >= b ? zat(S, colb[bi], k, a) : zat(S, ca, k, b)];
+        if (a < m && b < be) z = Z[a >= b ? zat(S, colseg[b - bs], k, a) : zat(S, ca, k, b)];
         ra[q] = z;
       }
     }
@@ -983,7 +985,10 @@ __global__ __launch_bounds__(256) void k_si_y(DevSym S, const double* __restrict
       const int b = b0 + sc + 4 * q;
       rbv[q] = (b < be && sr < kp) ? Lj[(int64_t)(c0 + sr) * m + b] : 0.0;
     }
-    if (above) {
+  };
+  fetch(bs);
+  for (int b0 = bs; b0 < be; b0 += KC) {
+    if (b0 >= a0 + TILE - 1) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) As[(tid & (KC - 1)) * ALD + (tid >> 4) + 16 * q] = ra[q];
     } else {
@@ -993,6 +998,7 @@ __global__ __launch_bounds__(256) void k_si_y(DevSym S, const double* __restrict
 #pragma unroll
     for (int q = 0; q < 4; ++q) Bs[(sc + 4 * q) * ALD + sr] = rbv[q];  // Bs[kb][t]
     __syncthreads();
+    if (b0 + KC < be) fetch(b0 + KC);
 #pragma unroll
     for (int ks = 0; ks < KC; ks += 4) {
       const int kr = (ks + lk) * ALD;
