@@ -94,18 +94,32 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 __device__ __forceinline__ void potrf16(double (&r)[MB], int lane, int j0, unsigned long long* __restrict__ status,
                                         int64_t col0) {
   int bad = MB;
+  // software-pipelined: the next column is updated, its pivot read and its
+  // inverse square root started right after the current column is scaled;
+  // the updates of the other columns fill that chain's latency
+  auto pivot = [&](double d, int q, double& rinv) {
+    const bool ok = d > 0.0;
+    bad = (!ok && bad == MB) ? q : bad;
+    d = ok ? d : 1.0;
+    rinv = rsqrt_nr(d);
+    return d;
+  };
+  double rinv;
+  double piv = pivot(readlane_d(r[0], j0), 0, rinv);
 #pragma unroll
   for (int q = 0; q < MB; ++q) {
-    double piv = readlane_d(r[q], j0 + q);
-    const bool ok = piv > 0.0;
-    bad = (!ok && bad == MB) ? q : bad;
-    piv = ok ? piv : 1.0;
-    const double rinv = rsqrt_nr(piv);
     const double ljj = piv * rinv;
     const double lq = (lane == j0 + q) ? ljj : (lane > j0 + q ? r[q] * rinv : 0.0);
     r[q] = lq;
+    double pivn = 1.0, rinvn = 1.0;
+    if (q + 1 < MB) {
+      r[q + 1] = fma(-lq, readlane_d(lq, j0 + q + 1), r[q + 1]);
+      pivn = pivot(readlane_d(r[q + 1], j0 + q + 1), q + 1, rinvn);
+    }
 #pragma unroll
-    for (int c = q + 1; c < MB; ++c) r[c] = fma(-lq, readlane_d(lq, j0 + c), r[c]);
+    for (int c = q + 2; c < MB; ++c) r[c] = fma(-lq, readlane_d(lq, j0 + c), r[c]);
+    piv = pivn;
+    rinv = rinvn;
   }
   if (bad < MB && lane == 0) atomicMin(status, (unsigned long long)(col0 + bad));
 }
