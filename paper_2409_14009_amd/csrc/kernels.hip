@@ -91,15 +91,16 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // square root; here both come from one inverse square root,
 // L_jj = d * (1/sqrt(d)).  A non-positive (or NaN) pivot is replaced by 1 so
 // the sweep runs on, and the first such column is reported after it.
+template <int NQ>
 __device__ __forceinline__ void potrf16(double (&r)[MB], int lane, int j0, unsigned long long* __restrict__ status,
                                         int64_t col0) {
-  int bad = MB;
+  int bad = NQ;
   // software-pipelined: the next column is updated, its pivot read and its
   // inverse square root started right after the current column is scaled;
   // the updates of the other columns fill that chain's latency
   auto pivot = [&](double d, int q, double& rinv) {
     const bool ok = d > 0.0;
-    bad = (!ok && bad == MB) ? q : bad;
+    bad = (!ok && bad == NQ) ? q : bad;
     d = ok ? d : 1.0;
     rinv = rsqrt_nr(d);
     return d;
@@ -107,21 +108,21 @@ __device__ __forceinline__ void potrf16(double (&r)[MB], int lane, int j0, unsig
   double rinv;
   double piv = pivot(readlane_d(r[0], j0), 0, rinv);
 #pragma unroll
-  for (int q = 0; q < MB; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     const double ljj = piv * rinv;
     const double lq = (lane == j0 + q) ? ljj : (lane > j0 + q ? r[q] * rinv : 0.0);
     r[q] = lq;
     double pivn = 1.0, rinvn = 1.0;
-    if (q + 1 < MB) {
+    if (q + 1 < NQ) {
       r[q + 1] = fma(-lq, readlane_d(lq, j0 + q + 1), r[q + 1]);
       pivn = pivot(readlane_d(r[q + 1], j0 + q + 1), q + 1, rinvn);
     }
 #pragma unroll
-    for (int c = q + 2; c < MB; ++c) r[c] = fma(-lq, readlane_d(lq, j0 + c), r[c]);
+    for (int c = q + 2; c < NQ; ++c) r[c] = fma(-lq, readlane_d(lq, j0 + c), r[c]);
     piv = pivn;
     rinv = rinvn;
   }
-  if (bad < MB && lane == 0) atomicMin(status, (unsigned long long)(col0 + bad));
+  if (bad < NQ && lane == 0) atomicMin(status, (unsigned long long)(col0 + bad));
 }
 
 // One wavefront's share of X = A V^T for a 64-row tile (A staged in LDS
@@ -298,7 +299,10 @@ __device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__
       for (int q = 0; q < MB; ++q) xb[q] = (lane >= j0) ? Dc[(j0 + q) * DLD + lane] : 0.0;
       // the sweep factors the 16 x 16 block (its lanes) and, on the lanes
       // below it, solves those rows against it
-      potrf16(xb, lane, j0, status, (int64_t)S.sfirst[J] + c0 + j0);
+      // a block of at most 4 real columns (most supernodes of the lower
+      // levels) sweeps only those; the identity-padded rest is unchanged
+      if (jn <= 4) potrf16<4>(xb, lane, j0, status, (int64_t)S.sfirst[J] + c0 + j0);
+      else potrf16<MB>(xb, lane, j0, status, (int64_t)S.sfirst[J] + c0 + j0);
       if (mine) {
 #pragma unroll
         for (int q = 0; q < MB; ++q)
