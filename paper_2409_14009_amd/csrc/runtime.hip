@@ -168,9 +168,12 @@ struct SolveWork {
     cap = 0;
   }
   ~SolveWork() { release(); }
-  // allocates (and clears acc); synchronous, never inside a capture
-  hipError_t ensure(int64_t n, int64_t nrhs) {
+  // allocates (and clears acc); synchronous, never inside a capture;
+  // *moved is set when the buffers were (re)allocated
+  hipError_t ensure(int64_t n, int64_t nrhs, bool* moved = nullptr) {
+    if (moved) *moved = false;
     if (cap >= n * nrhs && acc) return hipSuccess;
+    if (moved) *moved = true;
     release();
     const size_t v = (size_t)(n * nrhs > 0 ? n * nrhs : 1) * sizeof(double);
     hipError_t e = hipMalloc((void**)&y, v);
@@ -187,8 +190,26 @@ struct SolveWork {
   }
 };
 
+// A launch sequence seen again with the same arguments is captured as a
+// hipGraph and replayed from then on (one host launch instead of hundreds).
+struct CachedGraph {
+  int kind = 0;            // 0: factorization, 1: solve
+  const void* ptr = nullptr;  // values / right-hand sides
+  int64_t a = 0, b = 0;    // precision / (nrhs, ldb)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+};
+
 struct spchol_num_s {
   spchol_sym_s* sym = nullptr;
+  std::vector<CachedGraph> gcache;  // most recent last
+  bool gcache_on = true;
   double* L = nullptr;
   unsigned long long* status = nullptr;
   SolveWork sw;
@@ -204,7 +225,16 @@ struct spchol_num_s {
   double* lam = nullptr;   // adjoint solve, n x nrhs
   int64_t lcap = 0;
   Profiler prof;
+  void drop_graphs(int kind) {  // kind < 0: all
+    std::vector<CachedGraph> keep;
+    for (CachedGraph& g : gcache) {
+      if (kind < 0 || g.kind == kind) g.release();
+      else keep.push_back(g);
+    }
+    gcache.swap(keep);
+  }
   ~spchol_num_s() {
+    drop_graphs(-1);
     if (Z) (void)hipFree(Z);
     if (sibuf) (void)hipFree(sibuf);
     if (lam) (void)hipFree(lam);
@@ -338,8 +368,63 @@ static spchol_status residual_eta(spchol_num_s* num, const double* vals, const d
   return SPCHOL_OK;
 }
 
+// Enqueue a launch sequence through the graph cache: the first call with a
+// given key runs eagerly, the second captures the sequence into a hipGraph,
+// later ones replay it.  Eager when profiling (per-launch events), on the
+// legacy null stream, or while the stream is itself being captured.
+constexpr size_t kGraphCacheSize = 8;
+
+template <class F>
+static spchol_status cached_run(spchol_num_s* N, int kind, const void* ptr, int64_t a, int64_t b, hipStream_t st,
+                                F&& enqueue) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (!N->gcache_on || N->prof.on || !st || hipStreamIsCapturing(st, &cs) != hipSuccess ||
+      cs != hipStreamCaptureStatusNone)
+    return enqueue();
+  for (size_t i = 0; i < N->gcache.size(); ++i) {
+    CachedGraph g = N->gcache[i];
+    if (g.kind != kind || g.ptr != ptr || g.a != a || g.b != b) continue;
+    N->gcache.erase(N->gcache.begin() + i);  // move to the back (most recent)
+    if (!g.exec) {
+      // second call: capture
+      hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) {
+        N->gcache.push_back(g);
+        return enqueue();
+      }
+      spchol_status s = enqueue();
+      hipError_t e2 = hipStreamEndCapture(st, &g.graph);
+      if (s) {
+        g.release();
+        return s;
+      }
+      if (e2 == hipSuccess) e2 = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+      if (e2 != hipSuccess) {
+        g.release();
+        (void)hipGetLastError();
+        N->gcache.push_back(g);
+        return enqueue();  // capture failed: run eagerly
+      }
+    }
+    N->gcache.push_back(g);
+    HIP_TRY(hipGraphLaunch(g.exec, st));
+    return SPCHOL_OK;
+  }
+  if (N->gcache.size() >= kGraphCacheSize) {
+    N->gcache.front().release();
+    N->gcache.erase(N->gcache.begin());
+  }
+  CachedGraph g;
+  g.kind = kind;
+  g.ptr = ptr;
+  g.a = a;
+  g.b = b;
+  N->gcache.push_back(g);
+  return enqueue();
+}
+
 static spchol_status run_factor(spchol_num_s* N, const double* vals, hipStream_t st, int64_t* info) {
-  spchol_status s = enqueue_factor(N, vals, st);
+  spchol_status s = cached_run(N, 0, vals, N->prec, 0, st, [&] { return enqueue_factor(N, vals, st); });
   if (s) return s;
   return read_info(N, st, info);
 }
@@ -546,8 +631,10 @@ spchol_status spchol_solve(spchol_num num, double* B_dev, int64_t nrhs, int64_t 
   if (nrhs == 0 || S.n == 0) return SPCHOL_OK;
   if (!B_dev) return fail(SPCHOL_ERR_ARG, "null right-hand side");
   hipStream_t st = (hipStream_t)stream;
-  HIP_TRY(num->sw.ensure(S.n, nrhs));
-  return enqueue_solve(num, num->sw, B_dev, nrhs, ldb, st);
+  bool moved = false;
+  HIP_TRY(num->sw.ensure(S.n, nrhs, &moved));
+  if (moved) num->drop_graphs(1);  // captured solves hold the old work vectors
+  return cached_run(num, 1, B_dev, nrhs, ldb, st, [&] { return enqueue_solve(num, num->sw, B_dev, nrhs, ldb, st); });
 }
 
 spchol_status spchol_refine(spchol_num num, const double* vals_dev, const double* B_dev, double* X_dev,
