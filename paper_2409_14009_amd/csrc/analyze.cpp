@@ -488,11 +488,30 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
         deferred.clear();
         close(S.factor_plan);
       }
+      // external update tiles: those with a target column in the next
+      // level run now; the others ("far": every target two or more levels
+      // up) go to a second launch marked `side`, which the runtime runs on a
+      // second stream beside the next level's panel chain (a chain alone
+      // leaves most of the GPU idle) and joins before the level after
+      std::vector<Task> far;
       open(S.factor_plan, K_UPD_EXT, (int32_t)l, -1);
       for (int32_t J : bylev[l]) {
-        for (int64_t c0 = K(J); c0 < M(J); c0 += kTile)
-          for (int64_t r0 = c0; r0 < M(J); r0 += kTile) S.tasks.push_back({J, (int32_t)r0, (int32_t)c0, -1});
+        const int32_t* R = S.rows.data() + S.rptr[J];
+        for (int64_t c0 = K(J); c0 < M(J); c0 += kTile) {
+          bool isfar = l + 2 < S.nlevels;
+          for (int64_t c = c0; c < std::min<int64_t>(c0 + kTile, M(J)) && isfar; ++c)
+            isfar = S.level[S.snode_of[R[c]]] > l + 1;
+          for (int64_t r0 = c0; r0 < M(J); r0 += kTile) {
+            const Task t{J, (int32_t)r0, (int32_t)c0, -1};
+            if (isfar) far.push_back(t);
+            else S.tasks.push_back(t);
+          }
+        }
       }
+      close(S.factor_plan);
+      open(S.factor_plan, K_UPD_EXT, (int32_t)l, -1);
+      S.factor_plan.back().side = 1;
+      S.tasks.insert(S.tasks.end(), far.begin(), far.end());
       close(S.factor_plan);
     }
     // forward solve: leaves to root, panels ascending; one launch per

@@ -208,6 +208,11 @@ struct CachedGraph {
 
 struct spchol_num_s {
   spchol_sym_s* sym = nullptr;
+  // second stream (default priority) for the external updates that run
+  // beside the next level's panel chain, and the events that fork and join it
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> side_ev;  // per level
   std::vector<CachedGraph> gcache;  // most recent last
   bool gcache_on = true;
   double* L = nullptr;
@@ -235,6 +240,10 @@ struct spchol_num_s {
   }
   ~spchol_num_s() {
     drop_graphs(-1);
+    for (hipEvent_t e : side_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (side) (void)hipStreamDestroy(side);
     if (Z) (void)hipFree(Z);
     if (sibuf) (void)hipFree(sibuf);
     if (lam) (void)hipFree(lam);
@@ -274,7 +283,30 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
   HIP_TRY(launch_status_init(N->status, st));
   HIP_TRY(timed(N, SPCHOL_KERNEL_SCATTER_A, 0.0, 24.0 * D.nnzA, st,
                 [&] { return launch_scatter_values(D, vals, N->L, st); }));
+  if (!N->side) {
+    // created before any capture (stream and event creation is not captured)
+    HIP_TRY(hipStreamCreateWithFlags(&N->side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&N->fork_ev, hipEventDisableTiming));
+    N->side_ev.assign(S.nlevels + 1, nullptr);
+    for (hipEvent_t& e : N->side_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  std::vector<int64_t> outstanding;  // levels whose side launch is not joined yet
   for (const Launch& l : S.factor_plan) {
+    if (l.side) {
+      // fork: the side stream starts once everything before is done
+      HIP_TRY(hipEventRecord(N->fork_ev, st));
+      HIP_TRY(hipStreamWaitEvent(N->side, N->fork_ev, 0));
+      HIP_TRY(timed(N, SPCHOL_KERNEL_UPDATE_EXT, l.flops, l.bytes, N->side,
+                    [&] { return launch_update(D, N->L, l.kind, l.off, l.ntasks, prec, N->side); }));
+      HIP_TRY(hipEventRecord(N->side_ev[l.level], N->side));
+      outstanding.push_back(l.level);
+      continue;
+    }
+    // join: a side launch of level v must be done before level v + 2
+    while (!outstanding.empty() && l.level >= outstanding.front() + 2) {
+      HIP_TRY(hipStreamWaitEvent(st, N->side_ev[outstanding.front()], 0));
+      outstanding.erase(outstanding.begin());
+    }
     if (l.kind == K_FACTOR_LA) {
       HIP_TRY(timed(N, SPCHOL_KERNEL_FACTOR, l.flops, l.bytes, st, [&] {
         return launch_factor_la(D, N->L, l.off, l.nfirst, l.ntasks, N->status, N->winv, prec, st);
@@ -288,6 +320,7 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
                     l.bytes, st, [&] { return launch_update(D, N->L, l.kind, l.off, l.ntasks, prec, st); }));
     }
   }
+  for (int64_t v : outstanding) HIP_TRY(hipStreamWaitEvent(st, N->side_ev[v], 0));
   return SPCHOL_OK;
 }
 
@@ -596,6 +629,13 @@ spchol_status spchol_factor_prec(spchol_sym sym, const double* vals_dev, int32_t
   if (e == hipSuccess) e = hipMalloc((void**)&N->red, (size_t)(logdet_partials(sym->S.n) + 1) * sizeof(double));
   if (e == hipSuccess)
     e = hipMalloc((void**)&N->winv, (size_t)(sym->S.wbase[sym->S.ns] > 0 ? sym->S.wbase[sym->S.ns] : 1) * sizeof(double));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&N->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&N->fork_ev, hipEventDisableTiming);
+  if (e == hipSuccess) {
+    N->side_ev.assign(sym->S.nlevels + 1, nullptr);
+    for (hipEvent_t& ev : N->side_ev)
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
     delete N;
     return fail(e == hipErrorOutOfMemory ? SPCHOL_ERR_OOM : SPCHOL_ERR_HIP,

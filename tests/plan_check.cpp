@@ -130,8 +130,23 @@ int main(int argc, char** argv) {
   };
 
   bool ok = true;
+  // a launch marked `side` (external updates of level v) runs beside the
+  // launches of level v + 1 and is joined before level v + 2: it is replayed
+  // at that point, after everything it may overlap with
+  std::vector<const Launch*> order, pending;
   for (const Launch& L : S.factor_plan) {
+    if (L.side) { pending.push_back(&L); continue; }
+    while (!pending.empty() && L.level >= pending.front()->level + 2) {
+      order.push_back(pending.front());
+      pending.erase(pending.begin());
+    }
+    order.push_back(&L);
+  }
+  for (const Launch* Lp : pending) order.push_back(Lp);
+  for (const Launch* Lp : order) {
+    const Launch& L = *Lp;
     ++g_launch;
+    if (L.side && L.kind != K_UPD_EXT) ok = fail("side launch that is not an external update");
     for (int32_t q = 0; q < L.ntasks && ok; ++q) {
       const Task& t = S.tasks[L.off + q];
       int32_t kind = L.kind;

@@ -178,3 +178,39 @@ def test_solve_only_graph():
     G.close()
     with pytest.raises(sc.SpcholError):
         F.capture(None, None, stream=stream)
+
+
+def test_graph_cache_repeated_calls():
+    """Repeated refactorizations / solves with the same buffers run eagerly,
+    then as a captured graph, then as replays: every call must see the
+    current contents of its buffers (values changed in place, new
+    right-hand sides), also after the solve workspace grows."""
+    p = gen.make_config(1, side=12)
+    S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, 0, 8)
+    v = torch.tensor(p.vals, device="cuda")
+    F = S.factor(v)
+    A = oracle.full_matrix(p.n, p.colptr, p.rowind, p.vals)
+    ld0 = oracle.Symbolic(p.n, p.colptr, p.rowind, p.perm, 0, 8).factor(p.vals).logdet()
+    rng = np.random.default_rng(5)
+    X = torch.empty((2, p.n), dtype=torch.float64, device="cuda")
+    for it, s in enumerate([1.0, 2.0, 0.5, 3.0, 1.0]):
+        v.copy_(torch.tensor(p.vals * s, device="cuda"))
+        F.refactor(v)
+        assert abs(F.logdet() - (ld0 + p.n * np.log(s))) <= 1e-11 * abs(ld0), it
+        B = rng.standard_normal((p.n, 2))
+        X.copy_(torch.tensor(B.T.copy(), device="cuda"))
+        F.solve_(X)
+        eta, _ = oracle.backward_error(A, X.cpu().numpy().T * s, B)
+        assert eta.max() <= 1e-12, (it, eta)
+    # a wider block moves the solve workspace: cached solves must follow
+    X4 = torch.tensor(rng.standard_normal((4, p.n)), device="cuda")
+    B4 = X4.cpu().numpy().T.copy()
+    for _ in range(3):
+        Y = X4.clone()
+        F.solve_(Y)
+        eta, _ = oracle.backward_error(A, Y.cpu().numpy().T, B4)
+        assert eta.max() <= 1e-12
+        X.copy_(torch.tensor(B[:, :2].T.copy(), device="cuda"))
+        F.solve_(X)
+        eta, _ = oracle.backward_error(A, X.cpu().numpy().T, B[:, :2])
+        assert eta.max() <= 1e-12
