@@ -369,6 +369,10 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
           if (diag) {
             for (int64_t j = 0; j < kp; ++j) fl += double(kp - j) * double(kp - j);
             by += 16.0 * double(kp * (kp + 1) / 2);
+            if (t.c == 1) {  // update of the diagonal block by the previous panel
+              fl += 2.0 * double(nb) * double(kp * (kp + 1) / 2);
+              by += 8.0 * double(nb) * double(kp);
+            }
           } else {
             by += 8.0 * double(kp * (kp + 1) / 2);
           }
@@ -429,32 +433,35 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       // holds panel p) is updated before that launch, the other tiles touch
       // only columns right of panel p and run beside its factorization
       std::vector<Task> deferred;
+      // How many rows below the block the diagonal task of round p solves
+      // itself: with many tasks in the launch, up to kTrsmRows (parallelism
+      // comes from the tasks); with few, none, so that the rows go to the
+      // parallel row-tile launch and the diagonal task (the sequential part)
+      // stays short -- unless every panel of the launch has at most one tile
+      // of rows, when the row-tile launch is skipped altogether.
+      std::vector<int64_t> inl_of(maxp + 1, 0);
       for (int64_t p = 0; p < maxp; ++p) {
-        // the tile holding the diagonal block factors it and writes it back;
-        // the other tiles of the panel run in a second launch that reads the
-        // factored block
-        // diagonal task: Cholesky of the block, its inverse, the first
-        // kTrsmRows rows below; a panel with more rows gets a scratch slot
-        // for the inverse, read by the row-tile tasks
-        // How many rows below the block the diagonal task solves itself:
-        // with many tasks in the launch, up to kTrsmRows (parallelism comes
-        // from the tasks); with few, none, so that the rows go to the
-        // parallel row-tile launch and the diagonal task (the sequential
-        // part) stays short -- unless every panel of the launch has at most
-        // one tile of rows, when the row-tile launch is skipped altogether.
         int64_t ntask = 0, maxrows = 0;
         for (int32_t J : bylev[l])
           if (npan(J) > p) {
             ++ntask;
             maxrows = std::max<int64_t>(maxrows, M(J) - (p * nb + kpan(J, p)));
           }
-        const int64_t inl = ntask >= kInlineMinTasks ? kTrsmRows : (maxrows <= kTile ? kTile : 0);
+        inl_of[p] = ntask >= kInlineMinTasks ? kTrsmRows : (maxrows <= kTile ? kTile : 0);
+      }
+      // With 64-column panels and no inline rows in round p + 1, the update
+      // of panel p + 1's columns by panel p needs no launch of its own: the
+      // diagonal task of round p + 1 applies it to its diagonal block first
+      // (task field c = 1), the tiles below run beside it
+      auto merged = [&](int64_t p) { return nb == kTile && p + 1 < maxp && inl_of[p + 1] == 0; };
+      for (int64_t p = 0; p < maxp; ++p) {
+        const int64_t inl = inl_of[p];
         open(S.factor_plan, K_FACTOR, (int32_t)l, (int32_t)p);
         for (int32_t J : bylev[l]) {
           if (npan(J) <= p) continue;
           const int64_t rb = p * nb + kpan(J, p);
           // b: first row the task solves inline (== m: none)
-          S.tasks.push_back({J, (int32_t)p, (int32_t)(inl > 0 ? rb : M(J)), 0});
+          S.tasks.push_back({J, (int32_t)p, (int32_t)(inl > 0 ? rb : M(J)), (p > 0 && merged(p - 1)) ? 1 : 0});
         }
         S.factor_plan.back().nfirst = (int32_t)((int64_t)S.tasks.size() - S.factor_plan.back().off);
         if (!deferred.empty()) {
@@ -476,8 +483,9 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
           for (int64_t c0 = (p + 1) * nb; c0 < K(J); c0 += kTile)
             for (int64_t r0 = c0; r0 < M(J); r0 += kTile) {
               const Task t{J, (int32_t)r0, (int32_t)c0, (int32_t)p};
-              if (c0 == (p + 1) * nb) S.tasks.push_back(t);
-              else deferred.push_back(t);
+              if (c0 != (p + 1) * nb) deferred.push_back(t);
+              else if (!merged(p)) S.tasks.push_back(t);
+              else if (r0 != c0) deferred.push_back(t);  // (r0 == c0: done by the diagonal task)
             }
         }
         close(S.factor_plan);

@@ -10,7 +10,9 @@ namespace spchol {
 
 // Work item of a batched launch.  Meaning of the fields per launch kind:
 //   FACTOR     J, panel, first local row the task solves itself (up to
-//              kTrsmRows rows from there; == m_J: none), -
+//              kTrsmRows rows from there; == m_J: none), 1 when the task
+//              first applies the previous panel's update to its diagonal
+//              block (else 0)
 //   FACTOR_LA  the first `nfirst` tasks are FACTOR tasks, the others
 //              UPD_INT tiles of the previous panel that do not touch the
 //              panel being factored (one-panel lookahead)

@@ -131,12 +131,9 @@ __device__ __forceinline__ void potrf16(double (&r)[MB], int lane, int j0, unsig
 // the fp64 matrix cores and stores sign * X to rows R0 + r < rowEnd of dst
 // (dst[c * ld + row]); with lower set only entries row >= R0 + c are stored.
 // K = kp (columns past kp are zero in As).
-__device__ __forceinline__ void tile_mfma(const double* __restrict__ As, const double* __restrict__ Wc, int kp,
-                                          int lane, int w, double* __restrict__ dst, int ld, int R0, int rowEnd,
-                                          bool lower, double sign) {
-  if (MB * w >= kp) return;
+__device__ __forceinline__ void tile_mfma_acc(const double* __restrict__ As, const double* __restrict__ Wc, int kp,
+                                              int lane, int w, d4 (&acc)[4]) {
   const int li = lane & 15, lk = lane >> 4;
-  d4 acc[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
   // k in chunks of 16: all LDS operands of a chunk are read before its
@@ -155,6 +152,15 @@ __device__ __forceinline__ void tile_mfma(const double* __restrict__ As, const d
       for (int rb2 = 0; rb2 < 4; ++rb2)
         acc[rb2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][rb2], bv[s], acc[rb2], 0, 0, 0);
   }
+}
+
+__device__ __forceinline__ void tile_mfma(const double* __restrict__ As, const double* __restrict__ Wc, int kp,
+                                          int lane, int w, double* __restrict__ dst, int ld, int R0, int rowEnd,
+                                          bool lower, double sign) {
+  if (MB * w >= kp) return;
+  const int li = lane & 15, lk = lane >> 4;
+  d4 acc[4];
+  tile_mfma_acc(As, Wc, kp, lane, w, acc);
   const int c = MB * w + li;
   if (c < kp) {
     double* d = dst + (int64_t)c * ld;
@@ -258,6 +264,7 @@ __device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__
   double* __restrict__ Dc = smem;
   double* __restrict__ Wc = smem + NBMAX * DLD;
   const int J = t.J, p = t.a, rb = t.b;
+  const bool pre = t.c == 1;
   const int m = S.sm[J], k = S.sk[J];
   const int c0 = p * S.nb;
   const int kp = min(S.nb, k - c0);
@@ -284,6 +291,30 @@ __device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__
     }
   }
   __syncthreads();
+
+  // 0. (c = 1) the previous panel's update of the diagonal block,
+  //    D -= A A^T with A = rows c0..c0+kp of panel p - 1, on the matrix
+  //    cores (A staged in Wc, which is cleared again afterwards)
+  if (pre) {
+    stage_rows(Wc, L + S.loff[J] + (int64_t)(c0 - S.nb) * m, m, S.nb, c0, tid, 256);
+    __syncthreads();
+    d4 acc[4];
+    tile_mfma_acc(Wc, Wc, S.nb, lane, w, acc);
+    const int c = MB * w + (lane & 15), lk = lane >> 4;
+#pragma unroll
+    for (int rb2 = 0; rb2 < 4; ++rb2)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * rb2 + 4 * v + lk;
+        if (r < kp && c <= r) Dc[c * DLD + r] -= acc[rb2][v];
+        // a last, narrower panel: rows kp..63 of the tile lie below its
+        // diagonal block, in storage (the row-tile launch reads them next)
+        else if (r >= kp && c < kp && c0 + r < m) Lp[(int64_t)c * m + c0 + r] -= acc[rb2][v];
+      }
+    __syncthreads();
+    for (int idx = tid; idx < NBMAX * DLD; idx += 256) Wc[idx] = 0.0;
+    __syncthreads();
+  }
 
   // 1. Cholesky of the diagonal block, right-looking over 16-column blocks:
   //    wavefront 0 sweeps block column b (rows >= 16b), then the four

@@ -155,6 +155,20 @@ int main(int argc, char** argv) {
       if (kind == K_FACTOR || kind == K_TRSM) {
         const int64_t c0 = int64_t(t.a) * nb, kp = std::min<int64_t>(nb, k - c0);
         if (kind == K_FACTOR) {
+          if (t.c == 1) {  // the previous panel's update of the diagonal block
+            if (t.a == 0) ok = fail("diagonal pre-update without a previous panel");
+            const int64_t cp = c0 - nb;
+            // the whole first 64-row tile of the panel's columns
+            const int64_t rE = std::min<int64_t>(c0 + kTile, m);
+            for (int64_t c = c0; c < c0 + kp && ok; ++c)
+              for (int64_t r = c; r < rE && ok; ++r) {
+                for (int64_t s2 = cp; s2 < c0 && ok; ++s2) ok = need_solved(idx(J, s2, r), q) && need_solved(idx(J, s2, c), q);
+                if (r >= c0 + kp) ok = ok && on_write(acc, idx(J, c, r), q, false);
+                got[idx(J, c, r)] += 1;
+              }
+          } else if (t.c != 0) {
+            ok = fail("unexpected FACTOR task flag");
+          }
           for (int64_t c = c0; c < c0 + kp && ok; ++c)
             for (int64_t r = c; r < c0 + kp && ok; ++r) ok = need_complete(idx(J, c, r), q) && solve_entry(idx(J, c, r), q);
           const int64_t re = std::min<int64_t>(int64_t(t.b) + kTrsmRows, m);
