@@ -118,3 +118,13 @@ def test_bf16_update_error_size():
     r = residual_rel(permuted_matrix(oracle.full_matrix(n, cp, ri, vv), perm), Lg)
     print(f"  bf16 residual {r:.2e}", flush=True)
     assert 1e-5 <= r <= 2e-2
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_mixed_with_wide_supernodes(prec):
+    """An 18^3 grid has supernodes of >= 128 columns with external updates,
+    so the reduced-precision products run over long inner dimensions;
+    refinement must still reach 1e-12."""
+    p = gen.make_config(4, side=18)
+    S, F, it = _case(p, 8, prec)
+    assert it >= 1

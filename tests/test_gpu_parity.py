@@ -169,3 +169,13 @@ def test_empty_and_one():
     S0 = sc.SparseCholesky(0, np.array([0]), np.zeros(0, np.int64))
     F0 = S0.factor(torch.zeros(0, device=DEV, dtype=torch.float64))
     assert F0.logdet() == 0.0
+
+
+def test_wide_supernodes_big_tiles():
+    """18^3 7-point grid: separators of >= 128 columns that still update
+    their ancestors (several panels feeding multi-tile external updates)."""
+    p = gen.make_config(1, side=18)
+    e = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, 0, 8).export()
+    k = np.diff(e["super_ptr"]); m = np.diff(e["row_ptr"])
+    assert ((k >= 128) & (m > k)).any()
+    run_case(p.n, p.colptr, p.rowind, p.vals, p.perm, p.B, 0, 8, 64, well_conditioned=False)

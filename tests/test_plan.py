@@ -43,7 +43,7 @@ def test_grid2d(checker, tmp_path, nb):
     _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, 0, nb)
 
 
-@pytest.mark.parametrize("side,z,nb", [(10, 8, 64), (12, 8, 32), (9, 0, 48), (11, 30, 16)])
+@pytest.mark.parametrize("side,z,nb", [(10, 8, 64), (12, 8, 32), (9, 0, 48), (11, 30, 16), (20, 8, 64)])
 def test_grid3d(checker, tmp_path, side, z, nb):
     p = gen.make_config(1, side=side)
     _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, z, nb)
