@@ -644,9 +644,12 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
   }
 }
 
-// kind 1: internal update tiles, kind 2: external (scattered) update tiles
+// kind 1: internal update tiles, kind 2: external (scattered) update tiles.
+// Four workgroups per compute unit (at most 128 registers a lane): while
+// some apply their scatter, the others keep the matrix cores busy.
 template <int P, int kind>
-__global__ __launch_bounds__(256) void k_update(DevSym S, double* __restrict__ L, int64_t off) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_update(DevSym S, double* __restrict__ L,
+                                                                                          int64_t off) {
   __shared__ __attribute__((aligned(16))) double smem[UPD_SMEM];
   update_body<P, kind>(S, L, S.tasks[off + blockIdx.x], smem);
 }
