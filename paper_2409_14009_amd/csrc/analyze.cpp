@@ -392,8 +392,7 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
           break;
         }
         case K_FWD:
-        case K_BWD:
-        case K_BWD_FIN: {
+        case K_BWD: {
           // the rows of L below the panel that the task covers, read once;
           // their entries of y / x; the panel's inverted diagonal block once
           // per panel
@@ -403,11 +402,9 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
           if (kind == K_FWD) {
             nr = t.b < 0 ? 0 : std::min<int64_t>(t.b + kTile, m) - t.b;
             once = t.c == 1;
-          } else if (kind == K_BWD) {
-            nr = t.c < 0 ? m - t.b : std::min<int64_t>(t.b + kTile, m) - t.b;
-            once = t.c < 0;
           } else {
-            once = true;
+            nr = t.c < 0 ? m - t.b : (t.c == 0 ? std::min<int64_t>(t.b + kTile, m) - t.b : int64_t(t.c) - 1);
+            once = t.c != 0;
           }
           fl += 2.0 * double(nr) * double(kp) + (once ? double(kp) * double(kp) : 0.0);
           by += 8.0 * double(nr) * double(kp) + 16.0 * double(nr) + (once ? 8.0 * double(kp * (kp + 1) / 2) : 0.0);
@@ -541,30 +538,42 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
         close(S.fwd_plan);
       }
     }
-    // backward solve: root to leaves, panels descending.  A panel with at
-    // most kBwdRows rows below is done by one task (c = -1: gather, then the
-    // inverted diagonal block); a taller one by 64-row tiles (c = 0) that add
-    // their share into an accumulator, finished by a task of a second
-    // launch of the round (BWD_FIN)
+    // backward solve: root to leaves, panels descending, one launch per
+    // round.  A panel with at most kBwdRows rows below is done by one task
+    // (c = -1: gather, then the inverted diagonal block).  A taller one is
+    // split with a one-panel lookahead: its far rows (past the next panel,
+    // whose solution is final one round earlier) are added into an
+    // accumulator by 64-row tiles (c = 0) in the launch of the round before,
+    // and its finishing task (c = 1 + n) gathers the n rows of the next
+    // panel, subtracts the accumulator and applies the inverse.  The far
+    // tiles of a level's first round run in a launch of their own.
     for (int64_t l = S.nlevels - 1; l >= 0; --l) {
       int64_t maxp = 0;
       for (int32_t J : bylev[l]) maxp = std::max(maxp, npan(J));
+      auto below = [&](int32_t J, int64_t p) { return p * nb + kpan(J, p); };
+      auto split = [&](int32_t J, int64_t p) { return p >= 0 && p < npan(J) && M(J) - below(J, p) > kBwdRows; };
+      auto near = [&](int32_t J, int64_t p) { return p + 1 < npan(J) ? kpan(J, p + 1) : int64_t(0); };
+      auto far_tiles = [&](int32_t J, int64_t p) {
+        for (int64_t r0 = below(J, p) + near(J, p); r0 < M(J); r0 += kTile)
+          S.tasks.push_back({J, (int32_t)p, (int32_t)r0, 0});
+      };
+      bool pro = false;
+      for (int32_t J : bylev[l]) pro = pro || split(J, maxp - 1);
+      if (pro) {
+        open(S.bwd_plan, K_BWD, (int32_t)l, (int32_t)maxp);
+        for (int32_t J : bylev[l])
+          if (split(J, maxp - 1)) far_tiles(J, maxp - 1);
+        close(S.bwd_plan);
+      }
       for (int64_t p = maxp - 1; p >= 0; --p) {
-        std::vector<int32_t> split;
         open(S.bwd_plan, K_BWD, (int32_t)l, (int32_t)p);
         for (int32_t J : bylev[l]) {
           if (npan(J) <= p) continue;
-          const int64_t below = p * nb + kpan(J, p);
-          if (M(J) - below <= kBwdRows) {
-            S.tasks.push_back({J, (int32_t)p, (int32_t)below, -1});
-          } else {
-            split.push_back(J);
-            for (int64_t r0 = below; r0 < M(J); r0 += kTile) S.tasks.push_back({J, (int32_t)p, (int32_t)r0, 0});
-          }
+          if (split(J, p)) S.tasks.push_back({J, (int32_t)p, (int32_t)below(J, p), (int32_t)(1 + near(J, p))});
+          else S.tasks.push_back({J, (int32_t)p, (int32_t)below(J, p), -1});
         }
-        close(S.bwd_plan);
-        open(S.bwd_plan, K_BWD_FIN, (int32_t)l, (int32_t)p);
-        for (int32_t J : split) S.tasks.push_back({J, (int32_t)p, 0, 0});
+        for (int32_t J : bylev[l])
+          if (split(J, p - 1)) far_tiles(J, p - 1);
         close(S.bwd_plan);
       }
     }

@@ -22,10 +22,10 @@ namespace spchol {
 //   UPD_EXT    J, first local row, first local col, -1
 //   FWD        J, panel, first local row of a 64-row tile below the panel
 //              (-1: the panel has no rows below), 1 on the panel's first task
-//   BWD        J, panel, first local row below the panel, -1 (the task
-//              does all rows and the diagonal block) or 0 (one 64-row tile,
-//              summed into the accumulator)
-//   BWD_FIN    J, panel, -, -  (the diagonal block of a tiled panel)
+//   BWD        J, panel, first local row of the task's rows, and -1 (all
+//              rows below the panel, then the diagonal block), 0 (one 64-row
+//              tile, summed into the accumulator) or 1 + n (n rows, then the
+//              accumulator and the diagonal block)
 struct Task {
   int32_t J, a, b, c;
 };
@@ -35,8 +35,7 @@ enum Kind : int32_t {
   K_UPD_INT = 1,
   K_UPD_EXT = 2,
   K_FWD = 3,    // forward solve round: inverse-block product + panel update
-  K_BWD = 4,    // backward solve round: panel gather (+ inverse-block product)
-  K_BWD_FIN = 5,  // backward solve: inverse-block product of split panels
+  K_BWD = 4,    // backward solve round: panel gathers, inverse-block products
   K_TRSM = 7,
   K_SI_W = 8,   // (unused: the factorization stores the inverted diagonal blocks)
   K_SI_Y = 9,   // Y = Z_BB L_Bp tiles

@@ -804,9 +804,12 @@ __device__ __forceinline__ double apply_wt(double (*Ws)[NBMAX + 1], const double
 // task gathers L_Rp^T x_R over all rows below the panel (x_R is final:
 // later panels and ancestors were done in earlier rounds), then forms
 // x_p = W_p^T (x_p - L_Rp^T x_R).  c = 0: the task adds the share of one
-// 64-row tile into acc_p; a BWD_FIN task of the next launch finishes the
-// panel.  Each 64-row chunk of L is staged in LDS (coalesced) once per four
-// right-hand sides; thread (lane, w) sums column lane over rows 16w..16w+15.
+// 64-row tile into acc_p (a round ahead of the panel).  c = 1 + n: the
+// task gathers the n rows from rb (the next panel's, finished in the round
+// before), subtracts acc_p, leaves acc_p at zero for the next solve and
+// finishes the panel.  Each 64-row chunk of L is staged in LDS (coalesced)
+// once per four right-hand sides; thread (lane, w) sums column lane over
+// rows 16w..16w+15.
 __global__ __launch_bounds__(256) void k_bwd(DevSym S, const double* __restrict__ L, const double* __restrict__ winv,
                                              int64_t off, double* __restrict__ x, double* __restrict__ acc,
                                              int64_t nrhs) {
@@ -816,14 +819,14 @@ __global__ __launch_bounds__(256) void k_bwd(DevSym S, const double* __restrict_
   __shared__ double vs[4][NBMAX];
   const DevTask t = S.tasks[off + blockIdx.x];
   const int J = t.J, p = t.a, rb = t.b;
-  const bool whole = t.c < 0;
+  const bool fin = t.c != 0, useacc = t.c > 0;
   const int m = S.sm[J], k = S.sk[J];
   const int c0 = p * S.nb, kp = min(S.nb, k - c0);
   const double* __restrict__ Lj = L + S.loff[J];
   const int32_t* __restrict__ R = S.rows + S.rptr[J];
   const int64_t fcol = S.sfirst[J] + c0;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int re = whole ? m : min(m, rb + TILE);
+  const int re = t.c < 0 ? m : (t.c == 0 ? min(m, rb + TILE) : rb + t.c - 1);
   for (int64_t cb = 0; cb < nrhs; cb += 4) {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for (int r0 = rb; r0 < re; r0 += TILE) {
@@ -851,44 +854,22 @@ __global__ __launch_bounds__(256) void k_bwd(DevSym S, const double* __restrict_
     {
       const int q = w, i = lane;  // thread (lane, w): entry lane of RHS cb + w
       const int64_t c = cb + q;
-      const double v = (red[0][q][i] + red[1][q][i]) + (red[2][q][i] + red[3][q][i]);
-      if (whole) vs[q][i] = (i < kp && c < nrhs) ? x[fcol + i + c * S.n] - v : 0.0;
-      else if (i < kp && c < nrhs) atomicAdd(acc + fcol + i + c * S.n, v);
+      const bool ok = i < kp && c < nrhs;
+      double v = (red[0][q][i] + red[1][q][i]) + (red[2][q][i] + red[3][q][i]);
+      if (useacc && ok) {
+        double* ap = acc + fcol + i + c * S.n;
+        v += *ap;
+        *ap = 0.0;
+      }
+      if (fin) vs[q][i] = ok ? x[fcol + i + c * S.n] - v : 0.0;
+      else if (ok) atomicAdd(acc + fcol + i + c * S.n, v);
     }
     __syncthreads();
-    if (whole) {
+    if (fin) {
       stage_w(winv + S.wbase[J] + (int64_t)p * S.nb * S.nb, kp, Ls, tid, 256);
       __syncthreads();
       if (lane < kp && cb + w < nrhs) x[fcol + lane + (cb + w) * S.n] = apply_wt(Ls, vs[w], lane);
     }
-  }
-}
-
-// Backward, second launch of a round: x_p = W_p^T (x_p - acc_p) for the
-// panels split into tiles; acc_p is left at zero for the next solve.
-__global__ __launch_bounds__(256) void k_bwd_fin(DevSym S, const double* __restrict__ winv, int64_t off,
-                                                 double* __restrict__ x, double* __restrict__ acc, int64_t nrhs) {
-  __shared__ double Ws[NBMAX][NBMAX + 1];
-  __shared__ double vs[4][NBMAX];
-  const DevTask t = S.tasks[off + blockIdx.x];
-  const int J = t.J, p = t.a;
-  const int k = S.sk[J];
-  const int c0 = p * S.nb, kp = min(S.nb, k - c0);
-  const int64_t fcol = S.sfirst[J] + c0;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  stage_w(winv + S.wbase[J] + (int64_t)p * S.nb * S.nb, kp, Ws, tid, 256);
-  for (int64_t cb = 0; cb < nrhs; cb += 4) {
-    const int64_t c = cb + w;  // thread (lane, w): entry lane of RHS cb + w
-    if (lane < kp && c < nrhs) {
-      double* ap = acc + fcol + lane + c * S.n;
-      vs[w][lane] = x[fcol + lane + c * S.n] - *ap;
-      *ap = 0.0;
-    } else {
-      vs[w][lane] = 0.0;
-    }
-    __syncthreads();
-    if (lane < kp && c < nrhs) x[fcol + lane + c * S.n] = apply_wt(Ws, vs[w], lane);
-    __syncthreads();
   }
 }
 
@@ -1332,8 +1313,7 @@ hipError_t launch_solve_step(const DevSym& S, const double* L, const double* win
                              int32_t ntasks, double* y, double* x, double* acc, int64_t nrhs, hipStream_t st) {
   if (ntasks <= 0) return hipSuccess;
   if (kind == 3) k_fwd<<<ntasks, 256, 0, st>>>(S, L, winv, off, y, x, nrhs);
-  else if (kind == 4) k_bwd<<<ntasks, 256, 0, st>>>(S, L, winv, off, x, acc, nrhs);
-  else k_bwd_fin<<<ntasks, 256, 0, st>>>(S, winv, off, x, acc, nrhs);
+  else k_bwd<<<ntasks, 256, 0, st>>>(S, L, winv, off, x, acc, nrhs);
   return hipGetLastError();
 }
 

@@ -247,23 +247,23 @@ int main(int argc, char** argv) {
     }
     for (int64_t i = 0; i < N && ok; ++i)
       if (!xdone[i] || yg[i] != ye[i]) ok = fail("forward solve incomplete");
-    // backward: a panel is done by its single task (c = -1) or, when split
-    // into row tiles (c = 0), by its finishing task of the next launch once
-    // every tile ran; tasks read x below the panel, which must be done, and
-    // not in the same launch
+    // backward: a panel is done by its single task (c = -1) or, when split,
+    // by 64-row tiles (c = 0) summed into its accumulator and a finishing
+    // task (c = 1 + n, n rows of its own) in a later launch; every row below
+    // the panel is gathered exactly once; tasks read x below the panel,
+    // which must be done, and not in the same launch
     std::vector<char> bdone(N, 0);
-    std::vector<int64_t> fin_launch(N, -1), tiles_seen(N, 0), tiles_need(N, 0);
-    for (int64_t J = 0; J < ns; ++J)
-      for (int64_t p = 0; p * nb < K(J); ++p) {
-        const int64_t below = p * nb + std::min<int64_t>(nb, K(J) - p * nb);
-        tiles_need[S.sptr[J] + p * nb] = (M(J) - below + kTile - 1) / kTile;
-      }
+    std::vector<int64_t> fin_launch(N, -1), tile_launch(N, -1);
+    std::vector<std::vector<char>> gathered(N);
     for (const Launch& L : S.bwd_plan) {
       ++g_launch;
+      if (L.kind != K_BWD) { ok = fail("unknown launch kind in the backward plan"); break; }
       for (int32_t q = 0; q < L.ntasks && ok; ++q) {
         const Task& t = S.tasks[L.off + q];
         const int64_t J = t.J, c0 = int64_t(t.a) * nb, kp = std::min<int64_t>(nb, K(J) - c0);
         const int64_t f0 = S.sptr[J] + c0, below = c0 + kp;
+        std::vector<char>& seen = gathered[f0];
+        if (seen.empty()) seen.assign(M(J) - below + 1, 0);
         auto finish = [&]() {
           for (int64_t i = 0; i < kp && ok; ++i) {
             if (bdone[f0 + i]) ok = fail("backward solution written twice");
@@ -271,25 +271,35 @@ int main(int argc, char** argv) {
             fin_launch[f0 + i] = g_launch;
           }
         };
-        auto read_rows = [&](int64_t r0, int64_t r1) {
+        auto gather = [&](int64_t r0, int64_t r1) {
+          if (r0 < below || r1 > M(J)) { ok = fail("backward task rows outside the rows below its panel"); return; }
+          if (bdone[f0]) { ok = fail("rows gathered for a panel already finished"); return; }
           for (int64_t r = r0; r < r1 && ok; ++r) {
             const int64_t g = S.rows[S.rptr[J] + r];
-            if (!bdone[g]) ok = fail("backward solve reads a row that is not solved");
+            if (seen[r - below]) ok = fail("a row gathered twice for one panel");
+            else if (!bdone[g]) ok = fail("backward solve reads a row that is not solved");
             else if (fin_launch[g] == g_launch) ok = fail("backward solve reads a row solved in the same launch");
+            seen[r - below] = 1;
           }
         };
-        if (L.kind == K_BWD && t.c < 0) {
+        auto all_gathered = [&]() {
+          for (int64_t r = below; r < M(J) && ok; ++r)
+            if (!seen[r - below]) ok = fail("panel finished before all rows below it were gathered");
+        };
+        if (t.c < 0) {
           if (t.b != below) ok = fail("whole-panel task does not start below the panel");
-          read_rows(t.b, M(J));
+          gather(t.b, M(J));
+          all_gathered();
           finish();
-        } else if (L.kind == K_BWD) {
-          read_rows(t.b, std::min<int64_t>(int64_t(t.b) + kTile, M(J)));
-          tiles_seen[f0] += 1;
-        } else if (L.kind == K_BWD_FIN) {
-          if (tiles_seen[f0] != tiles_need[f0]) ok = fail("panel finished before all its row tiles");
-          finish();
+        } else if (t.c == 0) {
+          gather(t.b, std::min<int64_t>(int64_t(t.b) + kTile, M(J)));
+          tile_launch[f0] = g_launch;
         } else {
-          ok = fail("unknown launch kind in the backward plan");
+          if (t.b != below) ok = fail("finishing task does not start below the panel");
+          if (tile_launch[f0] == g_launch) ok = fail("panel finished in the launch of one of its tiles");
+          gather(t.b, int64_t(t.b) + t.c - 1);
+          all_gathered();
+          finish();
         }
       }
       if (!ok) break;
@@ -301,6 +311,10 @@ int main(int argc, char** argv) {
     std::printf("violation (launch %lld): %s\n", (long long)g_launch, g_err.c_str());
     return 1;
   }
-  std::printf("ok launches=%zu+%zu+%zu\n", S.factor_plan.size(), S.fwd_plan.size(), S.bwd_plan.size());
+  int64_t bsplit = 0;
+  for (const Launch& L : S.bwd_plan)
+    for (int32_t q = 0; q < L.ntasks; ++q) bsplit += S.tasks[L.off + q].c > 0;
+  std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld\n", S.factor_plan.size(), S.fwd_plan.size(), S.bwd_plan.size(),
+              (long long)bsplit);
   return 0;
 }
