@@ -694,6 +694,14 @@ __global__ void k_perm_scatter(const int64_t* __restrict__ perm, int64_t n, cons
 // forward: y_p <- D_p^{-1} y_p, one wavefront per (J, panel); lane i owns
 // row i, column sweep: y_j is final, broadcast with readlane, subtracted
 // from the rows below
+// A value the compiler must treat as produced here (an empty asm, no
+// instruction): keeps the use of a prefetched load, and the wait for it, at
+// this point instead of hoisted next to the load, ahead of later loads.
+__device__ __forceinline__ double here(double v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // Forward round, one task per 64-row tile below a panel (Sec. II: the
 // supernodal forward substitution).  Every task forms z_p = W_p y_p with the
 // stored inverse of the panel's diagonal block (y_p is final: all panels and
@@ -723,24 +731,35 @@ __global__ __launch_bounds__(256) void k_fwd(DevSym S, const double* __restrict_
   const int t0 = 16 * w, t1 = min(kp, t0 + 16);
   const int row = r0 + lane;
   const bool rowok = r0 >= 0 && row < m;
-  for (int64_t cb = 0; cb < nrhs; cb += 4) {
+  // the thread's 16 entries of W and of the tile of L, the same for every
+  // block of right-hand sides: loaded once, all at the start, from clamped
+  // (in-bounds, finite) addresses and zeroed past kp / m by a factor, so
+  // that no load waits behind a branch of its own
+  double wr[16], lr[16];
+  const int32_t grow = R[rowok ? row : 0];  // the row this lane updates
+  {
+    const int il = min(lane, kp - 1), rl = rowok ? row : 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int tt = t0 + u, tc = min(tt, kp - 1);
+      wr[u] = W[(int64_t)tc * kp + il];
+      lr[u] = Lj[(int64_t)(c0 + tc) * m + rl];
+    }
+  }
+  // one block of four right-hand sides; the first block is peeled off the
+  // loop (no wait at a loop header for the loads above)
+  auto block = [&](int64_t cb) {
     {
       const int64_t c = cb + w;  // thread (lane, w) loads entry lane of RHS cb + w
       ys[w][lane] = (lane < kp && c < nrhs) ? y[fcol + lane + c * S.n] : 0.0;
     }
     __syncthreads();
-    // 16 independent loads per thread (clamped in bounds, zero past kp)
     double z[4] = {0.0, 0.0, 0.0, 0.0};
-    {
-      const int il = min(lane, kp - 1);
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int tt = t0 + u;
-        const double wv0 = W[(int64_t)min(tt, kp - 1) * kp + il];
-        const double wv = (tt < t1 && lane < kp) ? wv0 : 0.0;
+    for (int u = 0; u < 16; ++u) {
+      const double wv = here(wr[u]) * ((t0 + u < t1 && lane < kp) ? 1.0 : 0.0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) z[q] = fma(wv, ys[q][tt], z[q]);
-      }
+      for (int q = 0; q < 4; ++q) z[q] = fma(wv, ys[q][t0 + u], z[q]);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) part[w][q][lane] = z[q];
@@ -753,16 +772,11 @@ __global__ __launch_bounds__(256) void k_fwd(DevSym S, const double* __restrict_
     }
     __syncthreads();
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    {
-      const int rl = rowok ? row : 0;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int tt = t0 + u;
-        const double lv0 = Lj[(int64_t)(c0 + min(tt, kp - 1)) * m + rl];
-        const double lv = (tt < t1 && rowok) ? lv0 : 0.0;
+    for (int u = 0; u < 16; ++u) {
+      const double lv = here(lr[u]) * ((t0 + u < t1 && rowok) ? 1.0 : 0.0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = fma(lv, zs[q][tt], a[q]);
-      }
+      for (int q = 0; q < 4; ++q) a[q] = fma(lv, zs[q][t0 + u], a[q]);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) part[w][q][lane] = a[q];
@@ -770,15 +784,17 @@ __global__ __launch_bounds__(256) void k_fwd(DevSym S, const double* __restrict_
     {
       const int q = w, i = lane;
       const int64_t c = cb + q;
-      if (r0 >= 0 && r0 + i < m && c < nrhs) {
+      if (rowok && c < nrhs) {
         const double v = (part[0][q][i] + part[1][q][i]) + (part[2][q][i] + part[3][q][i]);
-        double* dst = y + R[r0 + i] + c * S.n;
+        double* dst = y + grow + c * S.n;
         if (r0 + i < k) *dst -= v;
         else atomicAdd(dst, -v);
       }
     }
     __syncthreads();
-  }
+  };
+  block(0);
+  for (int64_t cb = 4; cb < nrhs; cb += 4) block(cb);
 }
 
 // The panel's inverted diagonal block (kp x kp, column-major) into LDS,
@@ -810,7 +826,7 @@ __device__ __forceinline__ double apply_wt(double (*Ws)[NBMAX + 1], const double
 // finishes the panel.  Each 64-row chunk of L is staged in LDS (coalesced)
 // once per four right-hand sides; thread (lane, w) sums column lane over
 // rows 16w..16w+15.
-__global__ __launch_bounds__(256) void k_bwd(DevSym S, const double* __restrict__ L, const double* __restrict__ winv,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_bwd(DevSym S, const double* __restrict__ L, const double* __restrict__ winv,
                                              int64_t off, double* __restrict__ x, double* __restrict__ acc,
                                              int64_t nrhs) {
   __shared__ double Ls[TILE][NBMAX + 1];
@@ -827,18 +843,48 @@ __global__ __launch_bounds__(256) void k_bwd(DevSym S, const double* __restrict_
   const int64_t fcol = S.sfirst[J] + c0;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int re = t.c < 0 ? m : (t.c == 0 ? min(m, rb + TILE) : rb + t.c - 1);
-  for (int64_t cb = 0; cb < nrhs; cb += 4) {
+  // a finishing task loads the panel's inverse block at the start (thread
+  // tid holds entries u * 256 + tid, column-major, zero past kp), beside the
+  // gather's loads rather than after them
+  double wv[NBMAX * NBMAX / 256];
+  if (fin) {
+    const double* __restrict__ W = winv + S.wbase[J] + (int64_t)p * S.nb * S.nb;
+#pragma unroll
+    for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+      const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;
+      wv[u] = W[min(c, kp - 1) * kp + min(r, kp - 1)];  // (zeroed past kp when staged)
+    }
+  }
+  // one block of four right-hand sides, and in it one 64-row chunk; the
+  // first block and its first chunk are peeled off the loops (no wait at a
+  // loop header for the loads issued before)
+  auto block = [&](int64_t cb) {
+    // this block's entries of x_p and acc_p for thread (lane, w), issued
+    // before the gather
+    const int64_t cq = cb + w;
+    const bool okq = lane < kp && cq < nrhs;
+    const int64_t eq = fcol + (okq ? lane + cq * S.n : 0);
+    const double xq = fin ? x[eq] : 0.0;
+    const double aq = useacc ? acc[eq] : 0.0;
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int r0 = rb; r0 < re; r0 += TILE) {
+    auto chunk = [&](int r0) {
       const int nr = min(TILE, re - r0);
+      const int32_t gr = R[r0 + min(lane, nr - 1)];  // row lane of the chunk (clamped)
+      double lv[TILE * NBMAX / 256];
+#pragma unroll
+      for (int u = 0; u < TILE * NBMAX / 256; ++u) {
+        const int idx = u * 256 + tid, r = idx & (TILE - 1), tt = idx / TILE;
+        lv[u] = Lj[(int64_t)(c0 + min(tt, kp - 1)) * m + r0 + min(r, nr - 1)] * ((r < nr && tt < kp) ? 1.0 : 0.0);
+      }
       __syncthreads();
-      for (int idx = tid; idx < TILE * kp; idx += 256) {
-        const int r = idx & (TILE - 1), tt = idx / TILE;
-        Ls[r][tt] = r < nr ? Lj[(int64_t)(c0 + tt) * m + r0 + r] : 0.0;
+#pragma unroll
+      for (int u = 0; u < TILE * NBMAX / 256; ++u) {
+        const int idx = u * 256 + tid;
+        Ls[idx & (TILE - 1)][idx / TILE] = lv[u];
       }
       {
         const int64_t c = cb + w;  // thread (lane, w) loads row lane for RHS cb + w
-        xs[w][lane] = (lane < nr && c < nrhs) ? x[R[r0 + lane] + c * S.n] : 0.0;
+        xs[w][lane] = (lane < nr && c < nrhs) ? x[gr + c * S.n] : 0.0;
       }
       __syncthreads();
       if (lane < kp)
@@ -847,30 +893,32 @@ __global__ __launch_bounds__(256) void k_bwd(DevSym S, const double* __restrict_
 #pragma unroll
           for (int q = 0; q < 4; ++q) a[q] = fma(lv, xs[q][r], a[q]);
         }
-    }
+    };
+    if (rb < re) chunk(rb);
+    for (int r0 = rb + TILE; r0 < re; r0 += TILE) chunk(r0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) red[w][q][lane] = a[q];
     __syncthreads();
     {
       const int q = w, i = lane;  // thread (lane, w): entry lane of RHS cb + w
-      const int64_t c = cb + q;
-      const bool ok = i < kp && c < nrhs;
-      double v = (red[0][q][i] + red[1][q][i]) + (red[2][q][i] + red[3][q][i]);
-      if (useacc && ok) {
-        double* ap = acc + fcol + i + c * S.n;
-        v += *ap;
-        *ap = 0.0;
-      }
-      if (fin) vs[q][i] = ok ? x[fcol + i + c * S.n] - v : 0.0;
-      else if (ok) atomicAdd(acc + fcol + i + c * S.n, v);
+      const double v = (red[0][q][i] + red[1][q][i]) + (red[2][q][i] + red[3][q][i]);
+      if (useacc && okq) acc[eq] = 0.0;
+      if (fin) vs[q][i] = okq ? xq - (v + aq) : 0.0;
+      else if (okq) atomicAdd(acc + eq, v);
     }
     __syncthreads();
     if (fin) {
-      stage_w(winv + S.wbase[J] + (int64_t)p * S.nb * S.nb, kp, Ls, tid, 256);
+#pragma unroll
+      for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+        const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;
+        Ls[c][r] = here(wv[u]) * ((c < kp && r < kp) ? 1.0 : 0.0);
+      }
       __syncthreads();
-      if (lane < kp && cb + w < nrhs) x[fcol + lane + (cb + w) * S.n] = apply_wt(Ls, vs[w], lane);
+      if (okq) x[eq] = apply_wt(Ls, vs[w], lane);
     }
-  }
+  };
+  block(0);
+  for (int64_t cb = 4; cb < nrhs; cb += 4) block(cb);
 }
 
 // ---------------------------------------------------------------------------
