@@ -176,21 +176,34 @@ __device__ __forceinline__ void tile_mfma(const double* __restrict__ As, const d
 }
 
 // stage rows R0..R0+63 of the panel (kp columns) into As, zero padded
-__device__ __forceinline__ void stage_rows(double* __restrict__ As, const double* __restrict__ Lp, int m, int kp,
-                                           int R0, int tid, int nthr) {
-  for (int base = 0; base < NBMAX * NBMAX; base += 16 * nthr) {
-    double v[16];
+// A value the compiler must treat as produced here (an empty asm, no
+// instruction): keeps the use of a prefetched load, and the wait for it, at
+// this point instead of hoisted next to the load, ahead of later loads.
+__device__ __forceinline__ double here(double v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// A 64 x kp block of L (rows R0.. of the columns at Lp) in two steps, so
+// that other loads can be issued in between: load_rows fetches thread tid's
+// 16 entries (idx = u * 256 + tid, row idx & 63, column idx >> 6) from
+// clamped in-bounds addresses, store_rows writes them to As (column-major,
+// leading dimension DLD) with the entries past kp / m set to zero.
+__device__ __forceinline__ void load_rows(double (&v)[NBMAX * NBMAX / 256], const double* __restrict__ Lp, int m,
+                                          int kp, int R0, int tid) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = base + u * nthr + tid;
-      const int r = idx & 63, c = idx >> 6;
-      v[u] = (c < kp && R0 + r < m) ? Lp[(int64_t)c * m + R0 + r] : 0.0;
-    }
+  for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+    const int idx = u * 256 + tid, r = idx & 63, c = idx >> 6;
+    v[u] = Lp[(int64_t)min(c, kp - 1) * m + min(R0 + r, m - 1)];
+  }
+}
+
+__device__ __forceinline__ void store_rows(double* __restrict__ As, const double (&v)[NBMAX * NBMAX / 256], int m,
+                                           int kp, int R0, int tid) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = base + u * nthr + tid;
-      As[(idx >> 6) * DLD + (idx & 63)] = v[u];
-    }
+  for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+    const int idx = u * 256 + tid, r = idx & 63, c = idx >> 6;
+    As[c * DLD + r] = (c < kp && R0 + r < m) ? here(v[u]) : 0.0;
   }
 }
 
@@ -272,31 +285,27 @@ __device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__
   double* __restrict__ Lp = L + S.loff[J] + (int64_t)c0 * m;  // Lp[c * m + r] = L[r, c0 + c]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 
-  for (int base = 0; base < NBMAX * NBMAX; base += 16 * 256) {
-    double v[16];
+  // the diagonal block (identity-padded past kp) and, for c = 1, rows
+  // c0..c0+63 of panel p - 1 (else a dummy, never used): both loads in
+  // flight together
+  double v[NBMAX * NBMAX / 256], va[NBMAX * NBMAX / 256];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = base + u * 256 + tid;
-      const int i = idx & 63, c = idx >> 6;
-      const bool in = i < kp && c <= i;
-      // clamped in-bounds address, value selected afterwards (no branch)
-      const double x = Lp[(int64_t)min(c, kp - 1) * m + c0 + min(i, kp - 1)];
-      v[u] = in ? x : (i == c ? 1.0 : 0.0);
-    }
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = base + u * 256 + tid;
-      Dc[(idx >> 6) * DLD + (idx & 63)] = v[u];
-      Wc[(idx >> 6) * DLD + (idx & 63)] = 0.0;
-    }
+  for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+    const int idx = u * 256 + tid, i = idx & 63, c = idx >> 6;
+    v[u] = Lp[(int64_t)min(c, kp - 1) * m + c0 + min(i, kp - 1)];
   }
-  __syncthreads();
+  if (pre) load_rows(va, L + S.loff[J] + (int64_t)(c0 - S.nb) * m, m, S.nb, c0, tid);
+#pragma unroll
+  for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+    const int idx = u * 256 + tid, i = idx & 63, c = idx >> 6;
+    Dc[c * DLD + i] = (i < kp && c <= i) ? here(v[u]) : (i == c ? 1.0 : 0.0);
+  }
 
   // 0. (c = 1) the previous panel's update of the diagonal block,
   //    D -= A A^T with A = rows c0..c0+kp of panel p - 1, on the matrix
   //    cores (A staged in Wc, which is cleared again afterwards)
   if (pre) {
-    stage_rows(Wc, L + S.loff[J] + (int64_t)(c0 - S.nb) * m, m, S.nb, c0, tid, 256);
+    store_rows(Wc, va, m, S.nb, c0, tid);
     __syncthreads();
     d4 acc[4];
     tile_mfma_acc(Wc, Wc, S.nb, lane, w, acc);
@@ -304,17 +313,25 @@ __device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__
 #pragma unroll
     for (int rb2 = 0; rb2 < 4; ++rb2)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * rb2 + 4 * v + lk;
-        if (r < kp && c <= r) Dc[c * DLD + r] -= acc[rb2][v];
-        // a last, narrower panel: rows kp..63 of the tile lie below its
-        // diagonal block, in storage (the row-tile launch reads them next)
-        else if (r >= kp && c < kp && c0 + r < m) Lp[(int64_t)c * m + c0 + r] -= acc[rb2][v];
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * rb2 + 4 * q + lk;
+        if (r < kp && c <= r) Dc[c * DLD + r] -= acc[rb2][q];
       }
-    __syncthreads();
-    for (int idx = tid; idx < NBMAX * DLD; idx += 256) Wc[idx] = 0.0;
+    // a last, narrower panel: rows kp..63 of the tile lie below its
+    // diagonal block, in storage (the row-tile launch reads them next)
+    if (kp < NBMAX) {
+#pragma unroll
+      for (int rb2 = 0; rb2 < 4; ++rb2)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = 16 * rb2 + 4 * q + lk;
+          if (r >= kp && c < kp && c0 + r < m) Lp[(int64_t)c * m + c0 + r] -= acc[rb2][q];
+        }
+    }
     __syncthreads();
   }
+  for (int idx = tid; idx < NBMAX * DLD; idx += 256) Wc[idx] = 0.0;
+  __syncthreads();
 
   // 1. Cholesky of the diagonal block, right-looking over 16-column blocks:
   //    wavefront 0 sweeps block column b (rows >= 16b), then the four
@@ -385,12 +402,19 @@ __device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__
       if (r < kp && c < kp) dst[c * kp + r] = r >= c ? Wc[c * DLD + r] : 0.0;
     }
   }
-  // 3. rows rb .. rb + 255
-  for (int R0 = rb; R0 < min(rb + 4 * 64, m); R0 += 64) {
-    stage_rows(Dc, Lp, m, kp, R0, tid, 256);
-    __syncthreads();
-    tile_mfma(Dc, Wc, kp, lane, w, Lp, m, R0, m, false, 1.0);
-    __syncthreads();
+  // 3. rows rb .. rb + 255, the next 64-row tile fetched while this one is
+  //    solved
+  {
+    const int re = min(rb + 4 * 64, m);
+    double vr[NBMAX * NBMAX / 256];
+    if (rb < re) load_rows(vr, Lp, m, kp, rb, tid);
+    for (int R0 = rb; R0 < re; R0 += 64) {
+      store_rows(Dc, vr, m, kp, R0, tid);
+      __syncthreads();
+      if (R0 + 64 < re) load_rows(vr, Lp, m, kp, R0 + 64, tid);
+      tile_mfma(Dc, Wc, kp, lane, w, Lp, m, R0, m, false, 1.0);
+      __syncthreads();
+    }
   }
 }
 
@@ -416,21 +440,20 @@ __global__ __launch_bounds__(256) void k_panel_rows(DevSym S, double* __restrict
   double* __restrict__ Lp = L + S.loff[J] + (int64_t)c0 * m;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const double* __restrict__ src = winv + S.wbase[J] + (int64_t)p * S.nb * S.nb;
-  for (int base = 0; base < NBMAX * NBMAX; base += 16 * 256) {
-    double v[16];
+  // the inverse block and the tile's rows: both loads in flight together
+  double v[NBMAX * NBMAX / 256], vr[NBMAX * NBMAX / 256];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = base + u * 256 + tid;  // idx = c * 64 + r
-      const int c = idx >> 6, r = idx & 63;
-      v[u] = (r < kp && c < kp) ? src[c * kp + r] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = base + u * 256 + tid;
-      Wc[(idx >> 6) * DLD + (idx & 63)] = v[u];
-    }
+  for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+    const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;  // idx = c * 64 + r
+    v[u] = src[min(c, kp - 1) * kp + min(r, kp - 1)];
   }
-  stage_rows(As, Lp, m, kp, R0, tid, 256);
+  load_rows(vr, Lp, m, kp, R0, tid);
+#pragma unroll
+  for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+    const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;
+    Wc[c * DLD + r] = (r < kp && c < kp) ? here(v[u]) : 0.0;
+  }
+  store_rows(As, vr, m, kp, R0, tid);
   __syncthreads();
   tile_mfma(As, Wc, kp, lane, w, Lp, m, R0, m, false, 1.0);
 }
@@ -694,14 +717,6 @@ __global__ void k_perm_scatter(const int64_t* __restrict__ perm, int64_t n, cons
 // forward: y_p <- D_p^{-1} y_p, one wavefront per (J, panel); lane i owns
 // row i, column sweep: y_j is final, broadcast with readlane, subtracted
 // from the rows below
-// A value the compiler must treat as produced here (an empty asm, no
-// instruction): keeps the use of a prefetched load, and the wait for it, at
-// this point instead of hoisted next to the load, ahead of later loads.
-__device__ __forceinline__ double here(double v) {
-  asm volatile("" : "+v"(v));
-  return v;
-}
-
 // Forward round, one task per 64-row tile below a panel (Sec. II: the
 // supernodal forward substitution).  Every task forms z_p = W_p y_p with the
 // stored inverse of the panel's diagonal block (y_p is final: all panels and
@@ -733,8 +748,8 @@ __global__ __launch_bounds__(256) void k_fwd(DevSym S, const double* __restrict_
   const bool rowok = r0 >= 0 && row < m;
   // the thread's 16 entries of W and of the tile of L, the same for every
   // block of right-hand sides: loaded once, all at the start, from clamped
-  // (in-bounds, finite) addresses and zeroed past kp / m by a factor, so
-  // that no load waits behind a branch of its own
+  // in-bounds addresses, the entries past kp / m replaced by zero where
+  // used, so that no load waits behind a branch of its own
   double wr[16], lr[16];
   const int32_t grow = R[rowok ? row : 0];  // the row this lane updates
   {
@@ -757,7 +772,7 @@ __global__ __launch_bounds__(256) void k_fwd(DevSym S, const double* __restrict_
     double z[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const double wv = here(wr[u]) * ((t0 + u < t1 && lane < kp) ? 1.0 : 0.0);
+      const double wv = (t0 + u < t1 && lane < kp) ? here(wr[u]) : 0.0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) z[q] = fma(wv, ys[q][t0 + u], z[q]);
     }
@@ -774,7 +789,7 @@ __global__ __launch_bounds__(256) void k_fwd(DevSym S, const double* __restrict_
     double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const double lv = here(lr[u]) * ((t0 + u < t1 && rowok) ? 1.0 : 0.0);
+      const double lv = (t0 + u < t1 && rowok) ? here(lr[u]) : 0.0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) a[q] = fma(lv, zs[q][t0 + u], a[q]);
     }
@@ -852,7 +867,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 #pragma unroll
     for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
       const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;
-      wv[u] = W[min(c, kp - 1) * kp + min(r, kp - 1)];  // (zeroed past kp when staged)
+      wv[u] = W[min(c, kp - 1) * kp + min(r, kp - 1)];  // (replaced past kp when staged)
     }
   }
   // one block of four right-hand sides, and in it one 64-row chunk; the
@@ -874,13 +889,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 #pragma unroll
       for (int u = 0; u < TILE * NBMAX / 256; ++u) {
         const int idx = u * 256 + tid, r = idx & (TILE - 1), tt = idx / TILE;
-        lv[u] = Lj[(int64_t)(c0 + min(tt, kp - 1)) * m + r0 + min(r, nr - 1)] * ((r < nr && tt < kp) ? 1.0 : 0.0);
+        lv[u] = Lj[(int64_t)(c0 + min(tt, kp - 1)) * m + r0 + min(r, nr - 1)];
       }
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < TILE * NBMAX / 256; ++u) {
-        const int idx = u * 256 + tid;
-        Ls[idx & (TILE - 1)][idx / TILE] = lv[u];
+        const int idx = u * 256 + tid, r = idx & (TILE - 1), tt = idx / TILE;
+        Ls[r][tt] = (r < nr && tt < kp) ? here(lv[u]) : 0.0;
       }
       {
         const int64_t c = cb + w;  // thread (lane, w) loads row lane for RHS cb + w
@@ -911,7 +926,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 #pragma unroll
       for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
         const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;
-        Ls[c][r] = here(wv[u]) * ((c < kp && r < kp) ? 1.0 : 0.0);
+        Ls[c][r] = (c < kp && r < kp) ? here(wv[u]) : 0.0;
       }
       __syncthreads();
       if (okq) x[eq] = apply_wt(Ls, vs[w], lane);
