@@ -360,6 +360,16 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
     auto cost = [&](int32_t kind, const Task& t, double& fl, double& by) {
       const int64_t J = t.J, k = K(J), m = M(J);
       switch (kind) {
+        case K_SMALL: {
+          // factor and solve of all K columns, the inverse block, the update
+          // of the r rows below (r (r + 1) / 2 scattered entries)
+          const int64_t r = m - k;
+          for (int64_t j = 0; j < k; ++j) fl += double(k - j) * double(k - j);
+          fl += double(r) * double(k) * double(k) + double(k) * double(k) * double(k) / 3.0;
+          fl += 2.0 * double(k) * double(r * (r + 1) / 2);
+          by += 16.0 * double(k * m) + 8.0 * double(k * (k + 1) / 2) + 16.0 * double(r * (r + 1) / 2);
+          break;
+        }
         case K_FACTOR:
         case K_TRSM: {
           const int64_t c0 = int64_t(t.a) * nb, kp = std::min<int64_t>(nb, k - c0);
@@ -423,8 +433,17 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       }
     };
     for (int64_t l = 0; l < S.nlevels; ++l) {
+      // supernodes small enough for one wavefront: their whole step in one
+      // launch; the panel rounds and tiled updates below take the others
+      std::vector<int32_t> lev;
+      open(S.factor_plan, K_SMALL, (int32_t)l, -1);
+      for (int32_t J : bylev[l]) {
+        if (small_supernode(K(J), M(J))) S.tasks.push_back({J, 0, 0, 0});
+        else lev.push_back(J);
+      }
+      close(S.factor_plan);
       int64_t maxp = 0;
-      for (int32_t J : bylev[l]) maxp = std::max(maxp, npan(J));
+      for (int32_t J : lev) maxp = std::max(maxp, npan(J));
       // internal update tiles of panel p-1 deferred into the launch that
       // factors panel p: the first column tile of the trailing part (which
       // holds panel p) is updated before that launch, the other tiles touch
@@ -439,7 +458,7 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       std::vector<int64_t> inl_of(maxp + 1, 0);
       for (int64_t p = 0; p < maxp; ++p) {
         int64_t ntask = 0, maxrows = 0;
-        for (int32_t J : bylev[l])
+        for (int32_t J : lev)
           if (npan(J) > p) {
             ++ntask;
             maxrows = std::max<int64_t>(maxrows, M(J) - (p * nb + kpan(J, p)));
@@ -454,7 +473,7 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       for (int64_t p = 0; p < maxp; ++p) {
         const int64_t inl = inl_of[p];
         open(S.factor_plan, K_FACTOR, (int32_t)l, (int32_t)p);
-        for (int32_t J : bylev[l]) {
+        for (int32_t J : lev) {
           if (npan(J) <= p) continue;
           const int64_t rb = p * nb + kpan(J, p);
           // b: first row the task solves inline (== m: none)
@@ -468,14 +487,14 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
         }
         close(S.factor_plan);
         open(S.factor_plan, K_TRSM, (int32_t)l, (int32_t)p);
-        for (int32_t J : bylev[l]) {
+        for (int32_t J : lev) {
           if (npan(J) <= p) continue;
           for (int64_t r0 = p * nb + kpan(J, p) + inl; r0 < M(J); r0 += kTile)
             S.tasks.push_back({J, (int32_t)p, (int32_t)r0, 0});
         }
         close(S.factor_plan);
         open(S.factor_plan, K_UPD_INT, (int32_t)l, (int32_t)p);
-        for (int32_t J : bylev[l]) {
+        for (int32_t J : lev) {
           if (npan(J) <= p + 1) continue;
           for (int64_t c0 = (p + 1) * nb; c0 < K(J); c0 += kTile)
             for (int64_t r0 = c0; r0 < M(J); r0 += kTile) {
@@ -500,7 +519,7 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       // leaves most of the GPU idle) and joins before the level after
       std::vector<Task> far;
       open(S.factor_plan, K_UPD_EXT, (int32_t)l, -1);
-      for (int32_t J : bylev[l]) {
+      for (int32_t J : lev) {
         const int32_t* R = S.rows.data() + S.rptr[J];
         for (int64_t c0 = K(J); c0 < M(J); c0 += kTile) {
           bool isfar = l + 2 < S.nlevels;

@@ -20,6 +20,8 @@ namespace spchol {
 //   UPD_INT    J, first local row (target rows), first local col (target
 //              cols), panel (the K range)
 //   UPD_EXT    J, first local row, first local col, -1
+//   SMALL      J, -, -, -  (factor, inverse block and external update of
+//              a supernode for which small_supernode holds)
 //   FWD        J, panel, first local row of a 64-row tile below the panel
 //              (-1: the panel has no rows below), 1 on the panel's first task
 //   BWD        J, panel, first local row of the task's rows, and -1 (all
@@ -42,7 +44,14 @@ enum Kind : int32_t {
   K_SI_ZB = 10, // Z_Bp = -Y W tiles (+ T)
   K_SI_ZD = 11, // Z_pp = (W^T - T) W
   K_FACTOR_LA = 12,
+  K_SMALL = 13,  // a supernode whose whole numeric step fits one wavefront
 };
+
+// Supernodes done by one wavefront (K_SMALL): at most 16 columns, and with
+// the swept block padded to 4 (K <= 4) or 16 columns, the padded block, the
+// rows below and one unit row per column (for the inverse block) fit the
+// wavefront's 64 lanes.
+inline bool small_supernode(int64_t k, int64_t m) { return k <= 16 && (k <= 4 ? 4 : 16) + m <= 64; }
 
 struct Launch {
   int32_t kind;

@@ -58,6 +58,10 @@ hipError_t launch_residual(const DevSym& S, const double* vals, const double* B,
 hipError_t launch_axpy(double* X, int64_t ldx, const double* D, int64_t n, int64_t nrhs, hipStream_t st);
 hipError_t launch_copy_cols(double* Y, int64_t ldy, const double* B, int64_t ldb, int64_t n, int64_t nrhs,
                             hipStream_t st);
+// one wavefront per supernode of a K_SMALL launch (four per workgroup);
+// prec as for launch_update (the precision of the update products)
+hipError_t launch_small(const DevSym& S, double* L, int64_t off, int32_t ntasks, unsigned long long* status,
+                        double* winv, int32_t prec, hipStream_t st);
 hipError_t launch_perm_gather(const DevSym& S, const double* B, int64_t ldb, int64_t nrhs, double* y,
                               hipStream_t st);
 hipError_t launch_perm_scatter(const DevSym& S, const double* y, int64_t nrhs, double* B, int64_t ldb,

@@ -691,6 +691,111 @@ __global__ __launch_bounds__(256) void k_panel_la(DevSym S, double* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Small supernodes (at most 16 columns, the whole step within one
+// wavefront): one wavefront does a supernode's entire numeric step in
+// registers, one row per lane -- the Cholesky of the diagonal block, the
+// solve of the rows below (Sec. II), the inverse block the solves use, and
+// the update L_R L_R^T of the rows below, scattered into the ancestors
+// through the relative indices (Sec. II-A).  With the swept block padded to
+// NQ = 4 or 16 columns and r = m - K rows below, the lanes hold
+//   0 .. K-1            the rows of the diagonal block,
+//   K .. NQ-1           identity rows (the padding columns factor to
+//                       themselves),
+//   NQ .. NQ+r-1        the rows below,
+//   NQ+r .. NQ+r+K-1    unit rows e_j: the sweep solves x L^T = e_j, so the
+//                       lane ends with column j of W = L^-1 (zero above j).
+// The sweep is the panel kernel's, which factors the block and solves every
+// lane below it against it.  Four supernodes per workgroup, no LDS and no
+// barriers.  Precision P as for the tiled updates: the update's operands
+// rounded to fp32 (1) or bf16 (2) with fp32 accumulation; the diagonal
+// block, the solve and the scatter are fp64.
+// ---------------------------------------------------------------------------
+
+template <int P>
+__device__ __forceinline__ float low_precision(double v) {
+  if constexpr (P == 2) return __uint_as_float((unsigned)to_bf16(v) << 16);
+  else return (float)v;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_small(DevSym S, double* __restrict__ L, int64_t off, int32_t ntasks,
+                                               unsigned long long* __restrict__ status,
+                                               double* __restrict__ winv) {
+  const int lane = threadIdx.x & 63;
+  const int q = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (q >= ntasks) return;  // a whole wavefront; nothing below synchronizes
+  const DevTask t = S.tasks[off + q];
+  const int J = t.J, m = S.sm[J], k = S.sk[J];
+  const int nq = k <= 4 ? 4 : MB;
+  const int r = m - k;
+  const bool diag = lane < k;
+  const bool below = lane >= nq && lane < nq + r;
+  const bool unit = lane >= nq + r && lane < nq + r + k;
+  const int row = diag ? lane : (below ? k + lane - nq : 0);         // local row of J (else 0)
+  const int e = unit ? lane - nq - r : ((lane >= k && lane < nq) ? lane : -1);  // unit row
+  double* __restrict__ Lj = L + S.loff[J];
+  double x[MB];
+#pragma unroll
+  for (int c = 0; c < MB; ++c) {
+    const double v = Lj[(int64_t)min(c, k - 1) * m + row];
+    x[c] = ((diag || below) && c < k) ? v : (c == e ? 1.0 : 0.0);
+  }
+  if (nq == 4) potrf16<4>(x, lane, 0, status, (int64_t)S.sfirst[J]);
+  else potrf16<MB>(x, lane, 0, status, (int64_t)S.sfirst[J]);
+  if (diag || below) {
+#pragma unroll
+    for (int c = 0; c < MB; ++c)
+      if (c < k && c <= row) Lj[(int64_t)c * m + row] = x[c];
+  }
+  if (unit) {
+    double* __restrict__ Wd = winv + S.wbase[J];  // the one panel: K x K, column-major
+#pragma unroll
+    for (int c = 0; c < MB; ++c)
+      if (c < k) Wd[(int64_t)e * k + c] = c >= e ? x[c] : 0.0;
+  }
+  if (r == 0) return;
+  // update column b (local row k + b of J, a column of an ancestor): lane
+  // NQ + a adds -(L_R L_R^T)_ab, a >= b, at its row's position in that
+  // column; column data fetched per lane up front, row positions reloaded
+  // only when the ancestor changes (as in the tiled external update)
+  const int64_t ob = S.obase[J];
+  const int bl = min(lane, r - 1);
+  const int pair_l = S.opair[ob + bl];
+  const int64_t cbase_l = S.ocbase[ob + bl];
+  const int a = lane - nq;
+  float xl[MB];
+  if constexpr (P != 0) {
+#pragma unroll
+    for (int c = 0; c < MB; ++c) xl[c] = low_precision<P>(x[c]);
+  }
+  int cur = -1, tpv = 0;
+  for (int b = 0; b < r; ++b) {
+    double u;
+    if constexpr (P == 0) {
+      u = 0.0;
+#pragma unroll
+      for (int c = 0; c < MB; ++c)
+        if (c < k) u = fma(x[c], readlane_d(x[c], nq + b), u);
+    } else {
+      float uf = 0.f;
+#pragma unroll
+      for (int c = 0; c < MB; ++c)
+        if (c < k) uf = fmaf(xl[c], __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xl[c]), nq + b)), uf);
+      u = (double)uf;
+    }
+    const int pair = __builtin_amdgcn_readlane(pair_l, b);
+    const int64_t cbase = ((int64_t)__builtin_amdgcn_readlane((int)(cbase_l >> 32), b) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)cbase_l, b);
+    if (pair != cur) {
+      cur = pair;
+      const int a0 = S.pa0[pair];
+      tpv = (below && a >= a0) ? S.tpos[S.relptr[pair] + a - a0] : 0;
+    }
+    if (below && a >= b) atomicAdd(L + cbase + tpv, -u);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // solves.  y is the permuted right-hand side block, n x nrhs, ld = n.
 // ---------------------------------------------------------------------------
 
@@ -1355,6 +1460,16 @@ hipError_t launch_update(const DevSym& S, double* L, int32_t kind, int64_t off, 
     else if (prec == 1) k_update<1, 2><<<ntasks, 256, 0, st>>>(S, L, off);
     else k_update<0, 2><<<ntasks, 256, 0, st>>>(S, L, off);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_small(const DevSym& S, double* L, int64_t off, int32_t ntasks, unsigned long long* status,
+                        double* winv, int32_t prec, hipStream_t st) {
+  if (ntasks <= 0) return hipSuccess;
+  const int g = (ntasks + 3) / 4;
+  if (prec == 2) k_small<2><<<g, 256, 0, st>>>(S, L, off, ntasks, status, winv);
+  else if (prec == 1) k_small<1><<<g, 256, 0, st>>>(S, L, off, ntasks, status, winv);
+  else k_small<0><<<g, 256, 0, st>>>(S, L, off, ntasks, status, winv);
   return hipGetLastError();
 }
 

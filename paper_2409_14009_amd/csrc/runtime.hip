@@ -307,7 +307,11 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
       HIP_TRY(hipStreamWaitEvent(st, N->side_ev[outstanding.front()], 0));
       outstanding.erase(outstanding.begin());
     }
-    if (l.kind == K_FACTOR_LA) {
+    if (l.kind == K_SMALL) {
+      HIP_TRY(timed(N, SPCHOL_KERNEL_FACTOR, l.flops, l.bytes, st, [&] {
+        return launch_small(D, N->L, l.off, l.ntasks, N->status, N->winv, prec, st);
+      }));
+    } else if (l.kind == K_FACTOR_LA) {
       HIP_TRY(timed(N, SPCHOL_KERNEL_FACTOR, l.flops, l.bytes, st, [&] {
         return launch_factor_la(D, N->L, l.off, l.nfirst, l.ntasks, N->status, N->winv, prec, st);
       }));

@@ -181,6 +181,20 @@ int main(int argc, char** argv) {
           for (int64_t c = c0; c < c0 + kp && ok; ++c)
             for (int64_t r = t.b; r < re && ok; ++r) ok = need_complete(idx(J, c, r), q) && solve_entry(idx(J, c, r), q);
         }
+      } else if (kind == K_SMALL) {
+        // the whole supernode: every entry complete, then solved, then every
+        // pair of rows below scattered (atomic adds) into its ancestors
+        if (!small_supernode(k, m)) ok = fail("one-wavefront task for a supernode that does not fit");
+        if (k > nb) ok = fail("one-wavefront task for a supernode wider than a panel");
+        for (int64_t c = 0; c < k && ok; ++c)
+          for (int64_t r = c; r < m && ok; ++r) ok = need_complete(idx(J, c, r), q) && solve_entry(idx(J, c, r), q);
+        for (int64_t c = k; c < m && ok; ++c)
+          for (int64_t r = c; r < m && ok; ++r) {
+            const int64_t e = target(J, c, r);
+            ok = on_write(acc, e, q, true);
+            if (ok && solved[e]) ok = fail("update of an entry that is already solved");
+            got[e] += 1;
+          }
       } else if (kind == K_UPD_INT || kind == K_UPD_EXT) {
         const bool ext = kind == K_UPD_EXT;
         const int64_t kb = ext ? 0 : int64_t(t.c) * nb, ke = ext ? k : std::min<int64_t>(k, kb + nb);
@@ -314,7 +328,10 @@ int main(int argc, char** argv) {
   int64_t bsplit = 0;
   for (const Launch& L : S.bwd_plan)
     for (int32_t q = 0; q < L.ntasks; ++q) bsplit += S.tasks[L.off + q].c > 0;
-  std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld\n", S.factor_plan.size(), S.fwd_plan.size(), S.bwd_plan.size(),
-              (long long)bsplit);
+  int64_t nsmall = 0;
+  for (const Launch& L : S.factor_plan)
+    if (L.kind == K_SMALL) nsmall += L.ntasks;
+  std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld small=%lld\n", S.factor_plan.size(), S.fwd_plan.size(),
+              S.bwd_plan.size(), (long long)bsplit, (long long)nsmall);
   return 0;
 }
