@@ -1353,32 +1353,77 @@ __global__ void k_zero_u64(unsigned long long* __restrict__ p, int64_t count) {
   if (i < count) p[i] = 0ull;
 }
 
+// Rows of A (full-symmetric CSR) are read by groups of 16 lanes, 16 rows
+// per workgroup (coalesced runs of each row's entries); maxima are reduced
+// in the workgroup and added with one atomic per workgroup and statistic.
+constexpr int kRowLanes = 16;
+
+// the maximum of v over the workgroup (256 threads); sh holds 4 doubles
+__device__ __forceinline__ double block_max_256(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double m = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  __syncthreads();
+  return m;
+}
+
+// ||A||_inf = max_i sum_j |a_ij|
 __global__ __launch_bounds__(256) void k_anorm(const int64_t* __restrict__ rp, const int64_t* __restrict__ vidx,
                                                const double* __restrict__ vals, int64_t n,
                                                unsigned long long* __restrict__ out) {
-  const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
-  if (i >= n) return;
+  __shared__ double sh[4];
+  const int g = threadIdx.x % kRowLanes;
+  const int64_t i = blockIdx.x * (int64_t)(256 / kRowLanes) + threadIdx.x / kRowLanes;
   double s = 0.0;
-  for (int64_t q = rp[i]; q < rp[i + 1]; ++q) s += fabs(vals[vidx[q]]);
-  atomic_max_nonneg(out, s);
+  if (i < n)
+    for (int64_t q = rp[i] + g; q < rp[i + 1]; q += kRowLanes) s += fabs(vals[vidx[q]]);
+#pragma unroll
+  for (int o = kRowLanes / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kRowLanes);
+  const double m = block_max_256(s, sh);
+  if (threadIdx.x == 0) atomic_max_nonneg(out, m);
 }
 
-// R = B - A X for nrhs columns, with the normwise statistics
+// R = B - A X for nrhs columns, with the normwise statistics max|R|, max|X|,
+// max|B| per column; each entry of A is read once per four columns
 __global__ __launch_bounds__(256) void k_residual(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                   const int64_t* __restrict__ vidx, const double* __restrict__ vals,
                                                   int64_t n, const double* __restrict__ B, int64_t ldb,
                                                   const double* __restrict__ X, int64_t ldx, int64_t nrhs,
                                                   double* __restrict__ R, unsigned long long* __restrict__ stats) {
-  const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
-  if (i >= n) return;
-  for (int64_t c = 0; c < nrhs; ++c) {
-    const double* x = X + c * ldx;
-    double s = B[i + c * ldb];
-    for (int64_t q = rp[i]; q < rp[i + 1]; ++q) s = fma(-vals[vidx[q]], x[col[q]], s);
-    R[i + c * n] = s;
-    atomic_max_nonneg(stats + 3 * c + 0, fabs(s));
-    atomic_max_nonneg(stats + 3 * c + 1, fabs(x[i]));
-    atomic_max_nonneg(stats + 3 * c + 2, fabs(B[i + c * ldb]));
+  __shared__ double sh[4];
+  const int g = threadIdx.x % kRowLanes;
+  const int64_t i = blockIdx.x * (int64_t)(256 / kRowLanes) + threadIdx.x / kRowLanes;
+  const bool row = i < n;
+  const int64_t q0 = row ? rp[i] : 0, q1 = row ? rp[i + 1] : 0;
+  for (int64_t cb = 0; cb < nrhs; cb += 4) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t q = q0 + g; q < q1; q += kRowLanes) {
+      const double a = vals[vidx[q]];
+      const int64_t j = col[q];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (cb + u < nrhs) s[u] = fma(-a, X[(cb + u) * ldx + j], s[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int o = kRowLanes / 2; o > 0; o >>= 1) s[u] += __shfl_xor(s[u], o, kRowLanes);
+      const int64_t c = cb + u;
+      const bool ok = row && c < nrhs;
+      const double b = ok ? B[i + c * ldb] : 0.0;
+      const double r = b + s[u];
+      if (ok && g == 0) R[i + c * n] = r;
+      const double mr = block_max_256(ok ? fabs(r) : 0.0, sh);
+      const double mx = block_max_256(ok ? fabs(X[c * ldx + i]) : 0.0, sh);
+      const double mb = block_max_256(ok ? fabs(b) : 0.0, sh);
+      if (threadIdx.x == 0 && c < nrhs) {
+        atomic_max_nonneg(stats + 3 * c + 0, mr);
+        atomic_max_nonneg(stats + 3 * c + 1, mx);
+        atomic_max_nonneg(stats + 3 * c + 2, mb);
+      }
+    }
   }
 }
 
@@ -1512,7 +1557,7 @@ namespace spchol {
 
 hipError_t launch_anorm(const DevSym& S, const double* vals, unsigned long long* out, hipStream_t st) {
   k_zero_u64<<<1, 64, 0, st>>>(out, 1);
-  if (S.n > 0) k_anorm<<<(unsigned)((S.n + 255) / 256), 256, 0, st>>>(S.a_rp, S.a_vidx, vals, S.n, out);
+  if (S.n > 0) k_anorm<<<(unsigned)((S.n + 15) / 16), 256, 0, st>>>(S.a_rp, S.a_vidx, vals, S.n, out);
   return hipGetLastError();
 }
 
@@ -1520,8 +1565,8 @@ hipError_t launch_residual(const DevSym& S, const double* vals, const double* B,
                            int64_t ldx, int64_t nrhs, double* R, unsigned long long* stats, hipStream_t st) {
   k_zero_u64<<<(unsigned)((3 * nrhs + 63) / 64), 64, 0, st>>>(stats, 3 * nrhs);
   if (S.n > 0)
-    k_residual<<<(unsigned)((S.n + 255) / 256), 256, 0, st>>>(S.a_rp, S.a_col, S.a_vidx, vals, S.n, B, ldb, X, ldx,
-                                                              nrhs, R, stats);
+    k_residual<<<(unsigned)((S.n + 15) / 16), 256, 0, st>>>(S.a_rp, S.a_col, S.a_vidx, vals, S.n, B, ldb, X, ldx,
+                                                            nrhs, R, stats);
   return hipGetLastError();
 }
 
