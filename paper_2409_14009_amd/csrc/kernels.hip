@@ -574,6 +574,19 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
     }
   };
   fetch(kb);
+  // (external) lane l fetches tile column l's ancestor data (its pair's
+  // first row and relind offset, the column's storage offset) before the
+  // product, so that the scatter's row positions need one round trip after it
+  int64_t cbase_l = 0, rel_l = 0;
+  int a0_l = 0;
+  if constexpr (kind == 2) {
+    const int64_t ob = S.obase[J];
+    const int lc = min(col0 + lane, colEnd - 1) - k;
+    const int pair_l = S.opair[ob + lc];
+    cbase_l = S.ocbase[ob + lc];
+    a0_l = S.pa0[pair_l];
+    rel_l = S.relptr[pair_l];
+  }
   if constexpr (P == 2) {
     for (int kk = kb; kk < ke; kk += UKC) {
 #pragma unroll
@@ -620,6 +633,24 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
     __syncthreads();
   }
 
+  // (external) the row positions of the lane's row in the ancestors of the
+  // wavefront's 16 columns w, w + 4, ..., all loads issued before the tile
+  // goes through LDS (from a clamped in-bounds index: a position is used
+  // only for an entry on or below the diagonal, whose row then lies in the
+  // column's ancestor)
+  int tpvs[TILE / 4];
+  if constexpr (kind == 2) {
+    const int gr = row0 + lane;
+#pragma unroll
+    for (int j = 0; j < TILE / 4; ++j) {
+      const int cc = w + 4 * j;
+      const int a0 = __builtin_amdgcn_readlane(a0_l, cc);
+      const int64_t rel = ((int64_t)__builtin_amdgcn_readlane((int)(rel_l >> 32), cc) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)rel_l, cc);
+      const bool ok = gr < m && gr - k >= a0;
+      tpvs[j] = S.tpos[ok ? rel + (gr - k - a0) : rel];
+    }
+  }
   // Epilogue: the tile goes through LDS so that each wavefront then owns
   // whole tile columns, one row per lane: the target addresses of a column
   // are row runs of the ancestor's storage, so the read-modify-writes (and
@@ -642,27 +673,24 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
   } else {
     // target of entry (gr, gc): the ancestor column of row gc at storage
     // offset ocbase, row position tpos[relptr[pair] + gr - k - pa0[pair]]
-    // with pair = (J, ancestor).  Lane l fetches the column data of tile
-    // column l up front; the row positions depend only on the pair, which
-    // consecutive columns share, so they are reloaded only when it changes.
-    const int64_t ob = S.obase[J];
+    // with pair = (J, ancestor), fetched above
     const bool rowok = gr < m;
-    const int lc = min(col0 + lane, colEnd - 1) - k;
-    const int pair_l = S.opair[ob + lc];
-    const int64_t cbase_l = S.ocbase[ob + lc];
-    int cur = -1, tpv = 0;
-    for (int cc = w; cc < cmax; cc += 4) {
-      const int gc = col0 + cc;
-      const int pair = __builtin_amdgcn_readlane(pair_l, cc);
-      const int64_t cbase = ((int64_t)__builtin_amdgcn_readlane((int)(cbase_l >> 32), cc) << 32) |
-                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)cbase_l, cc);
-      if (pair != cur) {
-        cur = pair;
-        const int a0 = S.pa0[pair];
-        const int64_t base = S.relptr[pair] - a0 - k;
-        tpv = (rowok && gr - k >= a0) ? S.tpos[base + gr] : 0;
+    // the wavefront's 16 values of the lane's row, all read before the first
+    // atomic (one LDS wait, not one per column)
+    double cv[TILE / 4];
+#pragma unroll
+    for (int j = 0; j < TILE / 4; ++j) cv[j] = Cs[(w + 4 * j) * CLD + lane];
+#pragma unroll
+    for (int j = 0; j < TILE / 4; ++j) cv[j] = here(cv[j]);
+#pragma unroll
+    for (int j = 0; j < TILE / 4; ++j) {
+      const int cc = w + 4 * j;
+      if (cc < cmax) {
+        const int gc = col0 + cc;
+        const int64_t cbase = ((int64_t)__builtin_amdgcn_readlane((int)(cbase_l >> 32), cc) << 32) |
+                              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)cbase_l, cc);
+        if (rowok && gr >= gc) atomicAdd(L + cbase + tpvs[j], -cv[j]);
       }
-      if (rowok && gr >= gc) atomicAdd(L + cbase + tpv, -Cs[cc * CLD + lane]);
     }
   }
 }
