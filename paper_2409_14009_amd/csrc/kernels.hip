@@ -301,96 +301,208 @@ __device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__
     Dc[c * DLD + i] = (i < kp && c <= i) ? here(v[u]) : (i == c ? 1.0 : 0.0);
   }
 
-  // 0. (c = 1) the previous panel's update of the diagonal block,
-  //    D -= A A^T with A = rows c0..c0+kp of panel p - 1, on the matrix
-  //    cores (A staged in Wc, which is cleared again afterwards)
-  if (pre) {
-    store_rows(Wc, va, m, S.nb, c0, tid);
-    __syncthreads();
-    d4 acc[4];
-    tile_mfma_acc(Wc, Wc, S.nb, lane, w, acc);
-    const int c = MB * w + (lane & 15), lk = lane >> 4;
+  const int li = lane & 15, lk = lane >> 4;
+  // wavefront 0: sweep block column b (rows >= 16b) in registers; the
+  // sweep factors the 16 x 16 block (its lanes) and, on the lanes below it,
+  // solves those rows against it; a block of at most 4 real columns (most
+  // supernodes of the lower levels) sweeps only those, the identity-padded
+  // rest is unchanged
+  auto sweep = [&](int b) {
+    const int j0 = MB * b, jn = min(MB, kp - j0);
+    double xb[MB];
 #pragma unroll
-    for (int rb2 = 0; rb2 < 4; ++rb2)
+    for (int q = 0; q < MB; ++q) xb[q] = (lane >= j0) ? Dc[(j0 + q) * DLD + lane] : 0.0;
+    if (jn <= 4) potrf16<4>(xb, lane, j0, status, (int64_t)S.sfirst[J] + c0 + j0);
+    else potrf16<MB>(xb, lane, j0, status, (int64_t)S.sfirst[J] + c0 + j0);
+    if (lane >= j0 && lane < kp) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = 16 * rb2 + 4 * q + lk;
-        if (r < kp && c <= r) Dc[c * DLD + r] -= acc[rb2][q];
+      for (int q = 0; q < MB; ++q)
+        if (q < jn) Dc[(j0 + q) * DLD + lane] = (j0 + q <= lane) ? xb[q] : 0.0;
+    }
+  };
+  // one wavefront, matrix cores: D(i, bp) -= L(i, jb) L(bp, jb)^T on 16 x 16
+  // blocks of Dc (the whole block; above the diagonal is never read)
+  auto upd_tile = [&](int i, int bp, int jb) {
+    d4 P = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < MB; s += 4) {
+      const double av = Dc[(MB * jb + s + lk) * DLD + MB * i + li];   // L[16i + li][16jb + s + lk]
+      const double bv = Dc[(MB * jb + s + lk) * DLD + MB * bp + li];  // L[16bp + li][16jb + s + lk]
+      P = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, P, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Dc[(MB * bp + li) * DLD + MB * i + 4 * v + lk] -= P[v];
+  };
+
+  if (kp == NBMAX) {
+    // A full panel, pipelined: before the sweep of block b only block
+    // column b has to be complete, so the rest of the work runs on
+    // wavefronts 1-3 beside the sweep:
+    //   step b: wavefront 0 sweeps block b; the others apply (b = 0) the
+    //           previous panel's update to block columns 1-3, (b >= 1) block
+    //           b-1's update to block columns b+1.., and invert diagonal
+    //           block b-1 with the rest of row b-1 of W;
+    //   then:   block b's update of block column b+1 (all wavefronts);
+    //   last:   diagonal block 3 of W, then row 3 of W.
+    // (c = 1) D -= A A^T, A = rows c0..c0+63 of panel p - 1 staged in Wc
+    auto pre_tile = [&](int i, int c) {
+      d4 P = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < NBMAX; s += 4) {
+        const double av = Wc[(s + lk) * DLD + MB * i + li];
+        const double bv = Wc[(s + lk) * DLD + MB * c + li];
+        P = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, P, 0, 0, 0);
       }
-    // a last, narrower panel: rows kp..63 of the tile lie below its
-    // diagonal block, in storage (the row-tile launch reads them next)
-    if (kp < NBMAX) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Dc[(MB * c + li) * DLD + MB * i + 4 * v + lk] -= P[v];
+    };
+    // W_bb = inverse of L_bb by substitution: lane l < 16 forms column l
+    auto inv_diag = [&](int b) {
+      if (lane < MB) {
+        const int b0 = MB * b;
+        double x[MB], rd[MB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) rd[i] = 1.0 / Dc[(b0 + i) * DLD + b0 + i];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+          double z = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+          for (int q = 0; q < i; ++q) z = fma(-Dc[(b0 + q) * DLD + b0 + i], x[q], z);
+          x[i] = z * rd[i];
+        }
+#pragma unroll
+        for (int i = 0; i < MB; ++i) Wc[(b0 + lane) * DLD + b0 + i] = x[i];
+      }
+    };
+    // W_ib = -W_ii sum_{t=b}^{i-1} L_it W_tb (W_tb and W_ii already formed)
+    auto inv_off = [&](int i, int b) {
+      d4 T = d4{0.0, 0.0, 0.0, 0.0};
+      for (int tb = b; tb < i; ++tb)
+#pragma unroll
+        for (int s = 0; s < MB; s += 4) {
+          const double av = Dc[(MB * tb + s + lk) * DLD + MB * i + li];  // L[16i + li][16tb + s + lk]
+          const double bv = Wc[(MB * b + li) * DLD + MB * tb + s + lk];  // W[16tb + s + lk][16b + li]
+          T = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, T, 0, 0, 0);
+        }
+      // T's accumulator element v is exactly the B operand of k-step v
+      d4 O = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double av = Wc[(MB * i + 4 * s + lk) * DLD + MB * i + li];  // W[16i + li][16i + 4s + lk]
+        O = __builtin_amdgcn_mfma_f64_16x16x4f64(av, T[s], O, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Wc[(MB * b + li) * DLD + MB * i + 4 * v + lk] = -O[v];
+    };
+    if (pre) {
+      store_rows(Wc, va, m, S.nb, c0, tid);
+      __syncthreads();
+      pre_tile(w, 0);  // block column 0, one block per wavefront
+    }
+    __syncthreads();
+    for (int b = 0; b < 4; ++b) {
+      if (w == 0) {
+        sweep(b);
+      } else if (b == 0) {
+        // the previous panel's update of block columns 1-3, two blocks per
+        // wavefront: (1,1) (2,1) | (3,1) (2,2) | (3,2) (3,3)
+        if (pre) {
+          if (w == 1) { pre_tile(1, 1); pre_tile(2, 1); }
+          else if (w == 2) { pre_tile(3, 1); pre_tile(2, 2); }
+          else { pre_tile(3, 2); pre_tile(3, 3); }
+        }
+      } else if (w == 1) {
+        inv_diag(b - 1);
+        for (int j = b - 2; j >= 0; --j) inv_off(b - 1, j);
+      } else if (b == 1) {
+        // block 0's update of block columns 2-3: (2,2) (3,3) | (3,2)
+        if (w == 2) { upd_tile(2, 2, 0); upd_tile(3, 3, 0); }
+        else upd_tile(3, 2, 0);
+      } else if (b == 2 && w == 2) {
+        upd_tile(3, 3, 1);  // block 1's update of block column 3
+      }
+      __syncthreads();
+      if (b < 3) {
+        // Wc is free once the previous panel's update is applied: cleared
+        // for W, whose blocks above the diagonal stay zero
+        if (b == 0)
+          for (int idx = tid; idx < NBMAX * DLD; idx += 256) Wc[idx] = 0.0;
+        if (w <= 2 - b) upd_tile(b + 1 + w, b + 1, b);  // block column b+1 by block b
+        __syncthreads();
+      }
+    }
+    // write the factored block back (lower part), all threads, coalesced
+#pragma unroll
+    for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+      const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;
+      if (c <= r) Lp[(int64_t)c * m + c0 + r] = Dc[c * DLD + r];
+    }
+    if (w == 0) inv_diag(3);
+    __syncthreads();
+    if (w < 3) inv_off(3, w);
+    __syncthreads();
+  } else {
+    // 0. (c = 1) the previous panel's update of the diagonal block,
+    //    D -= A A^T with A = rows c0..c0+kp of panel p - 1, on the matrix
+    //    cores (A staged in Wc, which is cleared again afterwards)
+    if (pre) {
+      store_rows(Wc, va, m, S.nb, c0, tid);
+      __syncthreads();
+      d4 acc[4];
+      tile_mfma_acc(Wc, Wc, S.nb, lane, w, acc);
+      const int c = MB * w + (lane & 15), lk = lane >> 4;
 #pragma unroll
       for (int rb2 = 0; rb2 < 4; ++rb2)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int r = 16 * rb2 + 4 * q + lk;
-          if (r >= kp && c < kp && c0 + r < m) Lp[(int64_t)c * m + c0 + r] -= acc[rb2][q];
+          if (r < kp && c <= r) Dc[c * DLD + r] -= acc[rb2][q];
         }
+      // a last, narrower panel: rows kp..63 of the tile lie below its
+      // diagonal block, in storage (the row-tile launch reads them next)
+      if (kp < NBMAX) {
+#pragma unroll
+        for (int rb2 = 0; rb2 < 4; ++rb2)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = 16 * rb2 + 4 * q + lk;
+            if (r >= kp && c < kp && c0 + r < m) Lp[(int64_t)c * m + c0 + r] -= acc[rb2][q];
+          }
+      }
+      __syncthreads();
     }
+    for (int idx = tid; idx < NBMAX * DLD; idx += 256) Wc[idx] = 0.0;
     __syncthreads();
-  }
-  for (int idx = tid; idx < NBMAX * DLD; idx += 256) Wc[idx] = 0.0;
-  __syncthreads();
 
-  // 1. Cholesky of the diagonal block, right-looking over 16-column blocks:
-  //    wavefront 0 sweeps block column b (rows >= 16b), then the four
-  //    wavefronts apply its update to the 16 x 16 blocks (i, b') with
-  //    i >= b' > b on the matrix cores:
-  //    D[i][b'] -= L[i][b] L[b'][b]^T
-  for (int b = 0; b < nblk; ++b) {
-    const int j0 = MB * b, jn = min(MB, kp - j0);
-    const bool mine = (w == 0) && lane >= j0 && lane < kp;
-    if (w == 0) {
-      double xb[MB];
-#pragma unroll
-      for (int q = 0; q < MB; ++q) xb[q] = (lane >= j0) ? Dc[(j0 + q) * DLD + lane] : 0.0;
-      // the sweep factors the 16 x 16 block (its lanes) and, on the lanes
-      // below it, solves those rows against it
-      // a block of at most 4 real columns (most supernodes of the lower
-      // levels) sweeps only those; the identity-padded rest is unchanged
-      if (jn <= 4) potrf16<4>(xb, lane, j0, status, (int64_t)S.sfirst[J] + c0 + j0);
-      else potrf16<MB>(xb, lane, j0, status, (int64_t)S.sfirst[J] + c0 + j0);
-      if (mine) {
-#pragma unroll
-        for (int q = 0; q < MB; ++q)
-          if (q < jn) Dc[(j0 + q) * DLD + lane] = (j0 + q <= lane) ? xb[q] : 0.0;
+    // 1. Cholesky of the diagonal block, right-looking over 16-column blocks:
+    //    wavefront 0 sweeps block column b (rows >= 16b), then the four
+    //    wavefronts apply its update to the 16 x 16 blocks (i, b') with
+    //    i >= b' > b on the matrix cores:
+    //    D[i][b'] -= L[i][b] L[b'][b]^T
+    for (int b = 0; b < nblk; ++b) {
+      if (w == 0) sweep(b);
+      __syncthreads();
+      const int nrest = nblk - 1 - b;  // block columns right of b
+      const int npairs = nrest * (nrest + 1) / 2;
+      for (int pr = w; pr < npairs; pr += 4) {
+        // pair index -> (i, bp) with b < bp <= i < nblk
+        int bp = b + 1, rem = pr;
+        while (rem >= nblk - bp) { rem -= nblk - bp; ++bp; }
+        upd_tile(bp + rem, bp, b);
       }
+      __syncthreads();
     }
-    __syncthreads();
-    const int nrest = nblk - 1 - b;  // block columns right of b
-    const int npairs = nrest * (nrest + 1) / 2;
-    const int li = lane & 15, lk = lane >> 4;
-    for (int pr = w; pr < npairs; pr += 4) {
-      // pair index -> (i, bp) with b < bp <= i < nblk
-      int bp = b + 1, rem = pr;
-      while (rem >= nblk - bp) { rem -= nblk - bp; ++bp; }
-      const int i = bp + rem;
-      d4 P = d4{0.0, 0.0, 0.0, 0.0};
+    // write the factored block back (lower part), all threads, coalesced
 #pragma unroll
-      for (int s = 0; s < MB; s += 4) {
-        const double av = Dc[(j0 + s + lk) * DLD + MB * i + li];   // L[16i + li][16b + s + lk]
-        const double bv = Dc[(j0 + s + lk) * DLD + MB * bp + li];  // L[16bp + li][16b + s + lk]
-        P = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, P, 0, 0, 0);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        double* d = Dc + (MB * bp + li) * DLD + MB * i + 4 * v + lk;
-        *d -= P[v];
-      }
+    for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+      const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;
+      if (r < kp && c <= r) Lp[(int64_t)c * m + c0 + r] = Dc[c * DLD + r];
     }
-    __syncthreads();
-  }
-  // write the factored block back (lower part), all threads, coalesced
-#pragma unroll
-  for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
-    const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;
-    if (r < kp && c <= r) Lp[(int64_t)c * m + c0 + r] = Dc[c * DLD + r];
-  }
 
-  // 2. W = L_pp^{-1}
-  invert_diag_block(Dc, Wc, nblk, lane, w);
-  __syncthreads();
+    // 2. W = L_pp^{-1}
+    invert_diag_block(Dc, Wc, nblk, lane, w);
+    __syncthreads();
+  }
 
   // 4. W, kp x kp column-major (zeros above the diagonal), for the row-tile
   //    launch and the solves
@@ -418,7 +530,7 @@ __device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__
   }
 }
 
-__global__ __launch_bounds__(256) void k_panel(DevSym S, double* __restrict__ L, int64_t off,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_panel(DevSym S, double* __restrict__ L, int64_t off,
                                                unsigned long long* __restrict__ status,
                                                double* __restrict__ winv) {
   __shared__ __attribute__((aligned(16))) double smem[PANEL_SMEM];
@@ -709,7 +821,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 // the others apply internal update tiles of panel p-1 to columns right of
 // panel p.  The two sets touch disjoint columns.
 template <int P>
-__global__ __launch_bounds__(256) void k_panel_la(DevSym S, double* __restrict__ L, int64_t off, int32_t nfirst,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_panel_la(DevSym S, double* __restrict__ L, int64_t off, int32_t nfirst,
                                                   unsigned long long* __restrict__ status,
                                                   double* __restrict__ winv) {
   __shared__ __attribute__((aligned(16))) double smem[PANEL_SMEM > UPD_SMEM ? PANEL_SMEM : UPD_SMEM];
