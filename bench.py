@@ -105,6 +105,28 @@ def _timed_steps(steps, stream, phases):
             for i, (name, _) in enumerate(phases)}
 
 
+WIDE_K = 256
+
+
+def wide_update_levels(S, kmin=WIDE_K):
+    """Levels of the schedule whose external-update work (tiled launches;
+    the one-wavefront supernodes excluded) comes from supernodes of at
+    least kmin columns on average, weighted by flops."""
+    e = S.export()
+    k = np.diff(np.asarray(e["super_ptr"])).astype(np.float64)
+    m = np.diff(np.asarray(e["row_ptr"])).astype(np.float64)
+    lev = np.asarray(e["level"])
+    r = m - k
+    small = (k <= 16) & (np.where(k <= 4, 4, 16) + m <= 64)
+    w = np.where((r > 0) & ~small, k * r * (r + 1), 0.0)
+    out = set()
+    for lv in np.unique(lev):
+        s = lev == lv
+        if w[s].sum() > 0 and (w[s] * k[s]).sum() / w[s].sum() >= kmin:
+            out.add(int(lv))
+    return out
+
+
 def headline(args, dev):
     import torch
     import gen
@@ -146,8 +168,17 @@ def headline(args, dev):
         e2.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = F.profile_read()
+    recs = F.profile_launches()
     F.profile(False)
+    prof = {}
+    for r in recs:
+        a = prof.setdefault(r["kind"], dict(launches=0, ms=0.0, flops=0.0, bytes=0.0))
+        a["launches"] += 1
+        a["ms"] += r["ms"]
+        a["flops"] += r["flops"]
+        a["bytes"] += r["bytes"]
+    for kname in ("fill", "scatter_a", "factor", "update_int", "update_ext"):
+        prof.setdefault(kname, dict(launches=0, ms=0.0, flops=0.0, bytes=0.0))
     factor_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
     solve_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -179,6 +210,17 @@ def headline(args, dev):
     roof.update(kernel=dom, launches_per_step=d["launches"] / args.steps,
                 avg_launch_us=d["ms"] * 1e3 / max(d["launches"], 1),
                 flops_per_step=d["flops"] / args.steps, bytes_per_step=d["bytes"] / args.steps)
+    # the large-supernode updates: external-update launches of the levels
+    # whose update work comes from supernodes of >= 256 columns on average
+    # (flop-weighted), the part the fp64 matrix cores can run near their peak
+    wl = wide_update_levels(S)
+    wr = [r for r in recs if r["kind"] == "update_ext" and r["level"] in wl]
+    wms, wfl = sum(r["ms"] for r in wr), sum(r["flops"] for r in wr)
+    wide = dict(min_avg_columns=WIDE_K, levels=len(wl), launches_per_step=len(wr) / args.steps,
+                ms_per_step=wms / args.steps,
+                share_of_update_flops=wfl / prof["update_ext"]["flops"] if prof["update_ext"]["flops"] else None,
+                achieved=wfl / (wms * 1e-3) / 1e12 if wms > 0 else None, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                frac=wfl / (wms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS if wms > 0 else None)
     kernels = {k: dict(launches=v["launches"] / args.steps, ms=v["ms"] / args.steps,
                        gflops=(v["flops"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 and v["flops"] else None,
                        gbs=(v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 and v["bytes"] else None)
@@ -219,6 +261,7 @@ def headline(args, dev):
         raise RuntimeError(f"factorization reported a non-positive pivot at column {gstatus}")
     value = info["flops_alg"] / (tg["factor"] * 1e-3) / 1e9
     res = dict(value=value, ms_per_step=(t1 - t0) * 1e3 / args.steps, factor_ms=tg["factor"], panel_chain=chain,
+               wide_updates=wide,
                solve_logdet_ms=tg["solve"], eager_factor_ms=factor_ms, eager_solve_logdet_ms=solve_ms,
                eager_ms_per_step=ms_per_step, eager_gflops=gflops,
                backward_error=max(max(eta), max(eta_g)), logdet=box["ld"], roofline=roof, kernels=kernels,
@@ -451,6 +494,7 @@ def main():
         "logdet": res["logdet"],
         "roofline": res["roofline"],
         "panel_chain": res["panel_chain"],
+        "wide_updates": res["wide_updates"],
         "cpu_baseline": cpu,
         "kernels": res["kernels"],
     }

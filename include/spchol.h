@@ -289,12 +289,35 @@ typedef struct {
   double bytes;     /* algorithmic HBM bytes of those launches                 */
 } spchol_kernel_stat;
 
+/* One timed launch.  level: the launch's level in the leaves-to-root
+ * schedule of the supernodal elimination tree (Fig. 1; -1 for launches
+ * outside it: fills, permutations, log-determinant, selected inversion);
+ * side: 1 for external updates that ran on the second stream beside the
+ * next level's panel chain, else 0. */
+typedef struct {
+  int32_t kind;     /* SPCHOL_KERNEL_*                                         */
+  int32_t level;
+  int32_t side;
+  int32_t reserved; /* 0                                                       */
+  double ms;        /* event time of the launch                                */
+  double flops;     /* algorithmic flops (stored structure)                    */
+  double bytes;     /* algorithmic HBM bytes                                   */
+} spchol_launch_record;
+
 /* enable != 0 starts collecting (clearing earlier records), 0 stops. */
 spchol_status spchol_profile(spchol_num num, int32_t enable);
 
 /* Synchronize the streams the records were made on, sum the records per
  * kind into out[SPCHOL_KERNEL_KINDS] (host) and clear them. */
 spchol_status spchol_profile_read(spchol_num num, spchol_kernel_stat *out);
+
+/* The records one by one, in launch order.  *count receives the number of
+ * records.  With out == NULL nothing else happens (the records are kept);
+ * otherwise the first min(cap, *count) records are written to out (host
+ * array, caller-owned), the streams they were made on are synchronized and
+ * all records are cleared.  SPCHOL_ERR_ARG for a null handle or count, or
+ * cap < 0. */
+spchol_status spchol_profile_launches(spchol_num num, spchol_launch_record *out, int64_t cap, int64_t *count);
 
 void spchol_sym_destroy(spchol_sym sym);
 void spchol_num_destroy(spchol_num num);

@@ -381,6 +381,17 @@ class Factor:
         return {name: dict(launches=arr[i].launches, ms=arr[i].ms, flops=arr[i].flops, bytes=arr[i].bytes)
                 for i, name in enumerate(capi.KERNEL_KINDS)}
 
+    def profile_launches(self) -> list:
+        """The records since profile(True) one by one, in launch order: kind
+        name, schedule level (-1 outside the level schedule), side (1: second
+        stream), ms, flops, bytes; synchronizes and clears them."""
+        cnt = C.c_int64(0)
+        _check(capi.lib().spchol_profile_launches(self._h, None, 0, C.byref(cnt)))
+        arr = (capi.LaunchRecord * max(cnt.value, 1))()
+        _check(capi.lib().spchol_profile_launches(self._h, arr, cnt.value, C.byref(cnt)))
+        return [dict(kind=capi.KERNEL_KINDS[r.kind], level=r.level, side=r.side, ms=r.ms, flops=r.flops,
+                     bytes=r.bytes) for r in arr[:cnt.value]]
+
     def storage(self, stream=None):
         """Copy of the supernodal storage of L (float64 CUDA tensor)."""
         import torch

@@ -30,6 +30,11 @@ class KernelStat(C.Structure):
     _fields_ = [("launches", i64), ("ms", f64), ("flops", f64), ("bytes", f64)]
 
 
+class LaunchRecord(C.Structure):
+    _fields_ = [("kind", i32), ("level", i32), ("side", i32), ("reserved", i32), ("ms", f64), ("flops", f64),
+                ("bytes", f64)]
+
+
 KERNEL_KINDS = ["fill", "scatter_a", "factor", "update_int", "update_ext", "fwd", "bwd", "perm", "logdet",
                 "selinv"]
 
@@ -60,6 +65,7 @@ PROTOTYPES = {
     "spchol_selinv_export": (i32, [vp, vp, vp]),
     "spchol_profile": (i32, [vp, i32]),
     "spchol_profile_read": (i32, [vp, C.POINTER(KernelStat)]),
+    "spchol_profile_launches": (i32, [vp, C.POINTER(LaunchRecord), i64, C.POINTER(i64)]),
     "spchol_sym_destroy": (None, [vp]),
     "spchol_num_destroy": (None, [vp]),
     "spchol_last_error": (C.c_char_p, []),

@@ -1,6 +1,7 @@
 // C ABI: handles, device upload of the symbolic analysis, launch sequencing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -127,7 +128,7 @@ struct spchol_sym_s {
 // HIP events around launches, summed per kernel kind on request.
 struct Profiler {
   struct Rec {
-    int kind;
+    int kind, level, side;
     hipEvent_t a, b;
     double flops, bytes;
   };
@@ -256,11 +257,14 @@ struct spchol_num_s {
   }
 };
 
-// Run `launch` (returning hipError_t), bracketed by events when profiling.
+// Run `launch` (returning hipError_t), bracketed by events when profiling;
+// level / side: the launch's level in the schedule (-1: outside it) and
+// whether it runs on the second stream.
 template <class F>
-static hipError_t timed(spchol_num_s* N, int kind, double flops, double bytes, hipStream_t st, F&& launch) {
+static hipError_t timed_at(spchol_num_s* N, int kind, int level, int side, double flops, double bytes,
+                           hipStream_t st, F&& launch) {
   if (!N->prof.on) return launch();
-  Profiler::Rec r{kind, nullptr, nullptr, flops, bytes};
+  Profiler::Rec r{kind, level, side, nullptr, nullptr, flops, bytes};
   hipError_t e = N->prof.take(&r.a);
   if (e == hipSuccess) e = N->prof.take(&r.b);
   if (e == hipSuccess) e = hipEventRecord(r.a, st);
@@ -270,6 +274,11 @@ static hipError_t timed(spchol_num_s* N, int kind, double flops, double bytes, h
   e = hipEventRecord(r.b, st);
   if (e == hipSuccess) N->prof.recs.push_back(r);
   return e;
+}
+
+template <class F>
+static hipError_t timed(spchol_num_s* N, int kind, double flops, double bytes, hipStream_t st, F&& launch) {
+  return timed_at(N, kind, -1, 0, flops, bytes, st, launch);
 }
 
 // Enqueue the whole numeric factorization on st (no host synchronization:
@@ -296,8 +305,8 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
       // fork: the side stream starts once everything before is done
       HIP_TRY(hipEventRecord(N->fork_ev, st));
       HIP_TRY(hipStreamWaitEvent(N->side, N->fork_ev, 0));
-      HIP_TRY(timed(N, SPCHOL_KERNEL_UPDATE_EXT, l.flops, l.bytes, N->side,
-                    [&] { return launch_update(D, N->L, l.kind, l.off, l.ntasks, prec, N->side); }));
+      HIP_TRY(timed_at(N, SPCHOL_KERNEL_UPDATE_EXT, l.level, 1, l.flops, l.bytes, N->side,
+                       [&] { return launch_update(D, N->L, l.kind, l.off, l.ntasks, prec, N->side); }));
       HIP_TRY(hipEventRecord(N->side_ev[l.level], N->side));
       outstanding.push_back(l.level);
       continue;
@@ -308,20 +317,22 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
       outstanding.erase(outstanding.begin());
     }
     if (l.kind == K_SMALL) {
-      HIP_TRY(timed(N, SPCHOL_KERNEL_FACTOR, l.flops, l.bytes, st, [&] {
+      HIP_TRY(timed_at(N, SPCHOL_KERNEL_FACTOR, l.level, 0, l.flops, l.bytes, st, [&] {
         return launch_small(D, N->L, l.off, l.ntasks, N->status, N->winv, prec, st);
       }));
     } else if (l.kind == K_FACTOR_LA) {
-      HIP_TRY(timed(N, SPCHOL_KERNEL_FACTOR, l.flops, l.bytes, st, [&] {
+      HIP_TRY(timed_at(N, SPCHOL_KERNEL_FACTOR, l.level, 0, l.flops, l.bytes, st, [&] {
         return launch_factor_la(D, N->L, l.off, l.nfirst, l.ntasks, N->status, N->winv, prec, st);
       }));
     } else if (l.kind == K_FACTOR || l.kind == K_TRSM) {
       const bool diag = l.kind == K_FACTOR;
-      HIP_TRY(timed(N, SPCHOL_KERNEL_FACTOR, l.flops, l.bytes, st,
-                    [&] { return launch_factor_panel(D, N->L, l.off, l.ntasks, N->status, N->winv, diag, st); }));
+      HIP_TRY(timed_at(N, SPCHOL_KERNEL_FACTOR, l.level, 0, l.flops, l.bytes, st, [&] {
+        return launch_factor_panel(D, N->L, l.off, l.ntasks, N->status, N->winv, diag, st);
+      }));
     } else {
-      HIP_TRY(timed(N, l.kind == K_UPD_INT ? SPCHOL_KERNEL_UPDATE_INT : SPCHOL_KERNEL_UPDATE_EXT, l.flops,
-                    l.bytes, st, [&] { return launch_update(D, N->L, l.kind, l.off, l.ntasks, prec, st); }));
+      HIP_TRY(timed_at(N, l.kind == K_UPD_INT ? SPCHOL_KERNEL_UPDATE_INT : SPCHOL_KERNEL_UPDATE_EXT, l.level, 0,
+                       l.flops, l.bytes, st,
+                       [&] { return launch_update(D, N->L, l.kind, l.off, l.ntasks, prec, st); }));
     }
   }
   for (int64_t v : outstanding) HIP_TRY(hipStreamWaitEvent(st, N->side_ev[v], 0));
@@ -352,7 +363,7 @@ static spchol_status enqueue_solve(spchol_num_s* num, SolveWork& w, double* B_de
     // solve flops/bytes were counted for one right-hand side; L is read once
     const double fl = l.flops * double(nrhs);
     const double by = l.bytes;
-    return timed(num, l.kind == K_FWD ? SPCHOL_KERNEL_FWD : SPCHOL_KERNEL_BWD, fl, by, st, [&] {
+    return timed_at(num, l.kind == K_FWD ? SPCHOL_KERNEL_FWD : SPCHOL_KERNEL_BWD, l.level, 0, fl, by, st, [&] {
       return launch_solve_step(D, num->L, num->winv, l.kind, l.off, l.ntasks, w.y, w.x, w.acc, nrhs, st);
     });
   };
@@ -955,6 +966,23 @@ spchol_status spchol_profile_read(spchol_num num, spchol_kernel_stat* out) {
     s.ms += ms;
     s.flops += r.flops;
     s.bytes += r.bytes;
+  }
+  num->prof.recs.clear();
+  num->prof.used = 0;
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_profile_launches(spchol_num num, spchol_launch_record* out, int64_t cap, int64_t* count) {
+  if (!num || !count || cap < 0) return fail(SPCHOL_ERR_ARG, "null argument or negative capacity");
+  *count = (int64_t)num->prof.recs.size();
+  if (!out) return SPCHOL_OK;
+  const int64_t nout = std::min<int64_t>(cap, *count);
+  for (int64_t q = 0; q < nout; ++q) {
+    const Profiler::Rec& r = num->prof.recs[q];
+    HIP_TRY(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    out[q] = spchol_launch_record{r.kind, r.level, r.side, 0, ms, r.flops, r.bytes};
   }
   num->prof.recs.clear();
   num->prof.used = 0;
