@@ -315,6 +315,36 @@ def random_spd(n, density, rng, dominance=1.0):
     return n, colptr, rowind, vv
 
 
+def leaf_pair_spd(k, r, rng):
+    """Two dense leaf blocks of k columns, not coupled to each other, each
+    coupled densely to a dense parent block of r rows (ordered last): with
+    the identity ordering the leaves are supernodes of k columns and k + r
+    rows whose update goes to the parent.  Values strictly diagonally
+    dominant."""
+    n = 2 * k + r
+    rows, cols = [], []
+    par = np.arange(2 * k, n)
+    for b in range(2):
+        leaf = np.arange(b * k, (b + 1) * k)
+        for j in leaf:
+            below = np.concatenate([leaf[leaf > j], par])
+            rows.append(below)
+            cols.append(np.full(below.size, j))
+    for j in par:
+        below = par[par > j]
+        rows.append(below)
+        cols.append(np.full(below.size, j))
+    r_ = np.concatenate(rows).astype(np.int64) if rows else np.zeros(0, np.int64)
+    c_ = np.concatenate(cols).astype(np.int64) if cols else np.zeros(0, np.int64)
+    w = rng.uniform(0.1, 1.0, size=r_.size) * rng.choice([-1.0, 1.0], size=r_.size)
+    diag = np.ones(n)
+    np.add.at(diag, r_, np.abs(w))
+    np.add.at(diag, c_, np.abs(w))
+    colptr, rowind, vv = _lower_csc(n, np.concatenate([r_, np.arange(n)]), np.concatenate([c_, np.arange(n)]),
+                                    np.concatenate([w, diag]))
+    return n, colptr, rowind, vv
+
+
 # --------------------------------------------------------------------------
 # the five workloads
 # --------------------------------------------------------------------------

@@ -179,3 +179,15 @@ def test_wide_supernodes_big_tiles():
     k = np.diff(e["super_ptr"]); m = np.diff(e["row_ptr"])
     assert ((k >= 128) & (m > k)).any()
     run_case(p.n, p.colptr, p.rowind, p.vals, p.perm, p.B, 0, 8, 64, well_conditioned=False)
+
+
+@pytest.mark.parametrize("k,r", [(1, 59), (4, 56), (4, 57), (5, 43), (16, 32), (16, 33), (17, 10), (3, 0),
+                                 (16, 0), (8, 1)])
+def test_small_supernode_limits(k, r):
+    """Leaves at and past the limits of the one-wavefront supernode (two
+    leaves of k columns updating a parent of r rows): the same factor,
+    solve and log-determinant either way."""
+    rng = np.random.default_rng(2000 * k + r)
+    n, cp, ri, vv = gen.leaf_pair_spd(k, r, rng)
+    B = rng.standard_normal((n, 3))
+    run_case(n, cp, ri, vv, None, B, 0, 0, 64)

@@ -88,3 +88,21 @@ def test_batch_union(checker, tmp_path):
         nzoff += p.nnz
     cp = np.concatenate(cps + [[nzoff]]).astype(np.int64)
     _run(checker, tmp_path, off, cp, np.concatenate(ris), np.concatenate(pms), 0, 8, 64)
+
+
+# (leaf columns, rows of the parent): at and past the limits of the
+# one-wavefront supernode (at most 16 columns; padded block + rows below +
+# one unit row per column within 64 lanes)
+LEAF_SHAPES = [(1, 59, True), (4, 56, True), (4, 57, False), (5, 43, True), (16, 32, True), (16, 33, False),
+               (17, 10, False), (3, 0, True), (16, 0, True), (8, 1, True)]
+
+
+@pytest.mark.parametrize("k,r,small", LEAF_SHAPES)
+def test_small_supernode_limits(checker, tmp_path, k, r, small):
+    rng = np.random.default_rng(1000 * k + r)
+    n, cp, ri, _ = gen.leaf_pair_spd(k, r, rng)
+    out = _run(checker, tmp_path, n, cp, ri, None, 0, 0, 64)
+    nsmall = int(out.split("small=")[1])
+    # the two leaves, and the parent block too when it fits
+    parent = r > 0 and r <= 16 and (4 if r <= 4 else 16) + r <= 64
+    assert nsmall == (2 if small else 0) + (1 if parent else 0), out
