@@ -689,6 +689,16 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
   // (external) lane l fetches tile column l's ancestor data (its pair's
   // first row and relind offset, the column's storage offset) before the
   // product, so that the scatter's row positions need one round trip after it
+  // (internal) the tile's entries of the target, read now (no other task of
+  // the launch touches them) so that the epilogue only stores: thread
+  // (lane, w) owns row row0 + lane of columns col0 + w + 4j (clamped
+  // in-bounds addresses; the values are used only where the entry exists)
+  double cold[TILE / 4];
+  if constexpr (kind == 1) {
+    const int rr = min(row0 + lane, m - 1);
+#pragma unroll
+    for (int j = 0; j < TILE / 4; ++j) cold[j] = Lj[(int64_t)min(col0 + w + 4 * j, colEnd - 1) * m + rr];
+  }
   int64_t cbase_l = 0, rel_l = 0;
   int a0_l = 0;
   if constexpr (kind == 2) {
@@ -778,9 +788,10 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
   const int gr = row0 + lane;
   const int cmax = min(TILE, colEnd - col0);
   if constexpr (kind == 1) {
-    for (int cc = w; cc < cmax; cc += 4) {
-      const int gc = col0 + cc;
-      if (gr < m && gr >= gc) Lj[(int64_t)gc * m + gr] -= Cs[cc * CLD + lane];
+#pragma unroll
+    for (int j = 0; j < TILE / 4; ++j) {
+      const int cc = w + 4 * j, gc = col0 + cc;
+      if (cc < cmax && gr < m && gr >= gc) Lj[(int64_t)gc * m + gr] = cold[j] - Cs[cc * CLD + lane];
     }
   } else {
     // target of entry (gr, gc): the ancestor column of row gc at storage
