@@ -49,15 +49,15 @@ PEAK_HBM_GBS = 8000.0
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, scales from a plain 1 GiB copy;
 # profiles/update_ext_grid3d_64.md), valid for the kernel source they were
 # taken with: reported only while the source hash matches.
-MEASURED_TRAFFIC = {"kernel": "update_ext", "bytes_per_launch": 426574039,
-                    "kernels_sha256_16": "388341af543e8f46"}
+MEASURED_TRAFFIC = {"kernel": "update_ext", "bytes_per_launch": 450712122,
+                    "kernels_sha256_16": "d05e41d42f2c735b"}
 
 
 def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(p, z, ncols=32768):
+def cpu_baseline(p, z, ncols=65536):
     """The oracle (plain single-thread C left-looking factorization) on a
     bounded sample: the first `ncols` columns of the same elimination order,
     which form a complete nested-dissection subtree (columns < t depend only
