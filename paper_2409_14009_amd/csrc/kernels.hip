@@ -1314,41 +1314,64 @@ __global__ __launch_bounds__(256) void k_si_y(DevSym S, const double* __restrict
   for (int i = tid; i < kSiSeg; i += 256) colseg[i] = bs + i < be ? zcol(S, J, k, m, ob, bs + i) : ZCol{0, -1};
   __syncthreads();
   const ZCol ca = a < m ? cola[sr] : ZCol{0, -1};
+  // The loads of a chunk are issued together: the positions of the
+  // ancestor-column entries first, then the entries of Z and of L, all from
+  // clamped in-bounds indices; entries past the tile / segment are replaced
+  // by zero when staged (masks ma, mb).
   double ra[4], rbv[4];
+  bool ma[4], mb[4];
   auto fetch = [&](int b0) {
+    int64_t zb[4], ti[4];
+    int hv[4];
+    bool rl[4];
     if (b0 >= a0 + TILE - 1) {  // every b of the chunk >= every a of the tile
       const int bi = tid & (KC - 1), b = b0 + bi;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int ai = (tid >> 4) + 16 * q, aa = a0 + ai;
-        ra[q] = (aa < m && b < be) ? Z[zat(S, cola[ai], k, b)] : 0.0;
+        const int ai = (tid >> 4) + 16 * q;
+        const ZCol c = cola[ai];
+        ma[q] = a0 + ai < m && b < be;
+        zb[q] = c.colbase;
+        rl[q] = c.tb >= 0;
+        hv[q] = b;
+        ti[q] = c.tb + b - k;
       }
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int bi = sc + 4 * q, b = b0 + bi;
-        double z = 0.0;
-        if (a < m && b < be) z = Z[a >= b ? zat(S, colseg[b - bs], k, a) : zat(S, ca, k, b)];
-        ra[q] = z;
+        const int b = b0 + sc + 4 * q;
+        const ZCol c = a >= b ? colseg[min(b - bs, kSiSeg - 1)] : ca;
+        const int hi = a >= b ? a : b;
+        ma[q] = a < m && b < be;
+        zb[q] = c.colbase;
+        rl[q] = c.tb >= 0;
+        hv[q] = hi;
+        ti[q] = c.tb + hi - k;
       }
     }
+    int tp[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tp[q] = S.tpos[(ma[q] && rl[q]) ? ti[q] : 0];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int b = b0 + sc + 4 * q;
-      rbv[q] = (b < be && sr < kp) ? Lj[(int64_t)(c0 + sr) * m + b] : 0.0;
+      mb[q] = b < be && sr < kp;
+      rbv[q] = Lj[(int64_t)(c0 + min(sr, kp - 1)) * m + min(b, be - 1)];
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ra[q] = Z[ma[q] ? zb[q] + (rl[q] ? (int64_t)tp[q] : (int64_t)hv[q]) : 0];
   };
   fetch(bs);
   for (int b0 = bs; b0 < be; b0 += KC) {
     if (b0 >= a0 + TILE - 1) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) As[(tid & (KC - 1)) * ALD + (tid >> 4) + 16 * q] = ra[q];
+      for (int q = 0; q < 4; ++q) As[(tid & (KC - 1)) * ALD + (tid >> 4) + 16 * q] = ma[q] ? here(ra[q]) : 0.0;
     } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) As[(sc + 4 * q) * ALD + sr] = ra[q];  // As[kb][a - a0]
+      for (int q = 0; q < 4; ++q) As[(sc + 4 * q) * ALD + sr] = ma[q] ? here(ra[q]) : 0.0;  // As[kb][a - a0]
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) Bs[(sc + 4 * q) * ALD + sr] = rbv[q];  // Bs[kb][t]
+    for (int q = 0; q < 4; ++q) Bs[(sc + 4 * q) * ALD + sr] = mb[q] ? here(rbv[q]) : 0.0;  // Bs[kb][t]
     __syncthreads();
     if (b0 + KC < be) fetch(b0 + KC);
 #pragma unroll
