@@ -780,13 +780,18 @@ static spchol_status run_selinv(spchol_num_s* N, hipStream_t st) {
   }
   double* ybuf = N->sibuf;
   double* tbuf = ybuf + S.si_max_y;
-  for (const Launch& l : S.si_plan) {
-    const int64_t* yoff = N->sym->si_yoff + l.slot_base;
-    HIP_TRY(timed(N, SPCHOL_KERNEL_SELINV, 0.0, 0.0, st, [&] {
-      return launch_si(D, l.kind, l.off, l.ntasks, N->L, N->winv, N->Z, yoff, ybuf, tbuf, st);
-    }));
-  }
-  return SPCHOL_OK;
+  // the launch sequence (kernels only: the Y blocks and T accumulators are
+  // left zero by their readers) goes through the graph cache like the
+  // factorization and the solves
+  return cached_run(N, 2, N->Z, 0, 0, st, [&]() -> spchol_status {
+    for (const Launch& l : S.si_plan) {
+      const int64_t* yoff = N->sym->si_yoff + l.slot_base;
+      HIP_TRY(timed(N, SPCHOL_KERNEL_SELINV, 0.0, 0.0, st, [&] {
+        return launch_si(D, l.kind, l.off, l.ntasks, N->L, N->winv, N->Z, yoff, ybuf, tbuf, st);
+      }));
+    }
+    return SPCHOL_OK;
+  });
 }
 
 spchol_status spchol_backward(spchol_num num, const double* X_dev, const double* Xbar_dev, int64_t nrhs,

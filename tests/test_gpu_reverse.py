@@ -136,3 +136,29 @@ def test_finite_differences():
         worst = max(worst, abs(fd - Abar[e]) / max(abs(Abar[e]), 1e-8))
     print(f"  FD max rel error {worst:.2e}", flush=True)
     assert worst <= 1e-5
+
+
+def test_selected_inverse_graph_replays():
+    """On a stream of its own, repeated selected inversions go through the
+    graph cache (eager, then captured, then replayed); every call, with
+    other work and synchronizations between them, matches the first one
+    (eager) to rounding (the Y blocks are summed with atomics)."""
+    n, cp, ri, vv, perm, z = CASES["cfg1_10_z8"]()
+    print(f"selinv graph replays n={n}", flush=True)
+    S = sc.SparseCholesky(n, cp, ri, perm, 0, z)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        F = S.factor(torch.tensor(vv, device="cuda"))
+        ref = F.selinv().clone()
+        torch.cuda.synchronize()
+        scale = ref.abs().max().item()
+        B = torch.randn(3, n, dtype=torch.float64, device="cuda")
+        for it in range(5):
+            Z = F.selinv()
+            torch.cuda.synchronize()
+            err = (Z - ref).abs().max().item() / scale
+            print(f"  call {it}: max rel difference {err:.2e}", flush=True)
+            assert err <= 1e-12
+            X = B.clone()
+            F.solve_(X)  # other work between the calls
+            torch.cuda.synchronize()
