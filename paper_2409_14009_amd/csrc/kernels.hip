@@ -1414,33 +1414,64 @@ __global__ __launch_bounds__(256) void k_si_zb(DevSym S, const double* __restric
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double* __restrict__ Y = ybuf + yoff[slot];
   const double* __restrict__ W = winv + S.wbase[J] + (int64_t)p * S.nb * S.nb;  // kp x kp, column-major
-  for (int idx = tid; idx < NBMAX * NBMAX; idx += 256) {
-    const int r = idx >> 6, c = idx & 63;  // Y row-major
+  const double* __restrict__ Lp = L + S.loff[J] + (int64_t)c0 * m;
+  double* __restrict__ Zp = Z + S.loff[J] + (int64_t)c0 * m;
+  // every load at the start, from clamped in-bounds addresses (entries
+  // past the block replaced by zero when staged): the Y block (row-major),
+  // W, and the tile of L_Bp for T
+  double yv[NBMAX * NBMAX / 256], wv[NBMAX * NBMAX / 256], lv[NBMAX * NBMAX / 256];
+#pragma unroll
+  for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+    const int idx = u * 256 + tid, r = idx >> 6, c = idx & 63;
+    yv[u] = Y[(int64_t)(min(a0 + r, m - 1) - rb) * NBMAX + c];
+    wv[u] = W[min(c, kp - 1) * kp + min(r, kp - 1)];
+    lv[u] = Lp[(int64_t)min(r, kp - 1) * m + min(a0 + c, m - 1)];  // (row a0 + c, column r)
+  }
+#pragma unroll
+  for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+    const int idx = u * 256 + tid, r = idx >> 6, c = idx & 63;
     const bool iny = a0 + r < m;
-    double* yp = Y + (int64_t)(a0 + r - rb) * NBMAX + c;
-    As[c * DLD + r] = (iny && c < kp) ? *yp : 0.0;
-    if (iny) *yp = 0.0;  // leave Y cleared for the next round
+    As[c * DLD + r] = (iny && c < kp) ? here(yv[u]) : 0.0;
+    if (iny) Y[(int64_t)(a0 + r - rb) * NBMAX + c] = 0.0;  // leave Y cleared for the next round
     // V = W^T column-major: Wc[c * DLD + i] = V_ic = W_ci, i.e. Wc[r * DLD + c] = W_rc
-    Wc[r * DLD + c] = (r < kp && c < kp) ? W[c * kp + r] : 0.0;
+    Wc[r * DLD + c] = (r < kp && c < kp) ? here(wv[u]) : 0.0;
   }
   __syncthreads();
-  double* __restrict__ Zp = Z + S.loff[J] + (int64_t)c0 * m;
-  // Z_Bp = -(Y V^T) = -(Y W)
-  tile_mfma(As, Wc, kp, lane, w, Zp, m, a0, m, false, -1.0);
+  // Z_Bp = -(Y V^T) = -(Y W); wavefront w: columns 16w.., rows 16 rb2 + 4v + lk
+  const bool act = MB * w < kp;
+  const int li = lane & 15, lk = lane >> 4, cz = MB * w + li;
+  d4 zacc[4];
+  if (act) {
+    tile_mfma_acc(As, Wc, kp, lane, w, zacc);
+    if (cz < kp) {
+#pragma unroll
+      for (int rb2 = 0; rb2 < 4; ++rb2)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = 16 * rb2 + 4 * v + lk;
+          if (a0 + rr < m) Zp[(int64_t)cz * m + a0 + rr] = -zacc[rb2][v];
+        }
+    }
+  }
   __syncthreads();
-  // T partial: stage Z tile (column-major, zero past m) in As and L_Bp tile in Wc
-  const double* __restrict__ Lp = L + S.loff[J] + (int64_t)c0 * m;
-  for (int idx = tid; idx < NBMAX * NBMAX; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    const bool in = a0 + r < m && c < kp;
-    As[c * DLD + r] = in ? Zp[(int64_t)c * m + a0 + r] : 0.0;
-    Wc[c * DLD + r] = in ? Lp[(int64_t)c * m + a0 + r] : 0.0;
+  // T partial: the Z tile (column-major, zero past m / kp) from the
+  // accumulators into As, the L_Bp tile into Wc
+#pragma unroll
+  for (int rb2 = 0; rb2 < 4; ++rb2)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rr = 16 * rb2 + 4 * v + lk;
+      As[cz * DLD + rr] = (act && cz < kp && a0 + rr < m) ? -zacc[rb2][v] : 0.0;
+    }
+#pragma unroll
+  for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+    const int idx = u * 256 + tid, r = idx >> 6, c = idx & 63;
+    Wc[r * DLD + c] = (a0 + c < m && r < kp) ? here(lv[u]) : 0.0;
   }
   __syncthreads();
   // T[s][c] = sum_r Z[r][s] L[r][c]: A operand A[s][r] = Z[r][s] = As[s * DLD + r],
   // B operand B[r][c] = L[r][c] = Wc[c * DLD + r]; wavefront w owns columns 16w..
   if (MB * w < kp) {
-    const int li = lane & 15, lk = lane >> 4;
     d4 acc[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
@@ -1476,13 +1507,23 @@ __global__ __launch_bounds__(256) void k_si_zd(DevSym S, const double* __restric
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const double* __restrict__ W = winv + S.wbase[J] + (int64_t)p * S.nb * S.nb;  // kp x kp, column-major
   double* __restrict__ T = tbuf + (int64_t)slot * NBMAX * NBMAX;
-  for (int idx = tid; idx < NBMAX * NBMAX; idx += 256) {
-    const int r = idx >> 6, c = idx & 63;
+  // every load at the start (clamped, entries past kp replaced by zero)
+  double w1[NBMAX * NBMAX / 256], w2[NBMAX * NBMAX / 256], tv[NBMAX * NBMAX / 256];
+#pragma unroll
+  for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+    const int idx = u * 256 + tid, r = idx >> 6, c = idx & 63;
+    w1[u] = W[min(r, kp - 1) * kp + min(c, kp - 1)];
+    w2[u] = W[min(c, kp - 1) * kp + min(r, kp - 1)];
+    tv[u] = T[idx];
+  }
+#pragma unroll
+  for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+    const int idx = u * 256 + tid, r = idx >> 6, c = idx & 63;
     const bool in = r < kp && c < kp;
     // M = W^T - T column-major: As[c * DLD + r] = W[c][r] - T[r][c]
-    As[c * DLD + r] = (in ? W[r * kp + c] : 0.0) - T[idx];
+    As[c * DLD + r] = (in ? here(w1[u]) : 0.0) - here(tv[u]);
     T[idx] = 0.0;  // leave T cleared for the next round
-    Wc[r * DLD + c] = in ? W[c * kp + r] : 0.0;  // V = W^T column-major: Wc[r * DLD + c] = W_rc
+    Wc[r * DLD + c] = in ? here(w2[u]) : 0.0;  // V = W^T column-major: Wc[r * DLD + c] = W_rc
   }
   __syncthreads();
   double* __restrict__ Zp = Z + S.loff[J] + (int64_t)c0 * m;
