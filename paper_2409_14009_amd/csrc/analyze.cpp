@@ -401,6 +401,20 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
           by += 8.0 * double(kk) * double((r1 - t.a) + (c1 - t.b)) + 16.0 * double(valid);
           break;
         }
+        case K_FWD2:
+          if (t.c & 2) {
+            // z_p, the coupling block (kp1 x kp), z_{p+1}; the tile's rows in
+            // both panels' columns
+            const int64_t kp = std::min<int64_t>(nb, k - int64_t(t.a) * nb);
+            const int64_t c1 = int64_t(t.a) * nb + kp, kp1 = std::min<int64_t>(nb, k - c1);
+            const int64_t nr = t.b < 0 ? 0 : std::min<int64_t>(t.b + kTile, m) - t.b;
+            fl += double(kp) * double(kp) + 2.0 * double(kp1) * double(kp) + double(kp1) * double(kp1) +
+                  2.0 * double(nr) * double(kp + kp1);
+            by += 8.0 * double(nr) * double(kp + kp1) + 16.0 * double(nr) +
+                  ((t.c & 1) ? 8.0 * double(kp * (kp + 1) / 2 + kp1 * (kp1 + 1) / 2 + kp1 * kp) : 0.0);
+            break;
+          }
+          [[fallthrough]];
         case K_FWD:
         case K_BWD: {
           // the rows of L below the panel that the task covers, read once;
@@ -409,9 +423,9 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
           const int64_t kp = std::min<int64_t>(nb, k - int64_t(t.a) * nb);
           int64_t nr = 0;
           bool once = false;
-          if (kind == K_FWD) {
+          if (kind == K_FWD || kind == K_FWD2) {
             nr = t.b < 0 ? 0 : std::min<int64_t>(t.b + kTile, m) - t.b;
-            once = t.c == 1;
+            once = (t.c & 1) != 0;
           } else {
             nr = t.c < 0 ? m - t.b : (t.c == 0 ? std::min<int64_t>(t.b + kTile, m) - t.b : int64_t(t.c) - 1);
             once = t.c != 0;
@@ -538,21 +552,28 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       S.tasks.insert(S.tasks.end(), far.begin(), far.end());
       close(S.factor_plan);
     }
-    // forward solve: leaves to root, panels ascending; one launch per
-    // round, one task per 64-row tile below the panel (c = 1 on the first
-    // one, which also stores the panel's part of the solution); a panel
-    // with no rows below gets one task with b = -1
+    // forward solve: leaves to root, panels ascending, one launch per round
+    // of two panels: a supernode with panels p and p + 1 gets two-panel
+    // tasks (c bit 1: z_p, the coupling block's update of panel p + 1's
+    // right-hand side, z_{p+1}, then a 64-row tile below panel p + 1 with
+    // both), one whose last panel is p single-panel tasks; one task per
+    // 64-row tile (c bit 0 on the first, which also stores the solution);
+    // no rows below: one task with b = -1
     for (int64_t l = 0; l < S.nlevels; ++l) {
       int64_t maxp = 0;
       for (int32_t J : bylev[l]) maxp = std::max(maxp, npan(J));
-      for (int64_t p = 0; p < maxp; ++p) {
-        open(S.fwd_plan, K_FWD, (int32_t)l, (int32_t)p);
+      for (int64_t p = 0; p < maxp; p += 2) {
+        bool two = false;
+        for (int32_t J : bylev[l]) two = two || npan(J) > p + 1;
+        open(S.fwd_plan, two ? K_FWD2 : K_FWD, (int32_t)l, (int32_t)p);
         for (int32_t J : bylev[l]) {
           if (npan(J) <= p) continue;
-          const int64_t below = p * nb + kpan(J, p);
-          if (below >= M(J)) S.tasks.push_back({J, (int32_t)p, -1, 1});
+          const bool dbl = npan(J) > p + 1;
+          const int64_t below = dbl ? (p + 1) * nb + kpan(J, p + 1) : p * nb + kpan(J, p);
+          const int32_t f = dbl ? 2 : 0;
+          if (below >= M(J)) S.tasks.push_back({J, (int32_t)p, -1, f | 1});
           for (int64_t r0 = below; r0 < M(J); r0 += kTile)
-            S.tasks.push_back({J, (int32_t)p, (int32_t)r0, r0 == below ? 1 : 0});
+            S.tasks.push_back({J, (int32_t)p, (int32_t)r0, f | (r0 == below ? 1 : 0)});
         }
         close(S.fwd_plan);
       }

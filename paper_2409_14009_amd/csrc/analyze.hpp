@@ -24,6 +24,9 @@ namespace spchol {
 //              a supernode for which small_supernode holds)
 //   FWD        J, panel, first local row of a 64-row tile below the panel
 //              (-1: the panel has no rows below), 1 on the panel's first task
+//   FWD2       as FWD; c bit 1 set: the task covers panels p and p + 1 (its
+//              tile lies below panel p + 1; bit 0: it also stores both
+//              panels' solution)
 //   BWD        J, panel, first local row of the task's rows, and -1 (all
 //              rows below the panel, then the diagonal block), 0 (one 64-row
 //              tile, summed into the accumulator) or 1 + n (n rows, then the
@@ -45,6 +48,7 @@ enum Kind : int32_t {
   K_SI_ZD = 11, // Z_pp = (W^T - T) W
   K_FACTOR_LA = 12,
   K_SMALL = 13,  // a supernode whose whole numeric step fits one wavefront
+  K_FWD2 = 14,   // forward solve round with two-panel tasks
 };
 
 // Supernodes done by one wavefront (K_SMALL): at most 16 columns, and with

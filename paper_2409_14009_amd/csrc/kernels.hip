@@ -1068,6 +1068,132 @@ __global__ __launch_bounds__(256) void k_fwd(DevSym S, const double* __restrict_
   for (int64_t cb = 4; cb < nrhs; cb += 4) block(cb);
 }
 
+// Forward round with two-panel tasks (c bit 1; single-panel tasks of
+// supernodes whose last panel is p run as in k_fwd): z_p = W_p y_p, the
+// right-hand side of panel p + 1 less the coupling block's share,
+// t = y_{p+1} - L_{p+1,p} z_p, then z_{p+1} = W_{p+1} t; the first task
+// stores both, and the tile below panel p + 1 gets
+// y_R -= L_Rp z_p + L_R,p+1 z_{p+1}.  One launch instead of two for the
+// panel pair; the same thread layout as k_fwd (wavefront w: columns 16w..,
+// lane: row), every load issued at the start.
+__global__ __launch_bounds__(256) void k_fwd2(DevSym S, const double* __restrict__ L, const double* __restrict__ winv,
+                                              int64_t off, double* __restrict__ y, double* __restrict__ x,
+                                              int64_t nrhs) {
+  __shared__ double ys[4][NBMAX], ys1[4][NBMAX];
+  __shared__ double zs[4][NBMAX], zs1[4][NBMAX];
+  __shared__ double part[4][4][NBMAX];
+  const DevTask t = S.tasks[off + blockIdx.x];
+  const int J = t.J, p = t.a, r0 = t.b;
+  const bool first = (t.c & 1) != 0, dbl = (t.c & 2) != 0;
+  const int m = S.sm[J], k = S.sk[J];
+  const int c0 = p * S.nb, kp = min(S.nb, k - c0);
+  const int c1 = c0 + kp, kp1 = dbl ? min(S.nb, k - c1) : 1;  // (1: a valid clamp when single)
+  const double* __restrict__ Lj = L + S.loff[J];
+  const double* __restrict__ W = winv + S.wbase[J] + (int64_t)p * S.nb * S.nb;
+  const double* __restrict__ W1 = dbl ? W + (int64_t)S.nb * S.nb : W;
+  const int32_t* __restrict__ R = S.rows + S.rptr[J];
+  const int64_t fcol = S.sfirst[J] + c0, fcol1 = fcol + kp;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int t0 = 16 * w, t1 = min(kp, t0 + 16), t1b = dbl ? min(kp1, t0 + 16) : 0;
+  const int row = r0 + lane;
+  const bool rowok = r0 >= 0 && row < m;
+  const int32_t grow = R[rowok ? row : 0];
+  double wr[16], lr[16], wr1[16], lc[16], lr1[16];
+  {
+    const int il = min(lane, kp - 1), il1 = min(lane, kp1 - 1), rl = rowok ? row : 0;
+    const int rc = min(c1 + lane, m - 1);  // (a row of panel p + 1 when double)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int tt = t0 + u, tc = min(tt, kp - 1), tc1 = min(tt, kp1 - 1);
+      wr[u] = W[(int64_t)tc * kp + il];
+      lr[u] = Lj[(int64_t)(c0 + tc) * m + rl];
+      wr1[u] = W1[(int64_t)tc1 * kp1 + il1];
+      lc[u] = Lj[(int64_t)(c0 + tc) * m + rc];
+      lr1[u] = Lj[(int64_t)(dbl ? c1 + tc1 : c0 + tc) * m + rl];
+    }
+  }
+  // sum over the four wavefronts of v (thread (lane, w): RHS q, entry lane)
+  auto reduce = [&](const double (&v)[4], double (*out)[NBMAX]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[w][q][lane] = v[q];
+    __syncthreads();
+    out[w][lane] = (part[0][w][lane] + part[1][w][lane]) + (part[2][w][lane] + part[3][w][lane]);
+    __syncthreads();
+  };
+  auto block = [&](int64_t cb) {
+    {
+      const int64_t c = cb + w;  // thread (lane, w) loads entry lane of RHS cb + w
+      ys[w][lane] = (lane < kp && c < nrhs) ? y[fcol + lane + c * S.n] : 0.0;
+      ys1[w][lane] = (dbl && lane < kp1 && c < nrhs) ? y[fcol1 + lane + c * S.n] : 0.0;
+    }
+    __syncthreads();
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const double a = (t0 + u < t1 && lane < kp) ? here(wr[u]) : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = fma(a, ys[q][t0 + u], v[q]);
+    }
+    reduce(v, zs);  // z_p
+    if (first && lane < kp && cb + w < nrhs) x[fcol + lane + (cb + w) * S.n] = zs[w][lane];
+    if (dbl) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const double a = (t0 + u < t1 && lane < kp1) ? here(lc[u]) : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = fma(a, zs[q][t0 + u], v[q]);
+      }
+      reduce(v, part[0]);  // (the coupling block's share, in a free slot)
+      ys1[w][lane] -= part[0][w][lane];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const double a = (t0 + u < t1b && lane < kp1) ? here(wr1[u]) : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = fma(a, ys1[q][t0 + u], v[q]);
+      }
+      reduce(v, zs1);  // z_{p+1}
+      if (first && lane < kp1 && cb + w < nrhs) x[fcol1 + lane + (cb + w) * S.n] = zs1[w][lane];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const double a = (t0 + u < t1 && rowok) ? here(lr[u]) : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = fma(a, zs[q][t0 + u], v[q]);
+    }
+    if (dbl) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const double a = (t0 + u < t1b && rowok) ? here(lr1[u]) : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = fma(a, zs1[q][t0 + u], v[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[w][q][lane] = v[q];
+    __syncthreads();
+    {
+      const int q = w, i = lane;
+      const int64_t c = cb + q;
+      if (rowok && c < nrhs) {
+        const double sv = (part[0][q][i] + part[1][q][i]) + (part[2][q][i] + part[3][q][i]);
+        double* dst = y + grow + c * S.n;
+        if (r0 + i < k) *dst -= sv;
+        else atomicAdd(dst, -sv);
+      }
+    }
+    __syncthreads();
+  };
+  block(0);
+  for (int64_t cb = 4; cb < nrhs; cb += 4) block(cb);
+}
+
 // The panel's inverted diagonal block (kp x kp, column-major) into LDS,
 // Ws[c][r] = W_rc, zero past kp; coalesced.
 __device__ __forceinline__ void stage_w(const double* __restrict__ W, int kp, double (*Ws)[NBMAX + 1], int tid,
@@ -1751,6 +1877,7 @@ hipError_t launch_solve_step(const DevSym& S, const double* L, const double* win
                              int32_t ntasks, double* y, double* x, double* acc, int64_t nrhs, hipStream_t st) {
   if (ntasks <= 0) return hipSuccess;
   if (kind == 3) k_fwd<<<ntasks, 256, 0, st>>>(S, L, winv, off, y, x, nrhs);
+  else if (kind == 14) k_fwd2<<<ntasks, 256, 0, st>>>(S, L, winv, off, y, x, nrhs);
   else k_bwd<<<ntasks, 256, 0, st>>>(S, L, winv, off, x, acc, nrhs);
   return hipGetLastError();
 }

@@ -234,27 +234,49 @@ int main(int argc, char** argv) {
         const int64_t below = p * nb + std::min<int64_t>(nb, K(J) - p * nb);
         for (int64_t r = below; r < M(J); ++r) ye[S.rows[S.rptr[J] + r]] += 1;
       }
+    // a two-panel task (FWD2, c bit 1) reads panel p + 1's right-hand side
+    // lacking exactly panel p's contribution, which it applies itself (the
+    // first task credits it once); its tile rows get both panels'
+    std::vector<int64_t> credited(N, -1);
     Access ya(N), xa(N);
     for (const Launch& L : S.fwd_plan) {
       ++g_launch;
+      if (L.kind != K_FWD && L.kind != K_FWD2) { ok = fail("unknown launch kind in the forward plan"); break; }
       for (int32_t q = 0; q < L.ntasks && ok; ++q) {
         const Task& t = S.tasks[L.off + q];
+        const bool first = (t.c & 1) != 0, dbl = L.kind == K_FWD2 && (t.c & 2) != 0;
+        if (L.kind == K_FWD && t.c != 0 && t.c != 1) ok = fail("unexpected forward task flag");
         const int64_t J = t.J, c0 = int64_t(t.a) * nb, kp = std::min<int64_t>(nb, K(J) - c0);
         const int64_t f0 = S.sptr[J] + c0;
+        if (dbl && c0 + kp >= K(J)) ok = fail("two-panel task for a supernode's last panel");
+        const int64_t kp1 = dbl ? std::min<int64_t>(nb, K(J) - c0 - kp) : 0, f1 = f0 + kp;
         for (int64_t i = 0; i < kp && ok; ++i) {
           if (yg[f0 + i] != ye[f0 + i]) ok = fail("forward solve reads an incomplete right-hand side");
           else ok = on_read(ya, f0 + i, q);
-          if (ok && t.c == 1) {
+          if (ok && first) {
             if (xdone[f0 + i]) ok = fail("forward solution written twice");
             xdone[f0 + i] = 1;
             ok = ok && on_write(xa, f0 + i, q, false);
           }
         }
+        for (int64_t i = 0; i < kp1 && ok; ++i) {
+          const bool done_here = credited[f1 + i] == g_launch;
+          if (yg[f1 + i] != ye[f1 + i] - (done_here ? 0 : 1))
+            ok = fail("two-panel task reads an incomplete right-hand side of the second panel");
+          else ok = on_read(ya, f1 + i, q);
+          if (ok && first) {
+            if (xdone[f1 + i]) ok = fail("forward solution written twice");
+            xdone[f1 + i] = 1;
+            ok = on_write(xa, f1 + i, q, false);
+            if (!done_here) { yg[f1 + i] += 1; credited[f1 + i] = g_launch; }
+          }
+        }
+        if (ok && dbl && t.b >= 0 && t.b < c0 + kp + kp1) ok = fail("two-panel tile overlaps the second panel");
         if (t.b >= 0)
           for (int64_t r = t.b; r < std::min<int64_t>(int64_t(t.b) + kTile, M(J)) && ok; ++r) {
             const int64_t g = S.rows[S.rptr[J] + r];
             ok = on_write(ya, g, q, r >= K(J));
-            yg[g] += 1;
+            yg[g] += dbl ? 2 : 1;
           }
       }
       if (!ok) break;
@@ -328,10 +350,13 @@ int main(int argc, char** argv) {
   int64_t bsplit = 0;
   for (const Launch& L : S.bwd_plan)
     for (int32_t q = 0; q < L.ntasks; ++q) bsplit += S.tasks[L.off + q].c > 0;
-  int64_t nsmall = 0;
+  int64_t nsmall = 0, nfwd2 = 0;
   for (const Launch& L : S.factor_plan)
     if (L.kind == K_SMALL) nsmall += L.ntasks;
-  std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld small=%lld\n", S.factor_plan.size(), S.fwd_plan.size(),
-              S.bwd_plan.size(), (long long)bsplit, (long long)nsmall);
+  for (const Launch& L : S.fwd_plan)
+    if (L.kind == K_FWD2)
+      for (int32_t q = 0; q < L.ntasks; ++q) nfwd2 += (S.tasks[L.off + q].c & 2) != 0;
+  std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld fwd2=%lld small=%lld\n", S.factor_plan.size(),
+              S.fwd_plan.size(), S.bwd_plan.size(), (long long)bsplit, (long long)nfwd2, (long long)nsmall);
   return 0;
 }

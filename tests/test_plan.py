@@ -51,6 +51,8 @@ def test_grid3d(checker, tmp_path, side, z, nb):
         # panels with more than 512 rows below: the backward solve's split
         # (lookahead) tasks are part of the replay
         assert int(out.split("split_bwd=")[1].split()[0]) > 0, out
+        # supernodes of several panels: two-panel forward tasks
+        assert int(out.split("fwd2=")[1].split()[0]) > 0, out
     # the leaves of the dissection are done by one-wavefront tasks
     assert int(out.split("small=")[1]) > 0, out
 
