@@ -214,3 +214,49 @@ def test_graph_cache_repeated_calls():
         F.solve_(X)
         eta, _ = oracle.backward_error(A, X.cpu().numpy().T, B[:, :2])
         assert eta.max() <= 1e-12
+
+
+def test_graph_replay_fp32_updates():
+    """A batch factored with fp32 update products and captured: every
+    replay matches the eager fp32 factor and solve (same arithmetic;
+    atomics only reorder fp64 sums of the rounded products), and the
+    unrefined solve's backward error sits at fp32 level, well above fp64
+    rounding (the reduced-precision products are really used)."""
+    print("case graph replay fp32 count=24", flush=True)
+    probs, mats, vals, Bt = _batch(24, nrhs=2)
+    S = sc.BatchCholesky(mats, amalg_max_zeros=8)
+    cnt, co, no = S.batch_info()
+    v = torch.tensor(vals, device="cuda")
+    F = S.factor(v, precision="f32")
+    eager_ld = F.logdet_batch().cpu().numpy()
+    B0 = torch.tensor(Bt, device="cuda")
+    Xe = B0.clone()
+    F.solve_(Xe)
+    Xe = Xe.cpu().numpy()
+    stream = torch.cuda.Stream()
+    Xg = torch.empty_like(B0)
+    with torch.cuda.stream(stream):
+        G = F.capture(v, Xg, stream=stream)
+    for r in range(3):
+        with torch.cuda.stream(stream):
+            Xg.fill_(0.0)
+            junk = torch.randn(1 << 18, device="cuda", dtype=torch.float64).sum()
+            Xg.copy_(B0)
+            G.replay(stream)
+            lds = F.logdet_batch(stream=stream)
+            assert F.status(stream) == 0
+        stream.synchronize()
+        lds = lds.cpu().numpy()
+        Xr = Xg.cpu().numpy()
+        assert np.all(np.abs(lds - eager_ld) <= 1e-10 * np.maximum(np.abs(eager_ld), 1.0)), r
+        ex = np.abs(Xr - Xe).max() / np.abs(Xe).max()
+        assert ex <= 1e-10, (r, ex)
+        del junk
+    worst = 0.0
+    for b, p in enumerate(probs):
+        A = oracle.full_matrix(p.n, p.colptr, p.rowind, p.vals)
+        eta, _ = oracle.backward_error(A, Xr[:, co[b]:co[b + 1]].T, p.B)
+        worst = max(worst, float(eta.max()))
+    print(f"  worst unrefined eta {worst:.2e}", flush=True)
+    assert 1e-14 <= worst <= 1e-5
+    G.close()
