@@ -415,6 +415,13 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
             break;
           }
           [[fallthrough]];
+        case K_FWD_SMALL:
+        case K_BWD_SMALL: {
+          const int64_t nr = m - k;
+          fl += 2.0 * double(nr) * double(k) + double(k) * double(k);
+          by += 8.0 * double(nr) * double(k) + 16.0 * double(nr) + 8.0 * double(k * (k + 1) / 2);
+          break;
+        }
         case K_FWD:
         case K_BWD: {
           // the rows of L below the panel that the task covers, read once;
@@ -559,14 +566,33 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
     // both), one whose last panel is p single-panel tasks; one task per
     // 64-row tile (c bit 0 on the first, which also stores the solution);
     // no rows below: one task with b = -1
+    // Small one-panel supernodes of a level that holds many of them get a
+    // launch of their own (one wavefront each) in both solves; `rest` is the
+    // level without them.
+    std::vector<std::vector<int32_t>> rest(S.nlevels), smalls(S.nlevels);
     for (int64_t l = 0; l < S.nlevels; ++l) {
+      for (int32_t J : bylev[l])
+        (small_solve_supernode(K(J), M(J), nb) ? smalls[l] : rest[l]).push_back(J);
+      if ((int64_t)smalls[l].size() < kSmallSolveMin) {
+        rest[l] = bylev[l];
+        smalls[l].clear();
+      }
+    }
+    auto small_launch = [&](std::vector<Launch>& plan, int32_t kind, int64_t l) {
+      if (smalls[l].empty()) return;
+      open(plan, kind, (int32_t)l, 0);
+      for (int32_t J : smalls[l]) S.tasks.push_back({J, 0, (int32_t)K(J), 1});
+      close(plan);
+    };
+    for (int64_t l = 0; l < S.nlevels; ++l) {
+      small_launch(S.fwd_plan, K_FWD_SMALL, l);
       int64_t maxp = 0;
-      for (int32_t J : bylev[l]) maxp = std::max(maxp, npan(J));
+      for (int32_t J : rest[l]) maxp = std::max(maxp, npan(J));
       for (int64_t p = 0; p < maxp; p += 2) {
         bool two = false;
-        for (int32_t J : bylev[l]) two = two || npan(J) > p + 1;
+        for (int32_t J : rest[l]) two = two || npan(J) > p + 1;
         open(S.fwd_plan, two ? K_FWD2 : K_FWD, (int32_t)l, (int32_t)p);
-        for (int32_t J : bylev[l]) {
+        for (int32_t J : rest[l]) {
           if (npan(J) <= p) continue;
           const bool dbl = npan(J) > p + 1;
           const int64_t below = dbl ? (p + 1) * nb + kpan(J, p + 1) : p * nb + kpan(J, p);
@@ -588,8 +614,9 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
     // panel, subtracts the accumulator and applies the inverse.  The far
     // tiles of a level's first round run in a launch of their own.
     for (int64_t l = S.nlevels - 1; l >= 0; --l) {
+      small_launch(S.bwd_plan, K_BWD_SMALL, l);
       int64_t maxp = 0;
-      for (int32_t J : bylev[l]) maxp = std::max(maxp, npan(J));
+      for (int32_t J : rest[l]) maxp = std::max(maxp, npan(J));
       auto below = [&](int32_t J, int64_t p) { return p * nb + kpan(J, p); };
       auto split = [&](int32_t J, int64_t p) { return p >= 0 && p < npan(J) && M(J) - below(J, p) > kBwdRows; };
       auto near = [&](int32_t J, int64_t p) { return p + 1 < npan(J) ? kpan(J, p + 1) : int64_t(0); };
@@ -598,21 +625,21 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
           S.tasks.push_back({J, (int32_t)p, (int32_t)r0, 0});
       };
       bool pro = false;
-      for (int32_t J : bylev[l]) pro = pro || split(J, maxp - 1);
+      for (int32_t J : rest[l]) pro = pro || split(J, maxp - 1);
       if (pro) {
         open(S.bwd_plan, K_BWD, (int32_t)l, (int32_t)maxp);
-        for (int32_t J : bylev[l])
+        for (int32_t J : rest[l])
           if (split(J, maxp - 1)) far_tiles(J, maxp - 1);
         close(S.bwd_plan);
       }
       for (int64_t p = maxp - 1; p >= 0; --p) {
         open(S.bwd_plan, K_BWD, (int32_t)l, (int32_t)p);
-        for (int32_t J : bylev[l]) {
+        for (int32_t J : rest[l]) {
           if (npan(J) <= p) continue;
           if (split(J, p)) S.tasks.push_back({J, (int32_t)p, (int32_t)below(J, p), (int32_t)(1 + near(J, p))});
           else S.tasks.push_back({J, (int32_t)p, (int32_t)below(J, p), -1});
         }
-        for (int32_t J : bylev[l])
+        for (int32_t J : rest[l])
           if (split(J, p - 1)) far_tiles(J, p - 1);
         close(S.bwd_plan);
       }

@@ -27,6 +27,8 @@ namespace spchol {
 //   FWD2       as FWD; c bit 1 set: the task covers panels p and p + 1 (its
 //              tile lies below panel p + 1; bit 0: it also stores both
 //              panels' solution)
+//   FWD_SMALL, BWD_SMALL  J, 0, k_J, 1 (a supernode for which
+//              small_solve_supernode holds: all its rows in one task)
 //   BWD        J, panel, first local row of the task's rows, and -1 (all
 //              rows below the panel, then the diagonal block), 0 (one 64-row
 //              tile, summed into the accumulator) or 1 + n (n rows, then the
@@ -49,6 +51,8 @@ enum Kind : int32_t {
   K_FACTOR_LA = 12,
   K_SMALL = 13,  // a supernode whose whole numeric step fits one wavefront
   K_FWD2 = 14,   // forward solve round with two-panel tasks
+  K_FWD_SMALL = 15,  // forward solve of small one-panel supernodes, one wavefront each
+  K_BWD_SMALL = 16,  // backward solve of the same
 };
 
 // Supernodes done by one wavefront (K_SMALL): at most 16 columns, and with
@@ -56,6 +60,13 @@ enum Kind : int32_t {
 // rows below and one unit row per column (for the inverse block) fit the
 // wavefront's 64 lanes.
 inline bool small_supernode(int64_t k, int64_t m) { return k <= 16 && (k <= 4 ? 4 : 16) + m <= 64; }
+
+// Supernodes solved by one wavefront (K_FWD_SMALL, K_BWD_SMALL): one panel
+// of at most 16 columns and at most 64 rows below it.  A level gets such a
+// launch when it holds at least kSmallSolveMin of them (else they stay in
+// the level's ordinary rounds: one launch fewer).
+inline bool small_solve_supernode(int64_t k, int64_t m, int64_t nb) { return k <= 16 && k <= nb && m - k <= 64; }
+constexpr int64_t kSmallSolveMin = 256;
 
 struct Launch {
   int32_t kind;

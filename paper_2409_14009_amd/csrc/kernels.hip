@@ -1068,6 +1068,126 @@ __global__ __launch_bounds__(256) void k_fwd(DevSym S, const double* __restrict_
   for (int64_t cb = 4; cb < nrhs; cb += 4) block(cb);
 }
 
+// Solve rounds of small supernodes: one panel of at most 16 columns with at
+// most 64 rows below it (the leaf levels of a nested-dissection ordering,
+// thousands of supernodes a level).  One wavefront per supernode, four per
+// workgroup, no LDS and no barrier: lane i holds row (forward) or column
+// (backward) i of the inverted diagonal block and row k + i of L, and the
+// solution entries pass from lane to lane by readlane.  Task: J, 0, k_J, 1.
+constexpr int kSmallSolveCols = 16;
+
+// Forward: z = W y_J, stored into x; y_R -= L_RJ z with atomics (the rows
+// below are ancestors', shared with other supernodes of the level).
+__global__ __launch_bounds__(256) void k_fwd_small(DevSym S, const double* __restrict__ L,
+                                                   const double* __restrict__ winv, int64_t off, int32_t ntasks,
+                                                   double* __restrict__ y, double* __restrict__ x, int64_t nrhs) {
+  const int lane = threadIdx.x & 63;
+  const int ti = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (ti >= ntasks) return;
+  const int J = S.tasks[off + ti].J;
+  const int m = S.sm[J], k = S.sk[J], nbl = m - k;
+  const double* __restrict__ Lj = L + S.loff[J];
+  const double* __restrict__ W = winv + S.wbase[J];
+  const int64_t fcol = S.sfirst[J];
+  const bool own = lane < k, below = lane < nbl;
+  // clamped in-bounds rows: the lane's row of W and its row below the
+  // diagonal block (row 0 when there is none; then unused)
+  const int il = min(lane, k - 1), rl = nbl > 0 ? k + min(lane, nbl - 1) : 0;
+  const int32_t grow = S.rows[S.rptr[J] + rl];
+  double wr[kSmallSolveCols], lr[kSmallSolveCols];
+#pragma unroll
+  for (int u = 0; u < kSmallSolveCols; ++u) {
+    const int uc = min(u, k - 1);
+    wr[u] = W[uc * k + il];
+    lr[u] = Lj[(int64_t)uc * m + rl];
+  }
+  for (int64_t c = 0; c < nrhs; ++c) {
+    const double yv = own ? y[fcol + lane + c * S.n] : 0.0;
+    double z = 0.0;
+#pragma unroll
+    for (int u = 0; u < kSmallSolveCols; ++u) z = fma(u < k ? wr[u] : 0.0, readlane_d(yv, u), z);
+    z = own ? z : 0.0;
+    if (own) x[fcol + lane + c * S.n] = z;
+    double a = 0.0;
+#pragma unroll
+    for (int u = 0; u < kSmallSolveCols; ++u) a = fma(u < k ? lr[u] : 0.0, readlane_d(z, u), a);
+    if (below) atomicAdd(y + grow + c * S.n, -a);
+  }
+}
+
+// One step of the transposing butterfly below: a lane keeps half of its h
+// partial column sums, hands the other half to the partner lane (lane ^
+// msk) and adds the partner's half of its own.
+template <int H, int MSK>
+__device__ __forceinline__ void col_sum_step(double (&v)[kSmallSolveCols], int lane) {
+  const bool hi = (lane & MSK) != 0;
+#pragma unroll
+  for (int u = 0; u < H; ++u) {
+    const double send = hi ? v[u] : v[u + H];
+    const double keep = hi ? v[u + H] : v[u];
+    v[u] = keep + __shfl_xor(send, MSK);
+  }
+}
+
+// Column sums over the wavefront of v[u] (u = column): returns, in lane l,
+// the total of column 8 b5 + 4 b4 + 2 b3 + b2 (b_i: bit i of l).  After the
+// four halving steps a lane holds that column summed over the 16 lanes that
+// differ from it in bits 5..2; two exchanges add the other three groups.
+__device__ __forceinline__ double col_sums16(double (&v)[kSmallSolveCols], int lane) {
+  col_sum_step<8, 32>(v, lane);
+  col_sum_step<4, 16>(v, lane);
+  col_sum_step<2, 8>(v, lane);
+  col_sum_step<1, 4>(v, lane);
+  double s = v[0];
+  s += __shfl_xor(s, 2);
+  s += __shfl_xor(s, 1);
+  return s;
+}
+
+// the lane that holds column u after col_sums16
+__device__ __forceinline__ constexpr int col_sum_lane(int u) {
+  return ((u >> 3) & 1) * 32 + ((u >> 2) & 1) * 16 + ((u >> 1) & 1) * 8 + (u & 1) * 4;
+}
+
+// Backward: x_J = W^T (x_J - L_RJ^T x_R) (x_R final: ancestors are done in
+// earlier rounds).
+__global__ __launch_bounds__(256) void k_bwd_small(DevSym S, const double* __restrict__ L,
+                                                   const double* __restrict__ winv, int64_t off, int32_t ntasks,
+                                                   double* __restrict__ x, int64_t nrhs) {
+  const int lane = threadIdx.x & 63;
+  const int ti = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (ti >= ntasks) return;
+  const int J = S.tasks[off + ti].J;
+  const int m = S.sm[J], k = S.sk[J], nbl = m - k;
+  const double* __restrict__ Lj = L + S.loff[J];
+  const double* __restrict__ W = winv + S.wbase[J];
+  const int64_t fcol = S.sfirst[J];
+  const bool own = lane < k, below = lane < nbl;
+  const int il = min(lane, k - 1), rl = nbl > 0 ? k + min(lane, nbl - 1) : 0;
+  const int32_t grow = S.rows[S.rptr[J] + rl];
+  // wt[u] = W_{u, lane} (column `lane` of W), lr[u] = L_{k + lane, u}
+  double wt[kSmallSolveCols], lr[kSmallSolveCols];
+#pragma unroll
+  for (int u = 0; u < kSmallSolveCols; ++u) {
+    const int uc = min(u, k - 1);
+    wt[u] = W[il * k + uc];
+    lr[u] = Lj[(int64_t)uc * m + rl];
+  }
+  for (int64_t c = 0; c < nrhs; ++c) {
+    const double xr = below ? x[grow + c * S.n] : 0.0;
+    const double xf = own ? x[fcol + lane + c * S.n] : 0.0;
+    double v[kSmallSolveCols];
+#pragma unroll
+    for (int u = 0; u < kSmallSolveCols; ++u) v[u] = (u < k && below) ? lr[u] * xr : 0.0;
+    const double s = col_sums16(v, lane);
+    double r = 0.0;
+#pragma unroll
+    for (int u = 0; u < kSmallSolveCols; ++u)
+      r = fma(u < k ? wt[u] : 0.0, readlane_d(xf, u) - readlane_d(s, col_sum_lane(u)), r);
+    if (own) x[fcol + lane + c * S.n] = r;
+  }
+}
+
 // Forward round with two-panel tasks (c bit 1; single-panel tasks of
 // supernodes whose last panel is p run as in k_fwd): z_p = W_p y_p, the
 // right-hand side of panel p + 1 less the coupling block's share,
@@ -1878,6 +1998,8 @@ hipError_t launch_solve_step(const DevSym& S, const double* L, const double* win
   if (ntasks <= 0) return hipSuccess;
   if (kind == 3) k_fwd<<<ntasks, 256, 0, st>>>(S, L, winv, off, y, x, nrhs);
   else if (kind == 14) k_fwd2<<<ntasks, 256, 0, st>>>(S, L, winv, off, y, x, nrhs);
+  else if (kind == 15) k_fwd_small<<<(ntasks + 3) / 4, 256, 0, st>>>(S, L, winv, off, ntasks, y, x, nrhs);
+  else if (kind == 16) k_bwd_small<<<(ntasks + 3) / 4, 256, 0, st>>>(S, L, winv, off, ntasks, x, nrhs);
   else k_bwd<<<ntasks, 256, 0, st>>>(S, L, winv, off, x, acc, nrhs);
   return hipGetLastError();
 }

@@ -363,7 +363,7 @@ static spchol_status enqueue_solve(spchol_num_s* num, SolveWork& w, double* B_de
     // solve flops/bytes were counted for one right-hand side; L is read once
     const double fl = l.flops * double(nrhs);
     const double by = l.bytes;
-    const bool fwd = l.kind == K_FWD || l.kind == K_FWD2;
+    const bool fwd = l.kind == K_FWD || l.kind == K_FWD2 || l.kind == K_FWD_SMALL;
     return timed_at(num, fwd ? SPCHOL_KERNEL_FWD : SPCHOL_KERNEL_BWD, l.level, 0, fl, by, st, [&] {
       return launch_solve_step(D, num->L, num->winv, l.kind, l.off, l.ntasks, w.y, w.x, w.acc, nrhs, st);
     });

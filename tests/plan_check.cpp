@@ -241,9 +241,31 @@ int main(int argc, char** argv) {
     Access ya(N), xa(N);
     for (const Launch& L : S.fwd_plan) {
       ++g_launch;
-      if (L.kind != K_FWD && L.kind != K_FWD2) { ok = fail("unknown launch kind in the forward plan"); break; }
+      if (L.kind != K_FWD && L.kind != K_FWD2 && L.kind != K_FWD_SMALL) {
+        ok = fail("unknown launch kind in the forward plan");
+        break;
+      }
       for (int32_t q = 0; q < L.ntasks && ok; ++q) {
         const Task& t = S.tasks[L.off + q];
+        if (L.kind == K_FWD_SMALL) {
+          // the whole supernode: z over its one panel, all rows below
+          if (!small_solve_supernode(K(t.J), M(t.J), nb) || t.a != 0 || t.b != K(t.J) || t.c != 1)
+            ok = fail("small forward task for a supernode that does not qualify");
+          const int64_t f0 = S.sptr[t.J];
+          for (int64_t i = 0; i < K(t.J) && ok; ++i) {
+            if (yg[f0 + i] != ye[f0 + i]) ok = fail("forward solve reads an incomplete right-hand side");
+            else ok = on_read(ya, f0 + i, q);
+            if (ok && xdone[f0 + i]) ok = fail("forward solution written twice");
+            xdone[f0 + i] = 1;
+            ok = ok && on_write(xa, f0 + i, q, false);
+          }
+          for (int64_t r = K(t.J); r < M(t.J) && ok; ++r) {
+            const int64_t g = S.rows[S.rptr[t.J] + r];
+            ok = on_write(ya, g, q, true);
+            yg[g] += 1;
+          }
+          continue;
+        }
         const bool first = (t.c & 1) != 0, dbl = L.kind == K_FWD2 && (t.c & 2) != 0;
         if (L.kind == K_FWD && t.c != 0 && t.c != 1) ok = fail("unexpected forward task flag");
         const int64_t J = t.J, c0 = int64_t(t.a) * nb, kp = std::min<int64_t>(nb, K(J) - c0);
@@ -293,7 +315,7 @@ int main(int argc, char** argv) {
     std::vector<std::vector<char>> gathered(N);
     for (const Launch& L : S.bwd_plan) {
       ++g_launch;
-      if (L.kind != K_BWD) { ok = fail("unknown launch kind in the backward plan"); break; }
+      if (L.kind != K_BWD && L.kind != K_BWD_SMALL) { ok = fail("unknown launch kind in the backward plan"); break; }
       for (int32_t q = 0; q < L.ntasks && ok; ++q) {
         const Task& t = S.tasks[L.off + q];
         const int64_t J = t.J, c0 = int64_t(t.a) * nb, kp = std::min<int64_t>(nb, K(J) - c0);
@@ -322,7 +344,13 @@ int main(int argc, char** argv) {
           for (int64_t r = below; r < M(J) && ok; ++r)
             if (!seen[r - below]) ok = fail("panel finished before all rows below it were gathered");
         };
-        if (t.c < 0) {
+        if (L.kind == K_BWD_SMALL) {
+          if (!small_solve_supernode(K(J), M(J), nb) || t.a != 0 || t.b != below || t.c != 1)
+            ok = fail("small backward task for a supernode that does not qualify");
+          gather(t.b, M(J));
+          all_gathered();
+          finish();
+        } else if (t.c < 0) {
           if (t.b != below) ok = fail("whole-panel task does not start below the panel");
           gather(t.b, M(J));
           all_gathered();
@@ -350,13 +378,16 @@ int main(int argc, char** argv) {
   int64_t bsplit = 0;
   for (const Launch& L : S.bwd_plan)
     for (int32_t q = 0; q < L.ntasks; ++q) bsplit += S.tasks[L.off + q].c > 0;
-  int64_t nsmall = 0, nfwd2 = 0;
+  int64_t nsmall = 0, nfwd2 = 0, nssolve = 0;
   for (const Launch& L : S.factor_plan)
     if (L.kind == K_SMALL) nsmall += L.ntasks;
   for (const Launch& L : S.fwd_plan)
+    if (L.kind == K_FWD_SMALL) nssolve += L.ntasks;
+  for (const Launch& L : S.fwd_plan)
     if (L.kind == K_FWD2)
       for (int32_t q = 0; q < L.ntasks; ++q) nfwd2 += (S.tasks[L.off + q].c & 2) != 0;
-  std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld fwd2=%lld small=%lld\n", S.factor_plan.size(),
-              S.fwd_plan.size(), S.bwd_plan.size(), (long long)bsplit, (long long)nfwd2, (long long)nsmall);
+  std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld fwd2=%lld small=%lld small_solve=%lld\n",
+              S.factor_plan.size(), S.fwd_plan.size(), S.bwd_plan.size(), (long long)bsplit, (long long)nfwd2,
+              (long long)nsmall, (long long)nssolve);
   return 0;
 }

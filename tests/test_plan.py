@@ -53,8 +53,11 @@ def test_grid3d(checker, tmp_path, side, z, nb):
         assert int(out.split("split_bwd=")[1].split()[0]) > 0, out
         # supernodes of several panels: two-panel forward tasks
         assert int(out.split("fwd2=")[1].split()[0]) > 0, out
-    # the leaves of the dissection are done by one-wavefront tasks
-    assert int(out.split("small=")[1]) > 0, out
+    # the leaves of the dissection are done by one-wavefront tasks, in the
+    # solves too once a level holds enough of them
+    assert int(out.split("small=")[1].split()[0]) > 0, out
+    if side == 20:
+        assert int(out.split("small_solve=")[1].split()[0]) > 0, out
 
 
 def test_elasticity(checker, tmp_path):
@@ -104,7 +107,7 @@ def test_small_supernode_limits(checker, tmp_path, k, r, small):
     rng = np.random.default_rng(1000 * k + r)
     n, cp, ri, _ = gen.leaf_pair_spd(k, r, rng)
     out = _run(checker, tmp_path, n, cp, ri, None, 0, 0, 64)
-    nsmall = int(out.split("small=")[1])
+    nsmall = int(out.split("small=")[1].split()[0])
     # the two leaves, and the parent block too when it fits
     parent = r > 0 and r <= 16 and (4 if r <= 4 else 16) + r <= 64
     assert nsmall == (2 if small else 0) + (1 if parent else 0), out
