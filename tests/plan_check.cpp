@@ -199,6 +199,7 @@ int main(int argc, char** argv) {
         const bool ext = kind == K_UPD_EXT;
         const int64_t kb = ext ? 0 : int64_t(t.c) * nb, ke = ext ? k : std::min<int64_t>(k, kb + nb);
         const int64_t colEnd = ext ? m : k;
+        if (ext && t.b < k) ok = fail("external tile that starts inside the supernode's columns");
         const int64_t r1 = std::min<int64_t>(int64_t(t.a) + kTile, m), c1 = std::min<int64_t>(int64_t(t.b) + kTile, colEnd);
         for (int64_t c = t.b; c < c1 && ok; ++c)
           for (int64_t r = std::max<int64_t>(t.a, c); r < r1 && ok; ++r) {
@@ -377,7 +378,8 @@ int main(int argc, char** argv) {
   }
   int64_t bsplit = 0;
   for (const Launch& L : S.bwd_plan)
-    for (int32_t q = 0; q < L.ntasks; ++q) bsplit += S.tasks[L.off + q].c > 0;
+    if (L.kind == K_BWD)
+      for (int32_t q = 0; q < L.ntasks; ++q) bsplit += S.tasks[L.off + q].c > 0;
   int64_t nsmall = 0, nfwd2 = 0, nssolve = 0;
   for (const Launch& L : S.factor_plan)
     if (L.kind == K_SMALL) nsmall += L.ntasks;

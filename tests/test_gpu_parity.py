@@ -191,3 +191,21 @@ def test_small_supernode_limits(k, r):
     n, cp, ri, vv = gen.leaf_pair_spd(k, r, rng)
     B = rng.standard_normal((n, 3))
     run_case(n, cp, ri, vv, None, B, 0, 0, 64)
+
+
+@pytest.mark.parametrize("cfg,side,z,nrhs", [(4, 16, 8, 1), (4, 16, 8, 3), (4, 16, 8, 4), (4, 16, 8, 6),
+                                             (0, None, 0, 5)])
+def test_small_solve_levels(cfg, side, z, nrhs):
+    """Leaf levels with >= 256 supernodes of one small panel (<= 16
+    columns, <= 64 rows below) are solved one wavefront each, for several
+    right-hand-side counts, beside levels just under the threshold that
+    keep the ordinary rounds."""
+    p = gen.make_config(cfg, side=side) if side else gen.make_config(cfg)
+    S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, 0, z)
+    e = S.export()
+    k = np.diff(e["super_ptr"]); m = np.diff(e["row_ptr"]); lev = e["level"]
+    q = (k <= 16) & (m - k <= 64)
+    per_level = [int((q & (lev == l)).sum()) for l in range(int(lev.max()) + 1)]
+    assert max(per_level) >= 256 and any(0 < c < 256 for c in per_level), per_level
+    B = np.random.default_rng(77 + nrhs).standard_normal((p.n, nrhs))
+    run_case(p.n, p.colptr, p.rowind, p.vals, p.perm, B, 0, z, 64)
