@@ -321,7 +321,7 @@ def _mixed_ir_body(args, p, S, info, vals, Bt, Xt, stream, steps):
         ok = bool(max(it_box["berr"]) <= 1e-12)
         out[prec + "_ir"] = dict(factor_ms=tm["factor"], solve_ir_ms=tm["solve_ir"], total_ms=total,
                                  gflops=info["flops_alg"] / tm["factor"] * 1e-6, iterations=it_box["it"],
-                                 converged=ok, berr=it_box["berr"],
+                                 path="pcg" if Fm.last_refine_path else "ir", converged=ok, berr=it_box["berr"],
                                  speedup_vs_fp64=out["fp64"]["factor_solve_ms"] / total if ok else None)
         del Fm
     return out

@@ -187,17 +187,26 @@ spchol_status spchol_refactor_prec(spchol_num num, const double *vals_dev, int32
  * (possibly mixed-precision) factor, then repeatedly R = B - A X (fp64,
  * original ordering), X += A~^{-1} R, until the normwise backward error
  * eta = ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf) of every column is
- * <= tol or max_iter corrections were applied.
+ * <= tol or max_iter corrections were applied.  When a correction fails to
+ * halve eta of a column still above tol (refinement stalls: the reduced-
+ * precision factor is too far from A for the plain iteration to contract),
+ * the remaining corrections are conjugate-gradient steps on A preconditioned
+ * by the factor (M = A~, symmetric positive definite), each with one solve,
+ * one product with A and the same eta test.
  *   vals_dev: device, the fp64 values of A (same order as the pattern);
  *   B_dev: device, n x nrhs, leading dimension ldb (read only);
  *   X_dev: device, n x nrhs, leading dimension ldx (output);
  *   berr_out: host, nrhs entries (eta of the returned X), may be NULL;
- *   iters_out: host, corrections applied, may be NULL.
+ *   iters_out: host, corrections applied (both kinds), may be NULL;
+ *   path_out: host, 0 = refinement alone, 1 = switched to preconditioned
+ *             conjugate gradients, may be NULL.
  * Returns SPCHOL_ERR_NOCONV (X holds the last iterate) when the tolerance
- * is not reached.  Synchronizes `stream` once per iteration. */
+ * is not reached.  Synchronizes `stream` once per iteration (a few times
+ * per conjugate-gradient step). */
 spchol_status spchol_refine(spchol_num num, const double *vals_dev, const double *B_dev,
                             double *X_dev, int64_t nrhs, int64_t ldb, int64_t ldx, double tol,
-                            int32_t max_iter, void *stream, double *berr_out, int32_t *iters_out);
+                            int32_t max_iter, void *stream, double *berr_out, int32_t *iters_out,
+                            int32_t *path_out);
 
 /* Solve A X = B in place.  B_dev: device, n x nrhs column-major, leading
  * dimension ldb >= n, original (unpermuted) ordering.  Forward solve with L

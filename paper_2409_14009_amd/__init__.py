@@ -225,6 +225,7 @@ class Factor:
         self.sym = sym
         self._h = h
         self.info = 0
+        self.last_refine_path = 0
 
     def close(self):
         if getattr(self, "_h", None):
@@ -270,15 +271,19 @@ class Factor:
 
     def refine_(self, vals, Bt, Xt, tol=1e-12, max_iter=10, stream=None, check=True):
         """Iterative refinement on (nrhs, n) contiguous tensors (column-major
-        n x nrhs blocks): Xt <- A^{-1} Bt.  Returns (berr per RHS, iterations).
-        Raises SpcholError(SPCHOL_ERR_NOCONV) when check is set and the
-        tolerance is not reached."""
+        n x nrhs blocks): Xt <- A^{-1} Bt.  Returns (berr per RHS, iterations);
+        `last_refine_path` is then 0 (refinement alone) or 1 (it stalled and
+        the remaining corrections were preconditioned conjugate-gradient
+        steps).  Raises SpcholError(SPCHOL_ERR_NOCONV) when check is set and
+        the tolerance is not reached."""
         nrhs = Bt.shape[0] if Bt.dim() == 2 else 1
         berr = (C.c_double * max(nrhs, 1))()
         iters = C.c_int32(0)
+        path = C.c_int32(0)
         rc = capi.lib().spchol_refine(self._h, _dev_f64(vals, "vals"), _dev_f64(Bt, "B"), _dev_f64(Xt, "X"),
                                       nrhs, self.sym.n, self.sym.n, float(tol), int(max_iter), _stream_ptr(stream),
-                                      berr, C.byref(iters))
+                                      berr, C.byref(iters), C.byref(path))
+        self.last_refine_path = int(path.value)
         out = ([berr[c] for c in range(nrhs)], int(iters.value))
         if rc == -6 and not check:
             return out

@@ -56,6 +56,14 @@ hipError_t launch_anorm(const DevSym& S, const double* vals, unsigned long long*
 hipError_t launch_residual(const DevSym& S, const double* vals, const double* B, int64_t ldb, const double* X,
                            int64_t ldx, int64_t nrhs, double* R, unsigned long long* stats, hipStream_t st);
 hipError_t launch_axpy(double* X, int64_t ldx, const double* D, int64_t n, int64_t nrhs, hipStream_t st);
+// preconditioned conjugate gradients: out[c] = a[:, c] . b[:, c];
+// Y[:, c] += alpha[c] D[:, c]; P[:, c] = Z[:, c] + beta[c] P[:, c]
+// (blocks n x nrhs with leading dimension n, except Y: ldy; scalars on the
+// device).  launch_residual with B == NULL gives R = -A X.
+hipError_t launch_dot_cols(const double* a, const double* b, int64_t n, int64_t nrhs, double* out, hipStream_t st);
+hipError_t launch_axpy_cols(double* Y, int64_t ldy, const double* D, int64_t n, int64_t nrhs, const double* alpha,
+                            hipStream_t st);
+hipError_t launch_xpby_cols(double* P, const double* Z, int64_t n, int64_t nrhs, const double* beta, hipStream_t st);
 hipError_t launch_copy_cols(double* Y, int64_t ldy, const double* B, int64_t ldb, int64_t n, int64_t nrhs,
                             hipStream_t st);
 // one wavefront per supernode of a K_SMALL launch (four per workgroup);

@@ -6,6 +6,7 @@
 // elimination tree (Fig. 1), split into panels of at most 64 columns and
 // 64-row tiles.  Storage: supernode J is a dense column-major m_J x k_J
 // array (Sec. II-A), leading dimension m_J.
+#include <algorithm>
 #include <climits>
 
 #include "consts.hpp"
@@ -1873,7 +1874,7 @@ __global__ __launch_bounds__(256) void k_residual(const int64_t* __restrict__ rp
       for (int o = kRowLanes / 2; o > 0; o >>= 1) s[u] += __shfl_xor(s[u], o, kRowLanes);
       const int64_t c = cb + u;
       const bool ok = row && c < nrhs;
-      const double b = ok ? B[i + c * ldb] : 0.0;
+      const double b = (ok && B) ? B[i + c * ldb] : 0.0;
       const double r = b + s[u];
       if (ok && g == 0) R[i + c * n] = r;
       const double mr = block_max_256(ok ? fabs(r) : 0.0, sh);
@@ -1886,6 +1887,44 @@ __global__ __launch_bounds__(256) void k_residual(const int64_t* __restrict__ rp
       }
     }
   }
+}
+
+// Column dot products of two n x nrhs blocks (leading dimension n):
+// out[c] += sum_i a[i, c] b[i, c] (out zeroed beforehand); blockIdx.y is the
+// column, each workgroup one strided share of it.
+__global__ __launch_bounds__(256) void k_dot_cols(const double* __restrict__ a, const double* __restrict__ b,
+                                                  int64_t n, double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int64_t c = blockIdx.y;
+  double v = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    v = fma(a[i + c * n], b[i + c * n], v);
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out + c, sh[0]);
+}
+
+// Y[:, c] += alpha[c] D[:, c] (Y with leading dimension ldy, D with n)
+__global__ void k_axpy_cols(double* __restrict__ Y, int64_t ldy, const double* __restrict__ D, int64_t n,
+                            int64_t nrhs, const double* __restrict__ alpha) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n * nrhs; i += stride) {
+    const int64_t c = i / n, r = i % n;
+    Y[c * ldy + r] = fma(alpha[c], D[i], Y[c * ldy + r]);
+  }
+}
+
+// P[:, c] = Z[:, c] + beta[c] P[:, c] (leading dimension n)
+__global__ void k_xpby_cols(double* __restrict__ P, const double* __restrict__ Z, int64_t n, int64_t nrhs,
+                            const double* __restrict__ beta) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n * nrhs; i += stride) P[i] = fma(beta[i / n], P[i], Z[i]);
 }
 
 // X += D (n x nrhs, D with leading dimension n)
@@ -2037,6 +2076,28 @@ hipError_t launch_residual(const DevSym& S, const double* vals, const double* B,
 hipError_t launch_axpy(double* X, int64_t ldx, const double* D, int64_t n, int64_t nrhs, hipStream_t st) {
   if (n * nrhs <= 0) return hipSuccess;
   k_axpy<<<grid_for(n * nrhs), 256, 0, st>>>(X, ldx, D, n, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot_cols(const double* a, const double* b, int64_t n, int64_t nrhs, double* out,
+                           hipStream_t st) {
+  k_zero_u64<<<(unsigned)((nrhs + 63) / 64), 64, 0, st>>>(reinterpret_cast<unsigned long long*>(out), nrhs);
+  if (n <= 0 || nrhs <= 0) return hipGetLastError();
+  const int64_t per = std::min<int64_t>((n + 255) / 256, 512);
+  k_dot_cols<<<dim3((unsigned)per, (unsigned)nrhs), 256, 0, st>>>(a, b, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_cols(double* Y, int64_t ldy, const double* D, int64_t n, int64_t nrhs, const double* alpha,
+                            hipStream_t st) {
+  if (n * nrhs <= 0) return hipSuccess;
+  k_axpy_cols<<<grid_for(n * nrhs), 256, 0, st>>>(Y, ldy, D, n, nrhs, alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_xpby_cols(double* P, const double* Z, int64_t n, int64_t nrhs, const double* beta, hipStream_t st) {
+  if (n * nrhs <= 0) return hipSuccess;
+  k_xpby_cols<<<grid_for(n * nrhs), 256, 0, st>>>(P, Z, n, nrhs, beta);
   return hipGetLastError();
 }
 

@@ -224,6 +224,8 @@ struct spchol_num_s {
   int32_t prec = 0;           // update precision of the last factorization
   double* rwork = nullptr;    // refinement residual / correction, n x nrhs
   int64_t rcap = 0;
+  double* pwork = nullptr;    // conjugate gradients: z, p, q (n x nrhs each), then 3 nrhs scalars
+  int64_t pcap = 0;
   unsigned long long* stats = nullptr;  // refinement norms (3 per RHS + 1)
   int64_t scap = 0;
   double* Z = nullptr;     // selected inverse, layout of L
@@ -249,6 +251,7 @@ struct spchol_num_s {
     if (sibuf) (void)hipFree(sibuf);
     if (lam) (void)hipFree(lam);
     if (rwork) (void)hipFree(rwork);
+    if (pwork) (void)hipFree(pwork);
     if (stats) (void)hipFree(stats);
     if (L) (void)hipFree(L);
     if (winv) (void)hipFree(winv);
@@ -693,14 +696,82 @@ spchol_status spchol_solve(spchol_num num, double* B_dev, int64_t nrhs, int64_t 
   return cached_run(num, 1, B_dev, nrhs, ldb, st, [&] { return enqueue_solve(num, num->sw, B_dev, nrhs, ldb, st); });
 }
 
+// Preconditioned conjugate gradients on A (fp64, original ordering) with
+// M = L~ L~^T, the stored factor (symmetric positive definite whatever the
+// update precision, once the factorization succeeded), from the current X,
+// whose residual rwork holds; the path iterative refinement switches to when
+// it stalls.  Per column: z = M^{-1} r, p = z, then alpha = r.z / p.Ap,
+// x += alpha p, r = b - A x (recomputed, with eta), z = M^{-1} r,
+// beta = r.z (new) / r.z (old), p = z + beta p.  A column whose r.z or p.Ap
+// is zero or not finite keeps its iterate (its scalars are zero).  Runs
+// until every eta <= tol or `budget` iterations; adds them to *it.
+static spchol_status pcg(spchol_num_s* num, const double* vals, const double* B, int64_t ldb, double* X, int64_t ldx,
+                         int64_t nrhs, double tol, int32_t budget, hipStream_t st, std::vector<double>& eta,
+                         int32_t* it, bool* ok) {
+  const int64_t n = num->sym->S.n, blk = n * nrhs;
+  if (num->pcap < 3 * blk + 3 * nrhs) {
+    if (num->pwork) HIP_TRY(hipFree(num->pwork));
+    num->pwork = nullptr;
+    num->pcap = 0;
+    HIP_TRY(hipMalloc((void**)&num->pwork, (size_t)(3 * blk + 3 * nrhs) * sizeof(double)));
+    num->pcap = 3 * blk + 3 * nrhs;
+  }
+  double *z = num->pwork, *pv = z + blk, *q = pv + blk, *dots = q + blk, *scal = dots + nrhs;
+  std::vector<double> rz(nrhs), h(nrhs), a(nrhs);
+  auto precond = [&]() -> spchol_status {  // z = M^{-1} r, h = r.z
+    HIP_TRY(launch_copy_cols(z, n, num->rwork, n, n, nrhs, st));
+    spchol_status s = spchol_solve(num, z, nrhs, n, st);
+    if (s) return s;
+    HIP_TRY(launch_dot_cols(num->rwork, z, n, nrhs, dots, st));
+    HIP_TRY(hipMemcpyAsync(h.data(), dots, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return SPCHOL_OK;
+  };
+  auto upload = [&](const std::vector<double>& v) -> spchol_status {
+    HIP_TRY(hipMemcpyAsync(scal, v.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));  // v is pageable host memory
+    return SPCHOL_OK;
+  };
+  auto usable = [](double v) { return std::isfinite(v) && v != 0.0; };
+  spchol_status s = precond();
+  if (s) return s;
+  rz = h;
+  HIP_TRY(launch_copy_cols(pv, n, z, n, n, nrhs, st));
+  for (int32_t k = 0; k < budget; ++k) {
+    // q = -A p, h = p.q = -p.Ap
+    HIP_TRY(launch_residual(num->sym->dev, vals, nullptr, n, pv, n, nrhs, q, num->stats, st));
+    HIP_TRY(launch_dot_cols(pv, q, n, nrhs, dots, st));
+    HIP_TRY(hipMemcpyAsync(h.data(), dots, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t c = 0; c < nrhs; ++c) a[c] = (usable(rz[c]) && usable(h[c])) ? -rz[c] / h[c] : 0.0;
+    if ((s = upload(a))) return s;
+    HIP_TRY(launch_axpy_cols(X, ldx, pv, n, nrhs, scal, st));
+    ++*it;
+    if ((s = residual_eta(num, vals, B, ldb, X, ldx, nrhs, st, eta.data()))) return s;
+    *ok = true;
+    for (int64_t c = 0; c < nrhs; ++c)
+      if (!(eta[c] <= tol)) *ok = false;
+    if (*ok || k + 1 == budget) break;
+    if ((s = precond())) return s;
+    for (int64_t c = 0; c < nrhs; ++c) {
+      a[c] = (usable(rz[c]) && std::isfinite(h[c])) ? h[c] / rz[c] : 0.0;
+      rz[c] = h[c];
+    }
+    if ((s = upload(a))) return s;
+    HIP_TRY(launch_xpby_cols(pv, z, n, nrhs, scal, st));
+  }
+  return SPCHOL_OK;
+}
+
 spchol_status spchol_refine(spchol_num num, const double* vals_dev, const double* B_dev, double* X_dev,
                             int64_t nrhs, int64_t ldb, int64_t ldx, double tol, int32_t max_iter, void* stream,
-                            double* berr_out, int32_t* iters_out) {
+                            double* berr_out, int32_t* iters_out, int32_t* path_out) {
   if (!num) return fail(SPCHOL_ERR_ARG, "null handle");
   const Symbolic& S = num->sym->S;
   if (nrhs < 0 || ldb < S.n || ldx < S.n || ldb < 1 || ldx < 1 || max_iter < 0)
     return fail(SPCHOL_ERR_ARG, "bad nrhs, leading dimension or max_iter");
   if (iters_out) *iters_out = 0;
+  if (path_out) *path_out = 0;
   if (nrhs == 0 || S.n == 0) {
     for (int64_t c = 0; c < nrhs; ++c)
       if (berr_out) berr_out[c] = 0.0;
@@ -726,8 +797,8 @@ spchol_status spchol_refine(spchol_num num, const double* vals_dev, const double
     HIP_TRY(launch_copy_cols(X_dev, ldx, num->rwork, S.n, S.n, nrhs, st));
   }
   HIP_TRY(launch_anorm(D, vals_dev, anorm, st));
-  std::vector<double> eta(nrhs, 0.0);
-  int32_t it = 0;
+  std::vector<double> eta(nrhs, 0.0), prev(nrhs, INFINITY);
+  int32_t it = 0, path = 0;
   bool ok = false;
   for (;; ++it) {
     {
@@ -735,9 +806,22 @@ spchol_status spchol_refine(spchol_num num, const double* vals_dev, const double
       if (s) return s;
     }
     ok = true;
-    for (int64_t c = 0; c < nrhs; ++c)
+    bool stall = false;
+    for (int64_t c = 0; c < nrhs; ++c) {
       if (!(eta[c] <= tol)) ok = false;
+      // a correction that did not halve the backward error of a column
+      // still above the tolerance (or made it worse, or not finite)
+      if (it > 0 && !(eta[c] <= tol) && !(eta[c] <= 0.5 * prev[c])) stall = true;
+    }
     if (ok || it >= max_iter) break;
+    if (stall) {
+      // the remaining corrections as preconditioned conjugate gradients
+      path = 1;
+      spchol_status s = pcg(num, vals_dev, B_dev, ldb, X_dev, ldx, nrhs, tol, max_iter - it, st, eta, &it, &ok);
+      if (s) return s;
+      break;
+    }
+    prev = eta;
     spchol_status s = spchol_solve(num, num->rwork, nrhs, S.n, stream);
     if (s) return s;
     HIP_TRY(launch_axpy(X_dev, ldx, num->rwork, S.n, nrhs, st));
@@ -745,6 +829,7 @@ spchol_status spchol_refine(spchol_num num, const double* vals_dev, const double
   if (berr_out)
     for (int64_t c = 0; c < nrhs; ++c) berr_out[c] = eta[c];
   if (iters_out) *iters_out = it;
+  if (path_out) *path_out = path;
   if (!ok) return fail(SPCHOL_ERR_NOCONV, "iterative refinement did not reach the tolerance");
   return SPCHOL_OK;
 }

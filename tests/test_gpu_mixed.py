@@ -51,6 +51,7 @@ def test_fp64_factor_refine_converges_immediately():
     p = gen.make_config(2, side=7)
     S, F, it = _case(p, 8, "f64")
     assert it <= 1
+    assert F.last_refine_path == 0
 
 
 def test_refine_noconv_reported():
@@ -128,3 +129,41 @@ def test_mixed_with_wide_supernodes(prec):
     p = gen.make_config(4, side=18)
     S, F, it = _case(p, 8, prec)
     assert it >= 1
+
+
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_stalled_refinement_switches_to_pcg(nrhs):
+    """Refinement with the factor of M = A + delta I against A.  With delta
+    = 3 lambda_min(A) a plain correction shrinks the error along A's lowest
+    eigenvector only by delta / (lambda_min + delta) = 0.75, so refinement
+    stalls (eta not halved) and the remaining corrections are conjugate
+    gradients on A preconditioned by M: the spectrum of M^{-1} A,
+    lambda / (lambda + delta), lies in [0.25, 1) and clusters at 1, so they
+    converge in far fewer steps than the ~100 that 0.75 a step would take."""
+    p = gen.make_config(0)  # 32 x 32 grid Laplacian, n = 1024
+    A = oracle.full_matrix(p.n, p.colptr, p.rowind, p.vals)
+    lmin = float(np.linalg.eigvalsh(A.toarray())[0])
+    rows, cols = oracle.entry_coords(p.colptr, p.rowind)
+    vm = p.vals.copy()
+    vm[rows == cols] += 3.0 * lmin
+    print(f"case stalled refinement n={p.n} nrhs={nrhs} lambda_min={lmin:.3e}", flush=True)
+    S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, 0, 0)
+    F = S.factor(torch.tensor(vm, device="cuda"))
+    vals = torch.tensor(p.vals, device="cuda")
+    B = np.random.default_rng(31 + nrhs).standard_normal((p.n, nrhs))
+    X, berr, it = F.refine(vals, torch.tensor(B, device="cuda"), tol=1e-12, max_iter=40)
+    X = X.cpu().numpy().reshape(p.n, nrhs)
+    eta, _ = oracle.backward_error(A, X, B)
+    print(f"  path {F.last_refine_path} iterations {it} device eta {max(berr):.2e} host eta {eta.max():.2e}",
+          flush=True)
+    assert F.last_refine_path == 1
+    assert it <= 30
+    assert max(berr) <= 1e-12 and eta.max() <= 1e-12
+    Xo = oracle.Symbolic(p.n, p.colptr, p.rowind, p.perm, 0, 0).factor(p.vals).solve(B).reshape(p.n, nrhs)
+    assert np.abs(X - Xo).max() <= 1e-9 * np.abs(Xo).max()
+    # the same factor with five corrections allowed: the switch is taken
+    # (refinement contracts by about 0.3, 0.5, 0.55 in its first steps) but
+    # the tolerance is not reached, which is reported
+    with pytest.raises(sc.SpcholError):
+        F.refine(vals, torch.tensor(B, device="cuda"), tol=1e-12, max_iter=5)
+    assert F.last_refine_path == 1
