@@ -213,6 +213,7 @@ struct spchol_num_s {
   // beside the next level's panel chain, and the events that fork and join it
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev = nullptr;  // solves: the second stream's groups joined back
   std::vector<hipEvent_t> side_ev;  // per level
   std::vector<CachedGraph> gcache;  // most recent last
   bool gcache_on = true;
@@ -246,6 +247,7 @@ struct spchol_num_s {
     for (hipEvent_t e : side_ev)
       if (e) (void)hipEventDestroy(e);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (join_ev) (void)hipEventDestroy(join_ev);
     if (side) (void)hipStreamDestroy(side);
     if (Z) (void)hipFree(Z);
     if (sibuf) (void)hipFree(sibuf);
@@ -299,6 +301,7 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
     // created before any capture (stream and event creation is not captured)
     HIP_TRY(hipStreamCreateWithFlags(&N->side, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&N->fork_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&N->join_ev, hipEventDisableTiming));
     N->side_ev.assign(S.nlevels + 1, nullptr);
     for (hipEvent_t& e : N->side_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
@@ -362,17 +365,43 @@ static spchol_status enqueue_solve(spchol_num_s* num, SolveWork& w, double* B_de
   const double pbytes = 24.0 * double(S.n) * double(nrhs);
   HIP_TRY(timed(num, SPCHOL_KERNEL_PERM, 0.0, pbytes, st,
                 [&] { return launch_perm_gather(D, B_dev, ldb, nrhs, w.y, st); }));
-  auto step = [&](const Launch& l) {
-    // solve flops/bytes were counted for one right-hand side; L is read once
-    const double fl = l.flops * double(nrhs);
-    const double by = l.bytes;
-    const bool fwd = l.kind == K_FWD || l.kind == K_FWD2 || l.kind == K_FWD_SMALL;
-    return timed_at(num, fwd ? SPCHOL_KERNEL_FWD : SPCHOL_KERNEL_BWD, l.level, 0, fl, by, st, [&] {
-      return launch_solve_step(D, num->L, num->winv, l.kind, l.off, l.ntasks, w.y, w.x, w.acc, nrhs, st);
-    });
+  // The solve of columns [c0, c0 + nr) of the block on stream s: the
+  // forward and backward rounds, right-hand sides four at a time.
+  auto chain = [&](int64_t c0, int64_t nr, hipStream_t s) -> hipError_t {
+    double *y = w.y + c0 * S.n, *x = w.x + c0 * S.n, *acc = w.acc + c0 * S.n;
+    auto step = [&](const Launch& l) {
+      // solve flops/bytes were counted for one right-hand side; L is read once
+      const double fl = l.flops * double(nr);
+      const double by = l.bytes;
+      const bool fwd = l.kind == K_FWD || l.kind == K_FWD2 || l.kind == K_FWD_SMALL;
+      return timed_at(num, fwd ? SPCHOL_KERNEL_FWD : SPCHOL_KERNEL_BWD, l.level, s == st ? 0 : 1, fl, by, s, [&] {
+        return launch_solve_step(D, num->L, num->winv, l.kind, l.off, l.ntasks, y, x, acc, nr, s);
+      });
+    };
+    for (const Launch& l : S.fwd_plan) {
+      hipError_t e = step(l);
+      if (e != hipSuccess) return e;
+    }
+    for (const Launch& l : S.bwd_plan) {
+      hipError_t e = step(l);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   };
-  for (const Launch& l : S.fwd_plan) HIP_TRY(step(l));
-  for (const Launch& l : S.bwd_plan) HIP_TRY(step(l));
+  // The rounds are latency-bound chains: more than four right-hand sides
+  // go as groups of four, alternately on this stream and on the second one
+  // (idle once the factorization is done), so that two chains run at once.
+  const int64_t groups = (nrhs + 3) / 4;
+  if (groups <= 1) {
+    HIP_TRY(chain(0, nrhs, st));
+  } else {
+    HIP_TRY(hipEventRecord(num->fork_ev, st));
+    HIP_TRY(hipStreamWaitEvent(num->side, num->fork_ev, 0));
+    for (int64_t g = 0; g < groups; ++g)
+      HIP_TRY(chain(4 * g, std::min<int64_t>(4, nrhs - 4 * g), (g & 1) ? num->side : st));
+    HIP_TRY(hipEventRecord(num->join_ev, num->side));
+    HIP_TRY(hipStreamWaitEvent(st, num->join_ev, 0));
+  }
   HIP_TRY(timed(num, SPCHOL_KERNEL_PERM, 0.0, pbytes, st,
                 [&] { return launch_perm_scatter(D, w.x, nrhs, B_dev, ldb, st); }));
   return SPCHOL_OK;
@@ -650,6 +679,7 @@ spchol_status spchol_factor_prec(spchol_sym sym, const double* vals_dev, int32_t
     e = hipMalloc((void**)&N->winv, (size_t)(sym->S.wbase[sym->S.ns] > 0 ? sym->S.wbase[sym->S.ns] : 1) * sizeof(double));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&N->side, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&N->fork_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&N->join_ev, hipEventDisableTiming);
   if (e == hipSuccess) {
     N->side_ev.assign(sym->S.nlevels + 1, nullptr);
     for (hipEvent_t& ev : N->side_ev)

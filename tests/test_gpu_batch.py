@@ -260,3 +260,40 @@ def test_graph_replay_fp32_updates():
     print(f"  worst unrefined eta {worst:.2e}", flush=True)
     assert 1e-14 <= worst <= 1e-5
     G.close()
+
+
+@pytest.mark.parametrize("nrhs", [6, 10])
+def test_graph_replay_many_rhs(nrhs):
+    """More than four right-hand sides: groups of four solved alternately on
+    the caller's stream and the second stream (fork and join inside the
+    captured graph).  Every replay, with eager work and a change of values
+    in between, matches the eager solve and the oracle's backward-error bar."""
+    print(f"case graph replay nrhs={nrhs}", flush=True)
+    p = gen.make_config(4, side=14)
+    S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, 0, 8)
+    v = torch.tensor(p.vals, device="cuda")
+    F = S.factor(v)
+    B = np.random.default_rng(90 + nrhs).standard_normal((nrhs, p.n))
+    B0 = torch.tensor(B, device="cuda")
+    Xe = B0.clone()
+    F.solve_(Xe)
+    Xe = Xe.cpu().numpy()
+    A = oracle.full_matrix(p.n, p.colptr, p.rowind, p.vals)
+    eta, _ = oracle.backward_error(A, Xe.T, B.T)
+    assert eta.max() <= 1e-12, eta
+    stream = torch.cuda.Stream()
+    Xg = torch.empty_like(B0)
+    with torch.cuda.stream(stream):
+        G = F.capture(v, Xg, stream=stream)
+    for r, s in enumerate([1.0, 2.0, 1.0]):
+        with torch.cuda.stream(stream):
+            v.copy_(torch.tensor(p.vals * s, device="cuda"))
+            Xg.copy_(B0)
+            junk = torch.randn(1 << 18, device="cuda", dtype=torch.float64).sum()
+            G.replay(stream)
+            assert F.status(stream) == 0
+        stream.synchronize()
+        ex = np.abs(Xg.cpu().numpy() * s - Xe).max() / np.abs(Xe).max()
+        assert ex <= 1e-12, (r, ex)
+        del junk
+    G.close()
