@@ -1816,76 +1816,100 @@ __global__ void k_zero_u64(unsigned long long* __restrict__ p, int64_t count) {
 }
 
 // Rows of A (full-symmetric CSR) are read by groups of 16 lanes, 16 rows
-// per workgroup (coalesced runs of each row's entries); maxima are reduced
-// in the workgroup and added with one atomic per workgroup and statistic.
+// at a time per workgroup (coalesced runs of each row's entries); maxima are
+// reduced in the workgroup and added with one atomic per workgroup and
+// statistic.
 constexpr int kRowLanes = 16;
 
-// the maximum of v over the workgroup (256 threads); sh holds 4 doubles
-__device__ __forceinline__ double block_max_256(double v, double* sh) {
+// Maxima of NV values over the workgroup (wavefront exchanges, one LDS
+// step); thread t < NV returns the maximum of value t, the others 0.
+template <int NV>
+__device__ __forceinline__ double block_max_multi(const double (&v)[NV], double (*sh)[NV]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  for (int j = 0; j < NV; ++j) {
+    double m = v[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0) sh[w][j] = m;
+  }
   __syncthreads();
-  const double m = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  double r = 0.0;
+  if (threadIdx.x < NV) {
+    const int j = threadIdx.x;
+    r = fmax(fmax(sh[0][j], sh[1][j]), fmax(sh[2][j], sh[3][j]));
+  }
   __syncthreads();
-  return m;
+  return r;
 }
 
-// ||A||_inf = max_i sum_j |a_ij|
+// ||A||_inf = max_i sum_j |a_ij|.  Each 16-lane group takes rows
+// blockIdx.x * 16 + group, stepping by the grid: the workgroup's maximum
+// then costs one atomic (a grid of at most kStatBlocks workgroups keeps
+// the atomics on the one word few).
+constexpr int kStatBlocks = 1024;
 __global__ __launch_bounds__(256) void k_anorm(const int64_t* __restrict__ rp, const int64_t* __restrict__ vidx,
                                                const double* __restrict__ vals, int64_t n,
                                                unsigned long long* __restrict__ out) {
-  __shared__ double sh[4];
+  __shared__ double sh[4][1];
   const int g = threadIdx.x % kRowLanes;
-  const int64_t i = blockIdx.x * (int64_t)(256 / kRowLanes) + threadIdx.x / kRowLanes;
-  double s = 0.0;
-  if (i < n)
+  double m[1] = {0.0};
+  for (int64_t i = blockIdx.x * (int64_t)(256 / kRowLanes) + threadIdx.x / kRowLanes; i < n;
+       i += (int64_t)gridDim.x * (256 / kRowLanes)) {
+    double s = 0.0;
     for (int64_t q = rp[i] + g; q < rp[i + 1]; q += kRowLanes) s += fabs(vals[vidx[q]]);
 #pragma unroll
-  for (int o = kRowLanes / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kRowLanes);
-  const double m = block_max_256(s, sh);
-  if (threadIdx.x == 0) atomic_max_nonneg(out, m);
+    for (int o = kRowLanes / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kRowLanes);
+    m[0] = fmax(m[0], s);
+  }
+  const double r = block_max_multi<1>(m, sh);
+  if (threadIdx.x == 0) atomic_max_nonneg(out, r);
 }
 
-// R = B - A X for nrhs columns, with the normwise statistics max|R|, max|X|,
-// max|B| per column; each entry of A is read once per four columns
+// R = B - A X for nrhs columns (B == NULL: R = -A X), with the normwise
+// statistics max|R|, max|X|, max|B| per column; each entry of A is read
+// once per four columns.  Rows by 16-lane groups, stepping by the grid as
+// in k_anorm; per block of four columns the workgroup's twelve maxima go
+// out with one atomic each.
 __global__ __launch_bounds__(256) void k_residual(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                   const int64_t* __restrict__ vidx, const double* __restrict__ vals,
                                                   int64_t n, const double* __restrict__ B, int64_t ldb,
                                                   const double* __restrict__ X, int64_t ldx, int64_t nrhs,
                                                   double* __restrict__ R, unsigned long long* __restrict__ stats) {
-  __shared__ double sh[4];
+  __shared__ double sh[4][12];
   const int g = threadIdx.x % kRowLanes;
-  const int64_t i = blockIdx.x * (int64_t)(256 / kRowLanes) + threadIdx.x / kRowLanes;
-  const bool row = i < n;
-  const int64_t q0 = row ? rp[i] : 0, q1 = row ? rp[i + 1] : 0;
   for (int64_t cb = 0; cb < nrhs; cb += 4) {
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t q = q0 + g; q < q1; q += kRowLanes) {
-      const double a = vals[vidx[q]];
-      const int64_t j = col[q];
+    double mm[12];  // max |r|, |x|, |b| of columns cb + u at 3u, 3u + 1, 3u + 2
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (cb + u < nrhs) s[u] = fma(-a, X[(cb + u) * ldx + j], s[u]);
-    }
+    for (int j = 0; j < 12; ++j) mm[j] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)(256 / kRowLanes) + threadIdx.x / kRowLanes; i < n;
+         i += (int64_t)gridDim.x * (256 / kRowLanes)) {
+      const int64_t q0 = rp[i], q1 = rp[i + 1];
+      double s[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int64_t q = q0 + g; q < q1; q += kRowLanes) {
+        const double a = vals[vidx[q]];
+        const int64_t j = col[q];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 4; ++u)
+          if (cb + u < nrhs) s[u] = fma(-a, X[(cb + u) * ldx + j], s[u]);
+      }
 #pragma unroll
-      for (int o = kRowLanes / 2; o > 0; o >>= 1) s[u] += __shfl_xor(s[u], o, kRowLanes);
-      const int64_t c = cb + u;
-      const bool ok = row && c < nrhs;
-      const double b = (ok && B) ? B[i + c * ldb] : 0.0;
-      const double r = b + s[u];
-      if (ok && g == 0) R[i + c * n] = r;
-      const double mr = block_max_256(ok ? fabs(r) : 0.0, sh);
-      const double mx = block_max_256(ok ? fabs(X[c * ldx + i]) : 0.0, sh);
-      const double mb = block_max_256(ok ? fabs(b) : 0.0, sh);
-      if (threadIdx.x == 0 && c < nrhs) {
-        atomic_max_nonneg(stats + 3 * c + 0, mr);
-        atomic_max_nonneg(stats + 3 * c + 1, mx);
-        atomic_max_nonneg(stats + 3 * c + 2, mb);
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int o = kRowLanes / 2; o > 0; o >>= 1) s[u] += __shfl_xor(s[u], o, kRowLanes);
+        const int64_t c = cb + u;
+        if (c < nrhs) {
+          const double b = B ? B[i + c * ldb] : 0.0;
+          const double r = b + s[u];
+          if (g == 0) R[i + c * n] = r;
+          mm[3 * u] = fmax(mm[3 * u], fabs(r));
+          mm[3 * u + 1] = fmax(mm[3 * u + 1], fabs(X[c * ldx + i]));
+          mm[3 * u + 2] = fmax(mm[3 * u + 2], fabs(b));
+        }
       }
     }
+    const double r = block_max_multi<12>(mm, sh);
+    if (threadIdx.x < 12 && cb + threadIdx.x / 3 < nrhs) atomic_max_nonneg(stats + 3 * cb + threadIdx.x, r);
   }
 }
 
@@ -2060,7 +2084,9 @@ namespace spchol {
 
 hipError_t launch_anorm(const DevSym& S, const double* vals, unsigned long long* out, hipStream_t st) {
   k_zero_u64<<<1, 64, 0, st>>>(out, 1);
-  if (S.n > 0) k_anorm<<<(unsigned)((S.n + 15) / 16), 256, 0, st>>>(S.a_rp, S.a_vidx, vals, S.n, out);
+  if (S.n > 0)
+    k_anorm<<<(unsigned)std::min<int64_t>((S.n + 15) / 16, kStatBlocks), 256, 0, st>>>(S.a_rp, S.a_vidx, vals, S.n,
+                                                                                      out);
   return hipGetLastError();
 }
 
@@ -2068,7 +2094,7 @@ hipError_t launch_residual(const DevSym& S, const double* vals, const double* B,
                            int64_t ldx, int64_t nrhs, double* R, unsigned long long* stats, hipStream_t st) {
   k_zero_u64<<<(unsigned)((3 * nrhs + 63) / 64), 64, 0, st>>>(stats, 3 * nrhs);
   if (S.n > 0)
-    k_residual<<<(unsigned)((S.n + 15) / 16), 256, 0, st>>>(S.a_rp, S.a_col, S.a_vidx, vals, S.n, B, ldb, X, ldx,
+    k_residual<<<(unsigned)std::min<int64_t>((S.n + 15) / 16, kStatBlocks), 256, 0, st>>>(S.a_rp, S.a_col, S.a_vidx, vals, S.n, B, ldb, X, ldx,
                                                             nrhs, R, stats);
   return hipGetLastError();
 }
