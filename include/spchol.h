@@ -210,7 +210,12 @@ spchol_status spchol_refine(spchol_num num, const double *vals_dev, const double
 
 /* Solve A X = B in place.  B_dev: device, n x nrhs column-major, leading
  * dimension ldb >= n, original (unpermuted) ordering.  Forward solve with L
- * leaves to root, backward solve with L^T root to leaves. */
+ * leaves to root, backward solve with L^T root to leaves (Sec. II).  With
+ * more than four right-hand sides, groups of four alternate between
+ * `stream` and the handle's second stream, which waits for `stream` first
+ * and is joined back into it before the call's last launch: the call stays
+ * ordered on `stream` and can be captured into a graph on it.  Asynchronous
+ * (no host synchronization). */
 spchol_status spchol_solve(spchol_num num, double *B_dev, int64_t nrhs, int64_t ldb,
                            void *stream);
 
