@@ -62,10 +62,10 @@ enum Kind : int32_t {
 inline bool small_supernode(int64_t k, int64_t m) { return k <= 16 && (k <= 4 ? 4 : 16) + m <= 64; }
 
 // Supernodes solved by one wavefront (K_FWD_SMALL, K_BWD_SMALL): one panel
-// of at most 16 columns and at most 64 rows below it.  A level gets such a
-// launch when it holds at least kSmallSolveMin of them (else they stay in
-// the level's ordinary rounds: one launch fewer).
-inline bool small_solve_supernode(int64_t k, int64_t m, int64_t nb) { return k <= 16 && k <= nb && m - k <= 64; }
+// of at most 16 columns and at most 128 rows below it (two per lane).  A
+// level gets such a launch when it holds at least kSmallSolveMin of them
+// (else they stay in the level's ordinary rounds: one launch fewer).
+inline bool small_solve_supernode(int64_t k, int64_t m, int64_t nb) { return k <= 16 && k <= nb && m - k <= 128; }
 constexpr int64_t kSmallSolveMin = 256;
 
 struct Launch {

@@ -1070,12 +1070,44 @@ __global__ __launch_bounds__(256) void k_fwd(DevSym S, const double* __restrict_
 }
 
 // Solve rounds of small supernodes: one panel of at most 16 columns with at
-// most 64 rows below it (the leaf levels of a nested-dissection ordering,
+// most 128 rows below it (the leaf levels of a nested-dissection ordering,
 // thousands of supernodes a level).  One wavefront per supernode, four per
 // workgroup, no LDS and no barrier: lane i holds row (forward) or column
-// (backward) i of the inverted diagonal block and row k + i of L, and the
-// solution entries pass from lane to lane by readlane.  Task: J, 0, k_J, 1.
+// (backward) i of the inverted diagonal block and rows k + i and
+// k + 64 + i of L, and the solution entries pass from lane to lane by
+// readlane.  Task: J, 0, k_J, 1.
 constexpr int kSmallSolveCols = 16;
+
+// the lane's rows below the diagonal block, clamped in bounds (row 0 when
+// there is none: then unused), their global rows and entries of L
+struct SmallRows {
+  bool ok0, ok1;
+  int32_t g0, g1;
+  double l0[kSmallSolveCols], l1[kSmallSolveCols];
+};
+
+__device__ __forceinline__ void small_rows(const DevSym& S, const double* __restrict__ Lj, int J, int m, int k,
+                                           int lane, SmallRows& r) {
+  const int nbl = m - k;
+  const int32_t* __restrict__ R = S.rows + S.rptr[J];
+  r.ok0 = lane < nbl;
+  r.ok1 = TILE + lane < nbl;
+  const int rl0 = nbl > 0 ? k + min(lane, nbl - 1) : 0;
+  r.g0 = R[rl0];
+#pragma unroll
+  for (int u = 0; u < kSmallSolveCols; ++u) r.l0[u] = Lj[(int64_t)min(u, k - 1) * m + rl0];
+  // a second chunk of rows only where the supernode has one (a branch
+  // uniform over the wavefront)
+  r.g1 = 0;
+#pragma unroll
+  for (int u = 0; u < kSmallSolveCols; ++u) r.l1[u] = 0.0;
+  if (nbl > TILE) {
+    const int rl1 = k + TILE + min(lane, nbl - TILE - 1);
+    r.g1 = R[rl1];
+#pragma unroll
+    for (int u = 0; u < kSmallSolveCols; ++u) r.l1[u] = Lj[(int64_t)min(u, k - 1) * m + rl1];
+  }
+}
 
 // Forward: z = W y_J, stored into x; y_R -= L_RJ z with atomics (the rows
 // below are ancestors', shared with other supernodes of the level).
@@ -1086,22 +1118,17 @@ __global__ __launch_bounds__(256) void k_fwd_small(DevSym S, const double* __res
   const int ti = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (ti >= ntasks) return;
   const int J = S.tasks[off + ti].J;
-  const int m = S.sm[J], k = S.sk[J], nbl = m - k;
+  const int m = S.sm[J], k = S.sk[J];
   const double* __restrict__ Lj = L + S.loff[J];
   const double* __restrict__ W = winv + S.wbase[J];
   const int64_t fcol = S.sfirst[J];
-  const bool own = lane < k, below = lane < nbl;
-  // clamped in-bounds rows: the lane's row of W and its row below the
-  // diagonal block (row 0 when there is none; then unused)
-  const int il = min(lane, k - 1), rl = nbl > 0 ? k + min(lane, nbl - 1) : 0;
-  const int32_t grow = S.rows[S.rptr[J] + rl];
-  double wr[kSmallSolveCols], lr[kSmallSolveCols];
+  const bool own = lane < k;
+  const int il = min(lane, k - 1);  // the lane's row of W (clamped)
+  double wr[kSmallSolveCols];
 #pragma unroll
-  for (int u = 0; u < kSmallSolveCols; ++u) {
-    const int uc = min(u, k - 1);
-    wr[u] = W[uc * k + il];
-    lr[u] = Lj[(int64_t)uc * m + rl];
-  }
+  for (int u = 0; u < kSmallSolveCols; ++u) wr[u] = W[min(u, k - 1) * k + il];
+  SmallRows rw;
+  small_rows(S, Lj, J, m, k, lane, rw);
   for (int64_t c = 0; c < nrhs; ++c) {
     const double yv = own ? y[fcol + lane + c * S.n] : 0.0;
     double z = 0.0;
@@ -1109,10 +1136,15 @@ __global__ __launch_bounds__(256) void k_fwd_small(DevSym S, const double* __res
     for (int u = 0; u < kSmallSolveCols; ++u) z = fma(u < k ? wr[u] : 0.0, readlane_d(yv, u), z);
     z = own ? z : 0.0;
     if (own) x[fcol + lane + c * S.n] = z;
-    double a = 0.0;
+    double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-    for (int u = 0; u < kSmallSolveCols; ++u) a = fma(u < k ? lr[u] : 0.0, readlane_d(z, u), a);
-    if (below) atomicAdd(y + grow + c * S.n, -a);
+    for (int u = 0; u < kSmallSolveCols; ++u) {
+      const double zu = readlane_d(z, u);
+      a0 = fma(u < k ? rw.l0[u] : 0.0, zu, a0);
+      a1 = fma(u < k ? rw.l1[u] : 0.0, zu, a1);
+    }
+    if (rw.ok0) atomicAdd(y + rw.g0 + c * S.n, -a0);
+    if (rw.ok1) atomicAdd(y + rw.g1 + c * S.n, -a1);
   }
 }
 
@@ -1159,27 +1191,26 @@ __global__ __launch_bounds__(256) void k_bwd_small(DevSym S, const double* __res
   const int ti = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (ti >= ntasks) return;
   const int J = S.tasks[off + ti].J;
-  const int m = S.sm[J], k = S.sk[J], nbl = m - k;
+  const int m = S.sm[J], k = S.sk[J];
   const double* __restrict__ Lj = L + S.loff[J];
   const double* __restrict__ W = winv + S.wbase[J];
   const int64_t fcol = S.sfirst[J];
-  const bool own = lane < k, below = lane < nbl;
-  const int il = min(lane, k - 1), rl = nbl > 0 ? k + min(lane, nbl - 1) : 0;
-  const int32_t grow = S.rows[S.rptr[J] + rl];
-  // wt[u] = W_{u, lane} (column `lane` of W), lr[u] = L_{k + lane, u}
-  double wt[kSmallSolveCols], lr[kSmallSolveCols];
+  const bool own = lane < k;
+  const int il = min(lane, k - 1);
+  // wt[u] = W_{u, lane} (column `lane` of W)
+  double wt[kSmallSolveCols];
 #pragma unroll
-  for (int u = 0; u < kSmallSolveCols; ++u) {
-    const int uc = min(u, k - 1);
-    wt[u] = W[il * k + uc];
-    lr[u] = Lj[(int64_t)uc * m + rl];
-  }
+  for (int u = 0; u < kSmallSolveCols; ++u) wt[u] = W[il * k + min(u, k - 1)];
+  SmallRows rw;
+  small_rows(S, Lj, J, m, k, lane, rw);
   for (int64_t c = 0; c < nrhs; ++c) {
-    const double xr = below ? x[grow + c * S.n] : 0.0;
+    const double xr0 = rw.ok0 ? x[rw.g0 + c * S.n] : 0.0;
+    const double xr1 = rw.ok1 ? x[rw.g1 + c * S.n] : 0.0;
     const double xf = own ? x[fcol + lane + c * S.n] : 0.0;
     double v[kSmallSolveCols];
 #pragma unroll
-    for (int u = 0; u < kSmallSolveCols; ++u) v[u] = (u < k && below) ? lr[u] * xr : 0.0;
+    for (int u = 0; u < kSmallSolveCols; ++u)
+      v[u] = u < k ? fma(rw.ok0 ? rw.l0[u] : 0.0, xr0, (rw.ok1 ? rw.l1[u] : 0.0) * xr1) : 0.0;
     const double s = col_sums16(v, lane);
     double r = 0.0;
 #pragma unroll

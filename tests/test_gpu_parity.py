@@ -194,18 +194,22 @@ def test_small_supernode_limits(k, r):
 
 
 @pytest.mark.parametrize("cfg,side,z,nrhs", [(4, 16, 8, 1), (4, 16, 8, 3), (4, 16, 8, 4), (4, 16, 8, 6),
-                                             (0, None, 0, 5)])
+                                             (0, None, 0, 5), (2, 14, 8, 8)])
 def test_small_solve_levels(cfg, side, z, nrhs):
     """Leaf levels with >= 256 supernodes of one small panel (<= 16
-    columns, <= 64 rows below) are solved one wavefront each, for several
+    columns, <= 128 rows below) are solved one wavefront each, for several
     right-hand-side counts, beside levels just under the threshold that
     keep the ordinary rounds."""
     p = gen.make_config(cfg, side=side) if side else gen.make_config(cfg)
     S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, 0, z)
     e = S.export()
     k = np.diff(e["super_ptr"]); m = np.diff(e["row_ptr"]); lev = e["level"]
-    q = (k <= 16) & (m - k <= 64)
+    q = (k <= 16) & (m - k <= 128)
     per_level = [int((q & (lev == l)).sum()) for l in range(int(lev.max()) + 1)]
     assert max(per_level) >= 256 and any(0 < c < 256 for c in per_level), per_level
+    if cfg == 2:
+        # leaves of 3-dof points: 65..128 rows below (two rows a lane)
+        big = q & (m - k > 64) & (lev == int(np.argmax(per_level)))
+        assert big.sum() > 0
     B = np.random.default_rng(77 + nrhs).standard_normal((p.n, nrhs))
     run_case(p.n, p.colptr, p.rowind, p.vals, p.perm, B, 0, z, 64)
