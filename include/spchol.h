@@ -26,7 +26,12 @@
  *    host value (spchol_factor's info, spchol_logdet) synchronize it.
  *  - Handles are owned by the library and freed with their destroy call.
  *    A spchol_num keeps a reference to its spchol_sym: destroy the num
- *    first.  Handles may be used from one host thread at a time.
+ *    first.  Handles may be used from one host thread at a time.  A
+ *    spchol_num owns a second stream (factorization: external updates
+ *    beside the next level's panels; solves: every other group of four
+ *    right-hand sides) that waits for the caller's stream and is joined
+ *    back into it within each call, and its workspaces: work enqueued with
+ *    one num on two streams at once must be ordered by the caller.
  *  - On error the status is negative, outputs are unspecified, handles stay
  *    valid and spchol_last_error() returns a message (thread-local).
  *  - No C++ exception crosses this boundary.
