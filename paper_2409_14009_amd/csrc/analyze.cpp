@@ -666,15 +666,32 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
         for (int32_t kind : kinds) {
           open(S.si_plan, kind, (int32_t)l, (int32_t)p);
           S.si_plan.back().slot_base = base;
+          // Y: the segment length of the round.  A task's time grows with its
+          // segment (a chain of gathers of Z), so a round of few tasks gets
+          // shorter segments, as long as all its tasks still fit the GPU at
+          // once; a large round keeps long ones (fewer atomic partial sums)
+          int64_t seg = kSiSeg;
+          if (kind == K_SI_Y) {
+            auto ntasks = [&](int64_t sl) {
+              int64_t c = 0;
+              for (int32_t J : js) {
+                const int64_t r = M(J) - (p * nb + kpan(J, p));
+                c += ((r + kTile - 1) / kTile) * ((r + sl - 1) / sl);
+              }
+              return c;
+            };
+            while (seg > kTile && ntasks(seg / 2) <= kSiTasksMax) seg /= 2;
+            S.si_plan.back().seg = (int32_t)seg;
+          }
           for (size_t s = 0; s < js.size(); ++s) {
             const int32_t J = js[s];
             const int64_t rb = p * nb + kpan(J, p);
             if (kind == K_SI_Y) {
-              // split K: segments of kSiSeg rows of B per task (a = panel |
+              // split K: segments of `seg` rows of B per task (a = panel |
               // segment << 16), summed into the Y blocks (zero on entry:
               // their readers leave them cleared)
               for (int64_t a0 = rb; a0 < M(J); a0 += kTile)
-                for (int64_t sg = 0; rb + sg * kSiSeg < M(J); ++sg)
+                for (int64_t sg = 0; rb + sg * seg < M(J); ++sg)
                   S.tasks.push_back({J, (int32_t)(p | (sg << 16)), (int32_t)a0, (int32_t)s});
             } else if (kind == K_SI_ZB) {
               for (int64_t a0 = rb; a0 < M(J); a0 += kTile)

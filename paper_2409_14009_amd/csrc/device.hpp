@@ -49,7 +49,7 @@ hipError_t launch_update(const DevSym& S, double* L, int32_t kind, int64_t off, 
 hipError_t launch_factor_la(const DevSym& S, double* L, int64_t off, int32_t nfirst, int32_t ntasks,
                             unsigned long long* status, double* winv, int32_t prec, hipStream_t st);
 hipError_t launch_si(const DevSym& S, int32_t kind, int64_t off, int32_t ntasks, const double* L, const double* winv,
-                     double* Z, const int64_t* yoff, double* ybuf, double* tbuf, hipStream_t st);
+                     double* Z, const int64_t* yoff, double* ybuf, double* tbuf, int32_t seglen, hipStream_t st);
 hipError_t launch_abar(const DevSym& S, const double* Z, double g, const double* X, const double* lam, int64_t ld,
                        int64_t nrhs, double* Abar, hipStream_t st);
 hipError_t launch_anorm(const DevSym& S, const double* vals, unsigned long long* out, hipStream_t st);

@@ -1552,13 +1552,14 @@ __device__ __forceinline__ int64_t zat(const DevSym& S, ZCol c, int k, int hi) {
 }
 
 // Y[a][t] = sum_{b in B} Z(a, b) L[b][c0 + t] for a in [a0, a0 + 64), each
-// task over one segment of kSiSeg rows b of B (Y zeroed beforehand).  The
+// task over one segment of seglen (<= kSiSeg) rows b of B (Y zeroed
+// beforehand).  The
 // column data of the tile's rows a is fetched once; that of each K chunk's
 // 16 rows b once per chunk into LDS, so an entry of Z costs one relative
 // index load and the entry itself.
 __global__ __launch_bounds__(256) void k_si_y(DevSym S, const double* __restrict__ L, const double* __restrict__ Z,
                                               int64_t off, const int64_t* __restrict__ yoff,
-                                              double* __restrict__ ybuf) {
+                                              double* __restrict__ ybuf, int seglen) {
   __shared__ double As[KC * ALD];
   __shared__ double Bs[KC * ALD];
   const DevTask t = S.tasks[off + blockIdx.x];
@@ -1566,7 +1567,7 @@ __global__ __launch_bounds__(256) void k_si_y(DevSym S, const double* __restrict
   const int m = S.sm[J], k = S.sk[J];
   const int c0 = p * S.nb, kp = min(S.nb, k - c0);
   const int rb = c0 + kp;
-  const int bs = rb + seg * kSiSeg, be = min(m, bs + kSiSeg);  // this task's rows of B
+  const int bs = rb + seg * seglen, be = min(m, bs + seglen);  // this task's rows of B
   const double* __restrict__ Lj = L + S.loff[J];
   const int64_t ob = S.obase[J];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -2170,10 +2171,13 @@ hipError_t launch_copy_cols(double* Y, int64_t ldy, const double* B, int64_t ldb
 namespace spchol {
 
 hipError_t launch_si(const DevSym& S, int32_t kind, int64_t off, int32_t ntasks, const double* L, const double* winv,
-                     double* Z, const int64_t* yoff, double* ybuf, double* tbuf, hipStream_t st) {
+                     double* Z, const int64_t* yoff, double* ybuf, double* tbuf, int32_t seglen, hipStream_t st) {
   if (ntasks <= 0) return hipSuccess;
   switch (kind) {
-    case 9: k_si_y<<<ntasks, 256, 0, st>>>(S, L, Z, off, yoff, ybuf); break;
+    case 9:
+      if (seglen < 1 || seglen > kSiSeg) return hipErrorInvalidValue;
+      k_si_y<<<ntasks, 256, 0, st>>>(S, L, Z, off, yoff, ybuf, seglen);
+      break;
     case 10: k_si_zb<<<ntasks, 256, 0, st>>>(S, L, winv, Z, off, yoff, ybuf, tbuf); break;
     case 11: k_si_zd<<<ntasks, 256, 0, st>>>(S, winv, Z, off, tbuf); break;
     default: return hipErrorInvalidValue;

@@ -903,7 +903,7 @@ static spchol_status run_selinv(spchol_num_s* N, hipStream_t st) {
     for (const Launch& l : S.si_plan) {
       const int64_t* yoff = N->sym->si_yoff + l.slot_base;
       HIP_TRY(timed(N, SPCHOL_KERNEL_SELINV, 0.0, 0.0, st, [&] {
-        return launch_si(D, l.kind, l.off, l.ntasks, N->L, N->winv, N->Z, yoff, ybuf, tbuf, st);
+        return launch_si(D, l.kind, l.off, l.ntasks, N->L, N->winv, N->Z, yoff, ybuf, tbuf, l.seg, st);
       }));
     }
     return SPCHOL_OK;
