@@ -86,7 +86,7 @@ struct Launch {
 constexpr int kTile = 64;      // rows (and cols) of an update tile
 constexpr int kTrsmRows = 256; // rows solved by the diagonal-block workgroup
 constexpr int kInlineMinTasks = 128;  // launches with fewer diagonal tasks solve no rows inline
-constexpr int kBwdRows = 512;  // backward solve: taller panels are split into row tiles
+constexpr int kBwdRows = 256;  // backward solve: taller panels are split into row tiles
 constexpr int kMaxPanel = 64;  // largest panel width
 
 struct Symbolic {
