@@ -401,8 +401,7 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
           by += 8.0 * double(kk) * double((r1 - t.a) + (c1 - t.b)) + 16.0 * double(valid);
           break;
         }
-        case K_FWD2:
-          if (t.c & 2) {
+        case K_FWD2: {  // (two-panel tasks; single-panel ones are costed as K_FWD)
             // z_p, the coupling block (kp1 x kp), z_{p+1}; the tile's rows in
             // both panels' columns
             const int64_t kp = std::min<int64_t>(nb, k - int64_t(t.a) * nb);
@@ -414,7 +413,6 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
                   ((t.c & 1) ? 8.0 * double(kp * (kp + 1) / 2 + kp1 * (kp1 + 1) / 2 + kp1 * kp) : 0.0);
             break;
           }
-          [[fallthrough]];
         case K_FWD_SMALL:
         case K_BWD_SMALL: {
           const int64_t nr = m - k;
@@ -449,7 +447,9 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       L.ntasks = (int32_t)((int64_t)S.tasks.size() - L.off);
       if (L.ntasks == 0) { plan.pop_back(); return; }
       for (int64_t q = L.off; q < L.off + L.ntasks; ++q) {
-        const int32_t kind = L.kind == K_FACTOR_LA ? (q - L.off < L.nfirst ? K_FACTOR : K_UPD_INT) : L.kind;
+        int32_t kind = L.kind == K_FACTOR_LA ? (q - L.off < L.nfirst ? K_FACTOR : K_UPD_INT) : L.kind;
+        // a single-panel task of a two-panel forward round does what a K_FWD task does
+        if (kind == K_FWD2 && !(S.tasks[q].c & 2)) kind = K_FWD;
         cost(kind, S.tasks[q], L.flops, L.bytes);
       }
     };

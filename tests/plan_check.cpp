@@ -388,8 +388,13 @@ int main(int argc, char** argv) {
   for (const Launch& L : S.fwd_plan)
     if (L.kind == K_FWD2)
       for (int32_t q = 0; q < L.ntasks; ++q) nfwd2 += (S.tasks[L.off + q].c & 2) != 0;
-  std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld fwd2=%lld small=%lld small_solve=%lld\n",
+  // algorithmic bytes the plans charge per sweep (one right-hand side)
+  double fwd_bytes = 0, bwd_bytes = 0;
+  for (const Launch& L : S.fwd_plan) fwd_bytes += L.bytes;
+  for (const Launch& L : S.bwd_plan) bwd_bytes += L.bytes;
+  std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld fwd2=%lld small=%lld small_solve=%lld fwd_bytes=%.0f "
+              "bwd_bytes=%.0f storage=%lld\n",
               S.factor_plan.size(), S.fwd_plan.size(), S.bwd_plan.size(), (long long)bsplit, (long long)nfwd2,
-              (long long)nsmall, (long long)nssolve);
+              (long long)nsmall, (long long)nssolve, fwd_bytes, bwd_bytes, (long long)storage);
   return 0;
 }

@@ -53,6 +53,16 @@ def test_grid3d(checker, tmp_path, side, z, nb):
         assert int(out.split("split_bwd=")[1].split()[0]) > 0, out
         # supernodes of several panels: two-panel forward tasks
         assert int(out.split("fwd2=")[1].split()[0]) > 0, out
+    # the algorithmic bytes the solve plans charge: each sweep reads every
+    # stored entry of L below the diagonal blocks once and the lower
+    # triangle of each inverted diagonal block once (plus 16 bytes per row
+    # for the right-hand side), so both sweeps come to about 8 bytes per
+    # stored entry, and to the same amount
+    f = {kv.split("=")[0]: float(kv.split("=")[1]) for kv in out.split()[2:] if "=" in kv}
+    fr, br = f["fwd_bytes"] / (8 * f["storage"]), f["bwd_bytes"] / (8 * f["storage"])
+    assert abs(fr - br) <= 0.05 * br, (fr, br)
+    if z >= 8:  # (without amalgamation the 16 bytes per row weigh more)
+        assert 0.8 <= fr <= 1.2 and 0.8 <= br <= 1.2, (fr, br)
     # the leaves of the dissection are done by one-wavefront tasks, in the
     # solves too once a level holds enough of them
     assert int(out.split("small=")[1].split()[0]) > 0, out
