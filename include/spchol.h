@@ -74,10 +74,29 @@ typedef struct {
                               this many explicit zeros per column; 0 = off      */
   int32_t panel_width;     /* columns per factorization panel (0 = default 64,
                               must be a multiple of 16 and <= 64)              */
-  int32_t reserved;
+  int32_t deterministic;   /* nonzero: bitwise reproducible factorization,
+                              solves and selected inversion.  Concurrent
+                              supernodes add into shared ancestor entries
+                              (Sec. II-A) with fp64 atomics, whose order, and
+                              so the last bits, vary between runs; this mode
+                              splits every such launch into launches whose
+                              adds hit disjoint entries (a colouring of each
+                              level's supernodes by shared rows), run in a
+                              fixed order, never splits a backward-solve
+                              panel, and runs no update beside the next
+                              level.  More launches, same arithmetic.  The
+                              environment variable SPCHOL_DETERMINISTIC=1
+                              forces it at analysis.                         */
+  int64_t workspace_limit; /* bytes of device memory a numeric handle may
+                              hold (factor, inverse blocks, the analysis'
+                              device copy, solve / refinement / selected-
+                              inversion workspaces); 0 = no limit.  A call
+                              that would exceed it fails with SPCHOL_ERR_OOM
+                              before allocating or enqueuing anything.       */
 } spchol_options;
 
-/* Fill *opt with the defaults (fundamental, no amalgamation, panel 64). */
+/* Fill *opt with the defaults (fundamental, no amalgamation, panel 64,
+ * atomic scatter, no workspace limit). */
 spchol_status spchol_default_options(spchol_options *opt);
 
 /* Symbolic analysis (host only, no device work): elimination tree (Sec. II),

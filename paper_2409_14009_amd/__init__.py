@@ -87,13 +87,15 @@ class SparseCholesky:
     """Symbolic analysis of a sparse SPD pattern (host), bound to the device
     of its first factorization."""
 
-    def __init__(self, n, colptr, rowind, perm=None, snode_mode=0, amalg_max_zeros=0, panel_width=64):
+    def __init__(self, n, colptr, rowind, perm=None, snode_mode=0, amalg_max_zeros=0, panel_width=64,
+                 deterministic=False, workspace_limit=0):
         L = capi.lib()
         self.n = int(n)
         self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
         self._rowind = np.ascontiguousarray(rowind, dtype=np.int64)
         self._perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
-        opts = capi.Options(int(snode_mode), int(amalg_max_zeros), int(panel_width), 0)
+        opts = capi.Options(int(snode_mode), int(amalg_max_zeros), int(panel_width), int(bool(deterministic)),
+                            int(workspace_limit))
         h = C.c_void_p()
         _check(L.spchol_analyze(self.n, _hptr(self._colptr), _hptr(self._rowind), _hptr(self._perm),
                                 C.byref(opts), C.byref(h)))
@@ -175,7 +177,8 @@ class BatchCholesky(SparseCholesky):
     matrix: `mats` is a list of (n, colptr, rowind, perm) tuples.  Values
     and right-hand sides are the concatenation of the per-matrix ones."""
 
-    def __init__(self, mats, snode_mode=0, amalg_max_zeros=0, panel_width=64):
+    def __init__(self, mats, snode_mode=0, amalg_max_zeros=0, panel_width=64, deterministic=False,
+                 workspace_limit=0):
         L = capi.lib()
         self._keep = []
         cnt = len(mats)
@@ -186,7 +189,8 @@ class BatchCholesky(SparseCholesky):
         self._keep = [ns, cps, ris, pms]
         arr = lambda xs: (C.c_void_p * max(cnt, 1))(*[None if x is None else x.ctypes.data for x in xs])
         self._pa = (arr(cps), arr(ris), arr(pms))
-        opts = capi.Options(int(snode_mode), int(amalg_max_zeros), int(panel_width), 0)
+        opts = capi.Options(int(snode_mode), int(amalg_max_zeros), int(panel_width), int(bool(deterministic)),
+                            int(workspace_limit))
         h = C.c_void_p()
         _check(L.spchol_batch_analyze(cnt, _hptr(ns), C.cast(self._pa[0], C.c_void_p), C.cast(self._pa[1], C.c_void_p),
                                       C.cast(self._pa[2], C.c_void_p), C.byref(opts), C.byref(h)))

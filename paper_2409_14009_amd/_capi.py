@@ -17,7 +17,8 @@ STATUS = {
 
 
 class Options(C.Structure):
-    _fields_ = [("snode_mode", i32), ("amalg_max_zeros", i32), ("panel_width", i32), ("reserved", i32)]
+    _fields_ = [("snode_mode", i32), ("amalg_max_zeros", i32), ("panel_width", i32), ("deterministic", i32),
+                ("workspace_limit", i64)]
 
 
 class SymInfo(C.Structure):

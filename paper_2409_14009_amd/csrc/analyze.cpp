@@ -34,7 +34,8 @@ constexpr int ERR_ARG = -1, ERR_PATTERN = -2, ERR_OOM = -4;
 }  // namespace
 
 int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64_t* perm,
-            int snode_mode, int amalg_max_zeros, int panel_width, Symbolic& S, std::string& err) {
+            int snode_mode, int amalg_max_zeros, int panel_width, int deterministic, Symbolic& S,
+            std::string& err) {
   try {
     if (n < 0 || !colptr || (n > 0 && !rowind)) { err = "analyze: null pointer or n < 0"; return ERR_ARG; }
     if (n >= (int64_t(1) << 31) - 1) { err = "analyze: n too large (rows are stored as int32)"; return ERR_ARG; }
@@ -45,6 +46,7 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
     S = Symbolic();
     S.n = n;
     S.nb = nb;
+    S.deterministic = deterministic != 0;
     if (colptr[0] != 0) { err = "analyze: colptr[0] != 0"; return ERR_PATTERN; }
     for (int64_t j = 0; j < n; ++j)
       if (colptr[j + 1] < colptr[j]) { err = "analyze: colptr not monotone"; return ERR_PATTERN; }
@@ -543,7 +545,7 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       for (int32_t J : lev) {
         const int32_t* R = S.rows.data() + S.rptr[J];
         for (int64_t c0 = K(J); c0 < M(J); c0 += kTile) {
-          bool isfar = l + 2 < S.nlevels;
+          bool isfar = l + 2 < S.nlevels && !S.deterministic;
           for (int64_t c = c0; c < std::min<int64_t>(c0 + kTile, M(J)) && isfar; ++c)
             isfar = S.level[S.snode_of[R[c]]] > l + 1;
           for (int64_t r0 = c0; r0 < M(J); r0 += kTile) {
@@ -618,7 +620,10 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       int64_t maxp = 0;
       for (int32_t J : rest[l]) maxp = std::max(maxp, npan(J));
       auto below = [&](int32_t J, int64_t p) { return p * nb + kpan(J, p); };
-      auto split = [&](int32_t J, int64_t p) { return p >= 0 && p < npan(J) && M(J) - below(J, p) > kBwdRows; };
+      // (deterministic: never split, the accumulator would take several adds per entry)
+      auto split = [&](int32_t J, int64_t p) {
+        return !S.deterministic && p >= 0 && p < npan(J) && M(J) - below(J, p) > kBwdRows;
+      };
       auto near = [&](int32_t J, int64_t p) { return p + 1 < npan(J) ? kpan(J, p + 1) : int64_t(0); };
       auto far_tiles = [&](int32_t J, int64_t p) {
         for (int64_t r0 = below(J, p) + near(J, p); r0 < M(J); r0 += kTile)
@@ -705,6 +710,79 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
           if (Lb.ntasks == 0) S.si_plan.pop_back();
         }
       }
+    }
+    // deterministic schedule: every launch whose tasks add into shared
+    // entries (fp64 atomics) is split into launches whose adds hit disjoint
+    // entries, run in a fixed order.  Two supernodes of a level add into a
+    // common entry (external update, forward solve) exactly when their
+    // off-diagonal row lists meet (a common row r gives the common diagonal
+    // target (r, r)), so the supernodes of each level are coloured greedily,
+    // smallest free colour first, and a launch is split by colour; the
+    // selected inversion's Y segments and the T sums of its Z tiles are
+    // split by segment and by tile.
+    if (S.deterministic) {
+      std::vector<int32_t> color(ns, 0);
+      {
+        std::vector<std::vector<int32_t>> used(n);  // colours holding row r, this level
+        std::vector<char> taken;
+        for (int64_t l = 0; l < S.nlevels; ++l) {
+          for (int32_t J : bylev[l]) {
+            const int32_t* R = S.rows.data() + S.rptr[J];
+            taken.assign(taken.size(), 0);
+            for (int64_t i = K(J); i < M(J); ++i)
+              for (int32_t c : used[R[i]]) {
+                if ((size_t)c >= taken.size()) taken.resize(c + 1, 0);
+                taken[c] = 1;
+              }
+            int32_t c = 0;
+            while ((size_t)c < taken.size() && taken[c]) ++c;
+            color[J] = c;
+            for (int64_t i = K(J); i < M(J); ++i) used[R[i]].push_back(c);
+          }
+          for (int32_t J : bylev[l]) {
+            const int32_t* R = S.rows.data() + S.rptr[J];
+            for (int64_t i = K(J); i < M(J); ++i) used[R[i]].clear();
+          }
+        }
+      }
+      auto split_plan = [&](std::vector<Launch>& plan) {
+        std::vector<Launch> out;
+        for (const Launch& L : plan) {
+          int32_t kind = L.kind;
+          auto key = [&](const Task& t) -> int64_t {
+            if (kind == K_SI_Y) return t.a >> 16;
+            if (kind == K_SI_ZB) return t.b;
+            return color[t.J];
+          };
+          const bool adds = kind == K_SMALL || kind == K_UPD_EXT || kind == K_FWD || kind == K_FWD2 ||
+                            kind == K_FWD_SMALL || kind == K_SI_Y || kind == K_SI_ZB;
+          if (!adds) { out.push_back(L); continue; }
+          Task* t0 = S.tasks.data() + L.off;
+          std::stable_sort(t0, t0 + L.ntasks, [&](const Task& a, const Task& b) { return key(a) < key(b); });
+          int64_t parts = 0;
+          for (int64_t q = 0; q < L.ntasks;) {
+            int64_t e = q + 1;
+            while (e < L.ntasks && key(t0[e]) == key(t0[q])) ++e;
+            Launch P = L;
+            P.off = L.off + q;
+            P.ntasks = (int32_t)(e - q);
+            P.flops = P.bytes = 0;
+            for (int64_t u = P.off; u < P.off + P.ntasks; ++u) {
+              int32_t kd = kind;
+              if (kd == K_FWD2 && !(S.tasks[u].c & 2)) kd = K_FWD;
+              cost(kd, S.tasks[u], P.flops, P.bytes);
+            }
+            out.push_back(P);
+            ++parts;
+            q = e;
+          }
+          S.max_colors = std::max(S.max_colors, parts);
+        }
+        plan.swap(out);
+      };
+      split_plan(S.factor_plan);
+      split_plan(S.fwd_plan);
+      split_plan(S.si_plan);
     }
     // row and column of each stored entry (original ordering)
     S.e_row.resize(nz);

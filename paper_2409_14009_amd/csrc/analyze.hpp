@@ -126,10 +126,16 @@ struct Symbolic {
   std::vector<int64_t> si_yoff;  // per selected-inversion slot: offset of its Y block
   int64_t si_max_slots = 0, si_max_y = 0;
   std::vector<int32_t> e_row, e_col;  // row and column of each stored entry of A
+  // deterministic schedule: no launch holds two tasks that add into one
+  // entry (the adds of a level go in launches of disjoint targets, in a
+  // fixed order), so every run gives the same bits
+  bool deterministic = false;
+  int64_t max_colors = 0;  // most launches one scatter launch was split into
 };
 
 // Returns 0, or a negative spchol_status with a message in err.
 int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64_t* perm,
-            int snode_mode, int amalg_max_zeros, int panel_width, Symbolic& S, std::string& err);
+            int snode_mode, int amalg_max_zeros, int panel_width, int deterministic, Symbolic& S,
+            std::string& err);
 
 }  // namespace spchol

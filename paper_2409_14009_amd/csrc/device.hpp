@@ -41,9 +41,13 @@ struct DevSym {
 // launchers (kernels.hip); all enqueue on `st` and return hipGetLastError()
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t st);
 hipError_t launch_status_init(unsigned long long* status, hipStream_t st);
+hipError_t launch_status_min(unsigned long long* status, unsigned long long col, hipStream_t st);
 hipError_t launch_scatter_values(const DevSym& S, const double* vals, double* L, hipStream_t st);
 hipError_t launch_factor_panel(const DevSym& S, double* L, int64_t off, int32_t ntasks,
                                unsigned long long* status, double* winv, bool diag, hipStream_t st);
+// kind 1: internal tiles (plain read-modify-write); 2: external tiles,
+// fp64 atomic adds; 3: external tiles, plain read-modify-write (only for
+// launches whose tasks add into disjoint entries)
 hipError_t launch_update(const DevSym& S, double* L, int32_t kind, int64_t off, int32_t ntasks,
                          int32_t prec, hipStream_t st);
 hipError_t launch_factor_la(const DevSym& S, double* L, int64_t off, int32_t nfirst, int32_t ntasks,

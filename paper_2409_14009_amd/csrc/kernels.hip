@@ -32,6 +32,11 @@ __global__ void k_status_init(unsigned long long* status) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *status = ULLONG_MAX;
 }
 
+// the pivot status as if column col (0-based, permuted) had failed
+__global__ void k_status_min(unsigned long long* status, unsigned long long col) {
+  if (threadIdx.x == 0) atomicMin(status, col);
+}
+
 __global__ void k_scatter_values(const int64_t* __restrict__ amap, const double* __restrict__ vals,
                                  int64_t nnz, double* __restrict__ L) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -702,7 +707,7 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
   }
   int64_t cbase_l = 0, rel_l = 0;
   int a0_l = 0;
-  if constexpr (kind == 2) {
+  if constexpr (kind >= 2) {
     const int64_t ob = S.obase[J];
     const int lc = min(col0 + lane, colEnd - 1) - k;
     const int pair_l = S.opair[ob + lc];
@@ -762,7 +767,7 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
   // only for an entry on or below the diagonal, whose row then lies in the
   // column's ancestor)
   int tpvs[TILE / 4];
-  if constexpr (kind == 2) {
+  if constexpr (kind >= 2) {
     const int gr = row0 + lane;
 #pragma unroll
     for (int j = 0; j < TILE / 4; ++j) {
@@ -806,14 +811,36 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
     for (int j = 0; j < TILE / 4; ++j) cv[j] = Cs[(w + 4 * j) * CLD + lane];
 #pragma unroll
     for (int j = 0; j < TILE / 4; ++j) cv[j] = here(cv[j]);
+    if constexpr (kind == 2) {
 #pragma unroll
-    for (int j = 0; j < TILE / 4; ++j) {
-      const int cc = w + 4 * j;
-      if (cc < cmax) {
-        const int gc = col0 + cc;
+      for (int j = 0; j < TILE / 4; ++j) {
+        const int cc = w + 4 * j;
+        if (cc < cmax) {
+          const int gc = col0 + cc;
+          const int64_t cbase = ((int64_t)__builtin_amdgcn_readlane((int)(cbase_l >> 32), cc) << 32) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)cbase_l, cc);
+          if (rowok && gr >= gc) atomicAdd(L + cbase + tpvs[j], -cv[j]);
+        }
+      }
+    } else {
+      // kind 3: no other task of the launch adds into these entries (the
+      // launch holds supernodes with disjoint row lists), so a plain
+      // read-modify-write: every read issued first (clamped to the column's
+      // own storage where the entry does not exist), then the writes
+      int64_t addr[TILE / 4];
+      double old[TILE / 4];
+#pragma unroll
+      for (int j = 0; j < TILE / 4; ++j) {
+        const int cc = min(w + 4 * j, cmax - 1);
         const int64_t cbase = ((int64_t)__builtin_amdgcn_readlane((int)(cbase_l >> 32), cc) << 32) |
                               (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)cbase_l, cc);
-        if (rowok && gr >= gc) atomicAdd(L + cbase + tpvs[j], -cv[j]);
+        addr[j] = cbase + tpvs[j];
+        old[j] = L[addr[j]];
+      }
+#pragma unroll
+      for (int j = 0; j < TILE / 4; ++j) {
+        const int cc = w + 4 * j;
+        if (cc < cmax && rowok && gr >= col0 + cc) L[addr[j]] = old[j] - cv[j];
       }
     }
   }
@@ -2026,6 +2053,11 @@ hipError_t launch_status_init(unsigned long long* status, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_status_min(unsigned long long* status, unsigned long long col, hipStream_t st) {
+  k_status_min<<<1, 64, 0, st>>>(status, col);
+  return hipGetLastError();
+}
+
 hipError_t launch_scatter_values(const DevSym& S, const double* vals, double* L, hipStream_t st) {
   if (S.nnzA <= 0) return hipSuccess;
   k_scatter_values<<<grid_for(S.nnzA), 256, 0, st>>>(S.amap, vals, S.nnzA, L);
@@ -2056,6 +2088,10 @@ hipError_t launch_update(const DevSym& S, double* L, int32_t kind, int64_t off, 
     if (prec == 2) k_update<2, 1><<<ntasks, 256, 0, st>>>(S, L, off);
     else if (prec == 1) k_update<1, 1><<<ntasks, 256, 0, st>>>(S, L, off);
     else k_update<0, 1><<<ntasks, 256, 0, st>>>(S, L, off);
+  } else if (kind == 3) {
+    if (prec == 2) k_update<2, 3><<<ntasks, 256, 0, st>>>(S, L, off);
+    else if (prec == 1) k_update<1, 3><<<ntasks, 256, 0, st>>>(S, L, off);
+    else k_update<0, 3><<<ntasks, 256, 0, st>>>(S, L, off);
   } else {
     if (prec == 2) k_update<2, 2><<<ntasks, 256, 0, st>>>(S, L, off);
     else if (prec == 1) k_update<1, 2><<<ntasks, 256, 0, st>>>(S, L, off);

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -47,6 +48,7 @@ hipError_t upload(T** dst, const std::vector<T>& v) {
 
 struct spchol_sym_s {
   Symbolic S;
+  int64_t ws_limit = 0;  // device bytes a numeric handle may hold (0: no limit)
   std::vector<int64_t> batch_off, batch_nzoff;  // block boundaries of a batch (empty: one matrix)
   const int64_t* dev_batch_off = nullptr;
   bool uploaded = false;
@@ -66,6 +68,21 @@ struct spchol_sym_s {
     if (p) allocs.push_back(p);
     *dst = p;
     return e;
+  }
+
+  // device bytes of the upload below (without uploading)
+  int64_t device_bytes() const {
+    int64_t b = 0;
+    auto add = [&](size_t cnt, size_t sz) { b += (int64_t)((cnt > 0 ? cnt : 1) * sz); };
+    const size_t ns = (size_t)S.ns;
+    add(S.loff.size(), 8); add(ns, 4); add(ns, 4); add(ns, 4);
+    add(S.rptr.size(), 8); add(S.rows.size(), 4); add(S.obase.size(), 8); add(S.opair.size(), 4);
+    add(S.ocbase.size(), 8); add(S.pa0.size(), 4); add(S.relptr.size(), 8); add(S.tpos.size(), 4);
+    add((size_t)S.n, 4); add(S.amap.size(), 8); add(S.perm.size(), 8); add(S.tasks.size(), sizeof(DevTask));
+    add(S.a_rp.size(), 8); add(S.a_col.size(), 4); add(S.a_vidx.size(), 8); add(S.e_row.size(), 4);
+    add(S.e_col.size(), 4); add(S.wbase.size(), 8); add(S.si_yoff.size(), 8);
+    add(batch_off.empty() ? 2 : batch_off.size(), 8);
+    return b;
   }
 
   spchol_status ensure_device() {
@@ -161,32 +178,36 @@ struct SolveWork {
   double* x = nullptr;
   double* acc = nullptr;
   int64_t cap = 0;  // entries of y, x and acc (n x nrhs)
-  void release() {
-    if (y) (void)hipFree(y);
-    if (x) (void)hipFree(x);
-    if (acc) (void)hipFree(acc);
-    y = x = acc = nullptr;
-    cap = 0;
+  static int64_t bytes_for(int64_t n, int64_t nrhs) { return 3 * (n * nrhs > 0 ? n * nrhs : 1) * 8; }
+  int64_t bytes() const { return cap > 0 ? 3 * cap * 8 : 0; }
+  ~SolveWork() {
+    for (double* p : {y, x, acc})
+      if (p) (void)hipFreeAsync(p, nullptr);
   }
-  ~SolveWork() { release(); }
-  // allocates (and clears acc); synchronous, never inside a capture;
-  // *moved is set when the buffers were (re)allocated
-  hipError_t ensure(int64_t n, int64_t nrhs, bool* moved = nullptr) {
+  // (Re)allocates stream-ordered on st and clears acc with a kernel: no
+  // host synchronization, never inside a capture.  *moved is set when the
+  // buffers were (re)allocated.
+  hipError_t ensure(int64_t n, int64_t nrhs, hipStream_t st, bool* moved = nullptr) {
     if (moved) *moved = false;
     if (cap >= n * nrhs && acc) return hipSuccess;
     if (moved) *moved = true;
-    release();
-    const size_t v = (size_t)(n * nrhs > 0 ? n * nrhs : 1) * sizeof(double);
-    hipError_t e = hipMalloc((void**)&y, v);
-    if (e == hipSuccess) e = hipMalloc((void**)&x, v);
-    if (e == hipSuccess) e = hipMalloc((void**)&acc, v);
-    if (e == hipSuccess) e = hipMemset(acc, 0, v);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) {
-      release();
-      return e;
+    for (double** p : {&y, &x, &acc}) {
+      if (*p) {
+        hipError_t e = hipFreeAsync(*p, st);
+        if (e != hipSuccess) return e;
+      }
+      *p = nullptr;
     }
-    cap = n * nrhs;
+    cap = 0;
+    const int64_t cnt = n * nrhs > 0 ? n * nrhs : 1;
+    const size_t v = (size_t)cnt * sizeof(double);
+    for (double** p : {&y, &x, &acc}) {
+      hipError_t e = hipMallocAsync((void**)p, v, st);
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = launch_fill(acc, cnt, 0.0, st);
+    if (e != hipSuccess) return e;
+    cap = cnt;
     return hipSuccess;
   }
 };
@@ -233,7 +254,9 @@ struct spchol_num_s {
   double* sibuf = nullptr; // Y blocks, inverses and T of one round
   double* lam = nullptr;   // adjoint solve, n x nrhs
   int64_t lcap = 0;
+  int64_t zcap = 0, sicap = 0;  // elements of Z and sibuf
   Profiler prof;
+  int64_t held = 0;  // device bytes counted against the analysis' workspace limit
   void drop_graphs(int kind) {  // kind < 0: all
     std::vector<CachedGraph> keep;
     for (CachedGraph& g : gcache) {
@@ -249,12 +272,8 @@ struct spchol_num_s {
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     if (join_ev) (void)hipEventDestroy(join_ev);
     if (side) (void)hipStreamDestroy(side);
-    if (Z) (void)hipFree(Z);
-    if (sibuf) (void)hipFree(sibuf);
-    if (lam) (void)hipFree(lam);
-    if (rwork) (void)hipFree(rwork);
-    if (pwork) (void)hipFree(pwork);
-    if (stats) (void)hipFree(stats);
+    for (void* p : {(void*)Z, (void*)sibuf, (void*)lam, (void*)rwork, (void*)pwork, (void*)stats})
+      if (p) (void)hipFreeAsync(p, nullptr);
     if (L) (void)hipFree(L);
     if (winv) (void)hipFree(winv);
     if (status) (void)hipFree(status);
@@ -284,6 +303,40 @@ static hipError_t timed_at(spchol_num_s* N, int kind, int level, int side, doubl
 template <class F>
 static hipError_t timed(spchol_num_s* N, int kind, double flops, double bytes, hipStream_t st, F&& launch) {
   return timed_at(N, kind, -1, 0, flops, bytes, st, launch);
+}
+
+// The workspace limit of the analysis: fail before allocating `extra` more
+// bytes when the handle would then hold more than the limit.
+static spchol_status ws_check(spchol_num_s* N, int64_t extra) {
+  const int64_t lim = N->sym->ws_limit;
+  if (lim > 0 && N->held + extra > lim)
+    return fail(SPCHOL_ERR_OOM, "workspace limit of " + std::to_string(lim) + " bytes: the handle holds " +
+                                    std::to_string(N->held) + " and needs " + std::to_string(extra) + " more");
+  return SPCHOL_OK;
+}
+
+// Grow a device buffer of the handle to at least `want` elements,
+// stream-ordered on st (no host synchronization; never inside a capture),
+// after checking the workspace limit.  *moved is set when it was
+// (re)allocated.
+template <class T>
+static spchol_status grow(spchol_num_s* N, T** buf, int64_t* cap, int64_t want, hipStream_t st,
+                          bool* moved = nullptr) {
+  if (moved) *moved = false;
+  if (want < 1) want = 1;
+  if (*buf && *cap >= want) return SPCHOL_OK;
+  const int64_t oldb = *buf ? *cap * (int64_t)sizeof(T) : 0, newb = want * (int64_t)sizeof(T);
+  spchol_status s = ws_check(N, newb - oldb);
+  if (s) return s;
+  if (*buf) HIP_TRY(hipFreeAsync(*buf, st));
+  *buf = nullptr;
+  *cap = 0;
+  N->held -= oldb;
+  HIP_TRY(hipMallocAsync((void**)buf, (size_t)newb, st));
+  N->held += newb;
+  *cap = want;
+  if (moved) *moved = true;
+  return SPCHOL_OK;
 }
 
 // Enqueue the whole numeric factorization on st (no host synchronization:
@@ -336,12 +389,22 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
         return launch_factor_panel(D, N->L, l.off, l.ntasks, N->status, N->winv, diag, st);
       }));
     } else {
+      // deterministic schedule: an external launch's supernodes have
+      // disjoint row lists, so its tiles read-modify-write (update kind 3)
+      const int32_t uk = (l.kind == K_UPD_EXT && S.deterministic) ? 3 : l.kind;
       HIP_TRY(timed_at(N, l.kind == K_UPD_INT ? SPCHOL_KERNEL_UPDATE_INT : SPCHOL_KERNEL_UPDATE_EXT, l.level, 0,
                        l.flops, l.bytes, st,
-                       [&] { return launch_update(D, N->L, l.kind, l.off, l.ntasks, prec, st); }));
+                       [&] { return launch_update(D, N->L, uk, l.off, l.ntasks, prec, st); }));
     }
   }
   for (int64_t v : outstanding) HIP_TRY(hipStreamWaitEvent(st, N->side_ev[v], 0));
+  // failure injection for tests of the error paths: SPCHOL_DEBUG_FAIL_AT=c
+  // (1-based permuted column) reports a failed pivot at column c as if the
+  // factorization had met one (read when the launches are enqueued)
+  if (const char* ev = std::getenv("SPCHOL_DEBUG_FAIL_AT")) {
+    const long long c = std::atoll(ev);
+    if (c >= 1 && c <= S.n) HIP_TRY(launch_status_min(N->status, (unsigned long long)(c - 1), st));
+  }
   return SPCHOL_OK;
 }
 
@@ -357,18 +420,18 @@ static spchol_status read_info(spchol_num_s* N, hipStream_t st, int64_t* info) {
 }
 
 // Permute, forward and backward supernodal solves, permute back, with the
-// work vectors of w (allocated for n x nrhs).
-static spchol_status enqueue_solve(spchol_num_s* num, SolveWork& w, double* B_dev, int64_t nrhs, int64_t ldb,
-                                   hipStream_t st) {
+// work vectors wy, wx, wacc (n x nrhs each; wacc zero on entry, left zero).
+static spchol_status enqueue_solve(spchol_num_s* num, double* wy, double* wx, double* wacc, double* B_dev,
+                                   int64_t nrhs, int64_t ldb, hipStream_t st) {
   const Symbolic& S = num->sym->S;
   const DevSym& D = num->sym->dev;
   const double pbytes = 24.0 * double(S.n) * double(nrhs);
   HIP_TRY(timed(num, SPCHOL_KERNEL_PERM, 0.0, pbytes, st,
-                [&] { return launch_perm_gather(D, B_dev, ldb, nrhs, w.y, st); }));
+                [&] { return launch_perm_gather(D, B_dev, ldb, nrhs, wy, st); }));
   // The solve of columns [c0, c0 + nr) of the block on stream s: the
   // forward and backward rounds, right-hand sides four at a time.
   auto chain = [&](int64_t c0, int64_t nr, hipStream_t s) -> hipError_t {
-    double *y = w.y + c0 * S.n, *x = w.x + c0 * S.n, *acc = w.acc + c0 * S.n;
+    double *y = wy + c0 * S.n, *x = wx + c0 * S.n, *acc = wacc + c0 * S.n;
     auto step = [&](const Launch& l) {
       // solve flops/bytes were counted for one right-hand side; L is read once
       const double fl = l.flops * double(nr);
@@ -403,28 +466,16 @@ static spchol_status enqueue_solve(spchol_num_s* num, SolveWork& w, double* B_de
     HIP_TRY(hipStreamWaitEvent(st, num->join_ev, 0));
   }
   HIP_TRY(timed(num, SPCHOL_KERNEL_PERM, 0.0, pbytes, st,
-                [&] { return launch_perm_scatter(D, w.x, nrhs, B_dev, ldb, st); }));
+                [&] { return launch_perm_scatter(D, wx, nrhs, B_dev, ldb, st); }));
   return SPCHOL_OK;
 }
 
 // Residual and statistics buffers of the refinement (n x nrhs, 3 nrhs + 1).
-static spchol_status ensure_refine_work(spchol_num_s* num, int64_t nrhs) {
+static spchol_status ensure_refine_work(spchol_num_s* num, int64_t nrhs, hipStream_t st) {
   const int64_t n = num->sym->S.n;
-  if (num->rcap < n * nrhs) {
-    if (num->rwork) HIP_TRY(hipFree(num->rwork));
-    num->rwork = nullptr;
-    num->rcap = 0;
-    HIP_TRY(hipMalloc((void**)&num->rwork, (size_t)(n * nrhs) * sizeof(double)));
-    num->rcap = n * nrhs;
-  }
-  if (num->scap < 3 * nrhs + 1) {
-    if (num->stats) HIP_TRY(hipFree(num->stats));
-    num->stats = nullptr;
-    num->scap = 0;
-    HIP_TRY(hipMalloc((void**)&num->stats, (size_t)(3 * nrhs + 1) * sizeof(unsigned long long)));
-    num->scap = 3 * nrhs + 1;
-  }
-  return SPCHOL_OK;
+  spchol_status s = grow(num, &num->rwork, &num->rcap, n * nrhs, st);
+  if (s) return s;
+  return grow(num, &num->stats, &num->scap, 3 * nrhs + 1, st);
 }
 
 // rwork <- B - A X (fp64, original A) and the normwise backward error per
@@ -504,8 +555,51 @@ static spchol_status cached_run(spchol_num_s* N, int kind, const void* ptr, int6
   return enqueue();
 }
 
+// SPCHOL_TRACE=1: the factorization runs with per-launch events and, once
+// it is done, prints one JSON line to stderr with the time, launches and
+// algorithmic flops of every level of the schedule.
+static void trace_levels(spchol_num_s* N) {
+  struct Lv { int64_t launches = 0; double ms = 0, flops = 0; };
+  std::vector<Lv> lv(N->sym->S.nlevels + 1);
+  double other = 0;
+  for (const Profiler::Rec& r : N->prof.recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+    if (r.level < 0 || r.level >= (int)lv.size()) { other += ms; continue; }
+    lv[r.level].launches += 1;
+    lv[r.level].ms += ms;
+    lv[r.level].flops += r.flops;
+  }
+  std::string o = "{\"spchol_trace\": \"factor\", \"deterministic\": " +
+                  std::string(N->sym->S.deterministic ? "true" : "false") + ", \"other_ms\": " + std::to_string(other) +
+                  ", \"levels\": [";
+  for (size_t l = 0; l < lv.size(); ++l) {
+    if (!lv[l].launches) continue;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s{\"level\": %zu, \"launches\": %lld, \"ms\": %.4f, \"gflops\": %.2f}",
+                  o.back() == '[' ? "" : ", ", l, (long long)lv[l].launches, lv[l].ms,
+                  lv[l].ms > 0 ? lv[l].flops / lv[l].ms / 1e6 : 0.0);
+    o += buf;
+  }
+  o += "]}";
+  std::fprintf(stderr, "%s\n", o.c_str());
+}
+
 static spchol_status run_factor(spchol_num_s* N, const double* vals, hipStream_t st, int64_t* info) {
+  const char* tv = std::getenv("SPCHOL_TRACE");
+  const bool trace = tv && std::atoi(tv) != 0 && !N->prof.on;
+  if (trace) {
+    N->prof.on = true;
+    N->prof.recs.clear();
+    N->prof.used = 0;
+  }
   spchol_status s = cached_run(N, 0, vals, N->prec, 0, st, [&] { return enqueue_factor(N, vals, st); });
+  if (trace) {
+    N->prof.on = false;
+    if (!s) trace_levels(N);
+    N->prof.recs.clear();
+    N->prof.used = 0;
+  }
   if (s) return s;
   return read_info(N, st, info);
 }
@@ -521,7 +615,8 @@ spchol_status spchol_default_options(spchol_options* opt) {
   opt->snode_mode = SPCHOL_SNODE_FUNDAMENTAL;
   opt->amalg_max_zeros = 0;
   opt->panel_width = 64;
-  opt->reserved = 0;
+  opt->deterministic = 0;
+  opt->workspace_limit = 0;
   return SPCHOL_OK;
 }
 
@@ -532,14 +627,20 @@ spchol_status spchol_analyze(int64_t n, const int64_t* colptr, const int64_t* ro
   spchol_options o;
   spchol_default_options(&o);
   if (opt) o = *opt;
+  if (o.workspace_limit < 0) return fail(SPCHOL_ERR_ARG, "workspace_limit < 0");
+  {
+    const char* ev = std::getenv("SPCHOL_DETERMINISTIC");
+    if (ev && std::atoi(ev) != 0) o.deterministic = 1;
+  }
   spchol_sym_s* h = new (std::nothrow) spchol_sym_s();
   if (!h) return fail(SPCHOL_ERR_OOM, "out of host memory");
   std::string err;
-  int rc = analyze(n, colptr, rowind, perm, o.snode_mode, o.amalg_max_zeros, o.panel_width, h->S, err);
+  int rc = analyze(n, colptr, rowind, perm, o.snode_mode, o.amalg_max_zeros, o.panel_width, o.deterministic, h->S, err);
   if (rc) {
     delete h;
     return fail((spchol_status)rc, err);
   }
+  h->ws_limit = o.workspace_limit;
   *out = h;
   return SPCHOL_OK;
 }
@@ -666,12 +767,21 @@ spchol_status spchol_factor_prec(spchol_sym sym, const double* vals_dev, int32_t
   if (!vals_dev && sym->S.nnzA > 0) return fail(SPCHOL_ERR_ARG, "null values");
   *out = nullptr;
   if (info) *info = 0;
+  const int64_t storage = sym->S.loff[sym->S.ns];
+  // device bytes of the new handle: the factor, the inverted diagonal
+  // blocks, status and logdet partials, and the analysis' device copy;
+  // checked against the workspace limit before anything is allocated
+  const int64_t need = 8 * std::max<int64_t>(storage, 1) + 8 * std::max<int64_t>(sym->S.wbase[sym->S.ns], 1) +
+                       8 + 8 * (logdet_partials(sym->S.n) + 1) + sym->device_bytes();
+  if (sym->ws_limit > 0 && need > sym->ws_limit)
+    return fail(SPCHOL_ERR_OOM, "workspace limit of " + std::to_string(sym->ws_limit) + " bytes: the factor needs " +
+                                    std::to_string(need));
   spchol_status s = sym->ensure_device();
   if (s) return s;
   spchol_num_s* N = new (std::nothrow) spchol_num_s();
   if (!N) return fail(SPCHOL_ERR_OOM, "out of host memory");
   N->sym = sym;
-  const int64_t storage = sym->S.loff[sym->S.ns];
+  N->held = need;
   hipError_t e = hipMalloc((void**)&N->L, (size_t)(storage > 0 ? storage : 1) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&N->status, sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMalloc((void**)&N->red, (size_t)(logdet_partials(sym->S.n) + 1) * sizeof(double));
@@ -721,9 +831,17 @@ spchol_status spchol_solve(spchol_num num, double* B_dev, int64_t nrhs, int64_t 
   if (!B_dev) return fail(SPCHOL_ERR_ARG, "null right-hand side");
   hipStream_t st = (hipStream_t)stream;
   bool moved = false;
-  HIP_TRY(num->sw.ensure(S.n, nrhs, &moved));
+  if (num->sw.cap < S.n * nrhs || !num->sw.acc) {
+    const int64_t nb = SolveWork::bytes_for(S.n, nrhs), ob = num->sw.bytes();
+    spchol_status s = ws_check(num, nb - ob);
+    if (s) return s;
+    HIP_TRY(num->sw.ensure(S.n, nrhs, st, &moved));
+    num->held += nb - ob;
+  }
   if (moved) num->drop_graphs(1);  // captured solves hold the old work vectors
-  return cached_run(num, 1, B_dev, nrhs, ldb, st, [&] { return enqueue_solve(num, num->sw, B_dev, nrhs, ldb, st); });
+  return cached_run(num, 1, B_dev, nrhs, ldb, st, [&] {
+    return enqueue_solve(num, num->sw.y, num->sw.x, num->sw.acc, B_dev, nrhs, ldb, st);
+  });
 }
 
 // Preconditioned conjugate gradients on A (fp64, original ordering) with
@@ -739,12 +857,9 @@ static spchol_status pcg(spchol_num_s* num, const double* vals, const double* B,
                          int64_t nrhs, double tol, int32_t budget, hipStream_t st, std::vector<double>& eta,
                          int32_t* it, bool* ok) {
   const int64_t n = num->sym->S.n, blk = n * nrhs;
-  if (num->pcap < 3 * blk + 3 * nrhs) {
-    if (num->pwork) HIP_TRY(hipFree(num->pwork));
-    num->pwork = nullptr;
-    num->pcap = 0;
-    HIP_TRY(hipMalloc((void**)&num->pwork, (size_t)(3 * blk + 3 * nrhs) * sizeof(double)));
-    num->pcap = 3 * blk + 3 * nrhs;
+  {
+    spchol_status s0 = grow(num, &num->pwork, &num->pcap, 3 * blk + 3 * nrhs, st);
+    if (s0) return s0;
   }
   double *z = num->pwork, *pv = z + blk, *q = pv + blk, *dots = q + blk, *scal = dots + nrhs;
   std::vector<double> rz(nrhs), h(nrhs), a(nrhs);
@@ -811,7 +926,7 @@ spchol_status spchol_refine(spchol_num num, const double* vals_dev, const double
   hipStream_t st = (hipStream_t)stream;
   const DevSym& D = num->sym->dev;
   {
-    spchol_status s = ensure_refine_work(num, nrhs);
+    spchol_status s = ensure_refine_work(num, nrhs, st);
     if (s) return s;
   }
   unsigned long long* anorm = num->stats + 3 * nrhs;
@@ -875,7 +990,7 @@ spchol_status spchol_berr(spchol_num num, const double* vals_dev, const double* 
   }
   if (!vals_dev || !B_dev || !X_dev) return fail(SPCHOL_ERR_ARG, "null device pointer");
   hipStream_t st = (hipStream_t)stream;
-  spchol_status s = ensure_refine_work(num, nrhs);
+  spchol_status s = ensure_refine_work(num, nrhs, st);
   if (s) return s;
   HIP_TRY(launch_anorm(num->sym->dev, vals_dev, num->stats + 3 * nrhs, st));
   return residual_eta(num, vals_dev, B_dev, ldb, X_dev, ldx, nrhs, st, berr_out);
@@ -887,12 +1002,14 @@ static spchol_status run_selinv(spchol_num_s* N, hipStream_t st) {
   const int64_t storage = S.loff[S.ns];
   const int64_t blk = (int64_t)kMaxPanel * kMaxPanel;
   const int64_t ws = S.si_max_y + S.si_max_slots * blk;
-  if (!N->Z) {
-    HIP_TRY(hipMalloc((void**)&N->Z, (size_t)(storage > 0 ? storage : 1) * sizeof(double)));
-    // Y blocks and T accumulators: zero here, and left zero by their readers
-    HIP_TRY(hipMalloc((void**)&N->sibuf, (size_t)(ws > 0 ? ws : 1) * sizeof(double)));
-    HIP_TRY(hipMemset(N->sibuf, 0, (size_t)(ws > 0 ? ws : 1) * sizeof(double)));
-    HIP_TRY(hipDeviceSynchronize());
+  if (!N->Z || !N->sibuf) {
+    spchol_status s = ws_check(N, 8 * (std::max<int64_t>(storage, 1) + std::max<int64_t>(ws, 1)));
+    if (s) return s;
+    if ((s = grow(N, &N->Z, &N->zcap, storage, st))) return s;
+    if ((s = grow(N, &N->sibuf, &N->sicap, ws, st))) return s;
+    // Y blocks and T accumulators: zero here (a kernel, stream-ordered),
+    // and left zero by their readers
+    HIP_TRY(launch_fill(N->sibuf, std::max<int64_t>(ws, 1), 0.0, st));
   }
   double* ybuf = N->sibuf;
   double* tbuf = ybuf + S.si_max_y;
@@ -920,12 +1037,9 @@ spchol_status spchol_backward(spchol_num num, const double* X_dev, const double*
   const DevSym& D = num->sym->dev;
   const bool use_lam = nrhs > 0 && Xbar_dev != nullptr && S.n > 0;
   if (use_lam) {
-    if (num->lcap < S.n * nrhs) {
-      if (num->lam) HIP_TRY(hipFree(num->lam));
-      num->lam = nullptr;
-      num->lcap = 0;
-      HIP_TRY(hipMalloc((void**)&num->lam, (size_t)(S.n * nrhs) * sizeof(double)));
-      num->lcap = S.n * nrhs;
+    {
+      spchol_status s0 = grow(num, &num->lam, &num->lcap, S.n * nrhs, st);
+      if (s0) return s0;
     }
     HIP_TRY(launch_copy_cols(num->lam, S.n, Xbar_dev, ld, S.n, nrhs, st));
     spchol_status s = spchol_solve(num, num->lam, nrhs, S.n, stream);
@@ -1018,7 +1132,15 @@ spchol_status spchol_graph_create(spchol_num num, const double* vals_dev, double
   // buffers the captured work uses must exist before the capture; the graph
   // owns its solve vector so that later eager solves cannot move it
   if (nrhs > 0 && S.n > 0) {
-    hipError_t ea = G->sw.ensure(S.n, nrhs);
+    const int64_t nb = SolveWork::bytes_for(S.n, nrhs);
+    spchol_status s0 = ws_check(num, nb);
+    if (s0) {
+      delete G;
+      return s0;
+    }
+    hipError_t ea = G->sw.ensure(S.n, nrhs, st);
+    // the graph may be replayed on any stream: its buffers must exist first
+    if (ea == hipSuccess) ea = hipStreamSynchronize(st);
     if (ea != hipSuccess) {
       delete G;
       return fail(SPCHOL_ERR_OOM, std::string("graph work vectors: ") + hipGetErrorString(ea));
@@ -1030,7 +1152,7 @@ spchol_status spchol_graph_create(spchol_num num, const double* vals_dev, double
   spchol_status s = SPCHOL_OK;
   if (e == hipSuccess) {
     if (vals_dev || S.nnzA == 0) s = enqueue_factor(num, vals_dev, st);
-    if (!s && nrhs > 0 && S.n > 0) s = enqueue_solve(num, G->sw, B_dev, nrhs, ldb, st);
+    if (!s && nrhs > 0 && S.n > 0) s = enqueue_solve(num, G->sw.y, G->sw.x, G->sw.acc, B_dev, nrhs, ldb, st);
     hipError_t e2 = hipStreamEndCapture(st, &G->graph);
     if (!s && e2 != hipSuccess) e = e2;
   }

@@ -37,6 +37,7 @@ struct Access {
 
 int64_t g_launch = 0;
 std::string g_err;
+bool g_det = false;  // deterministic schedule: not even two atomic adds per entry and launch
 
 bool fail(const std::string& m) {
   if (g_err.empty()) g_err = m;
@@ -52,7 +53,8 @@ bool on_read(Access& A, int64_t e, int32_t task) {
 
 bool on_write(Access& A, int64_t e, int32_t task, bool atomic) {
   if (A.rl[e] == g_launch && A.rt[e] != task) return fail("write of an entry another task of the launch reads");
-  if (A.wl[e] == g_launch && A.wt[e] != task && !(atomic && A.wa[e])) return fail("two writers in one launch");
+  if (A.wl[e] == g_launch && A.wt[e] != task && !(atomic && A.wa[e] && !g_det))
+    return fail(g_det ? "two adds into one entry in one launch of a deterministic schedule" : "two writers in one launch");
   A.wl[e] = g_launch; A.wt[e] = task; A.wa[e] = atomic;
   return true;
 }
@@ -61,7 +63,7 @@ bool on_write(Access& A, int64_t e, int32_t task, bool atomic) {
 
 int main(int argc, char** argv) {
   if (argc < 5) {
-    std::fprintf(stderr, "usage: plan_check pattern.txt snode_mode amalg_z panel_width\n");
+    std::fprintf(stderr, "usage: plan_check pattern.txt snode_mode amalg_z panel_width [deterministic]\n");
     return 2;
   }
   FILE* f = std::fopen(argv[1], "r");
@@ -75,8 +77,9 @@ int main(int argc, char** argv) {
   std::fclose(f);
   Symbolic S;
   std::string err;
-  if (analyze(n, cp.data(), ri.data(), pm.data(), std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]), S,
-              err)) {
+  g_det = argc > 5 && std::atoi(argv[5]) != 0;
+  if (analyze(n, cp.data(), ri.data(), pm.data(), std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]),
+              g_det ? 1 : 0, S, err)) {
     std::printf("analyze failed: %s\n", err.c_str());
     return 1;
   }
@@ -393,8 +396,9 @@ int main(int argc, char** argv) {
   for (const Launch& L : S.fwd_plan) fwd_bytes += L.bytes;
   for (const Launch& L : S.bwd_plan) bwd_bytes += L.bytes;
   std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld fwd2=%lld small=%lld small_solve=%lld fwd_bytes=%.0f "
-              "bwd_bytes=%.0f storage=%lld\n",
+              "bwd_bytes=%.0f storage=%lld colors=%lld si_launches=%zu\n",
               S.factor_plan.size(), S.fwd_plan.size(), S.bwd_plan.size(), (long long)bsplit, (long long)nfwd2,
-              (long long)nsmall, (long long)nssolve, fwd_bytes, bwd_bytes, (long long)storage);
+              (long long)nsmall, (long long)nssolve, fwd_bytes, bwd_bytes, (long long)storage,
+              (long long)S.max_colors, S.si_plan.size());
   return 0;
 }

@@ -40,7 +40,7 @@ def test_version_and_defaults():
     from paper_2409_14009_amd import _capi
     o = _capi.Options()
     assert sc.lib().spchol_default_options(C.byref(o)) == 0
-    assert (o.snode_mode, o.amalg_max_zeros, o.panel_width) == (0, 0, 64)
+    assert (o.snode_mode, o.amalg_max_zeros, o.panel_width, o.deterministic, o.workspace_limit) == (0, 0, 64, 0, 0)
 
 
 def _status(n, cp, ri, perm=None, opts=None):
@@ -66,7 +66,7 @@ def test_analyze_argument_errors():
     assert _status(2, np.array([0, 2, 2]), np.array([0, 1])) == -2      # missing diagonal col 1
     assert _status(2, np.array([0, 3, 4]), np.array([0, 1, 1, 1])) == -2  # duplicate
     from paper_2409_14009_amd import _capi
-    bad = _capi.Options(0, 0, 40, 0)
+    bad = _capi.Options(0, 0, 40, 0, 0)
     assert _status(2, cp, ri, None, bad) == -1                 # panel width not a multiple of 16
     assert "panel" in sc.lib().spchol_last_error().decode()
 
@@ -152,3 +152,37 @@ def test_storage_offsets():
     m = np.diff(e["row_ptr"])
     assert np.array_equal(np.diff(off), k * m)
     assert off[-1] == S.info()["storage"]
+
+
+def test_workspace_limit_fails_before_any_device_work():
+    """A workspace limit below what the factor needs gives SPCHOL_ERR_OOM
+    before the library allocates or enqueues anything (so the host path
+    reports it even where no GPU is present); a negative limit is an
+    argument error."""
+    p = gen.make_config(0, side=12)
+    S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, workspace_limit=4096)
+    h = C.c_void_p()
+    info = C.c_int64(0)
+    fake = C.c_void_p(256)  # never dereferenced: the limit check comes first
+    rc = sc.lib().spchol_factor(S._h, fake, None, C.byref(h), C.byref(info))
+    assert rc == -4 and not h.value
+    msg = sc.lib().spchol_last_error().decode()
+    assert "workspace limit of 4096 bytes" in msg
+    need = int(msg.split("needs ")[1])
+    st = S.info()["storage"]
+    assert need > 8 * st
+    from paper_2409_14009_amd import _capi
+    assert _status(2, np.array([0, 2, 3]), np.array([0, 1, 1]), None, _capi.Options(0, 0, 64, 0, -1)) == -1
+
+
+def test_deterministic_option_keeps_the_structure(monkeypatch):
+    """The deterministic schedule changes launches, not the analysis: the
+    exported structure is identical, with the option or the environment
+    override."""
+    p = gen.make_config(1, side=10)
+    a = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, 0, 8).export()
+    b = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, 0, 8, deterministic=True).export()
+    monkeypatch.setenv("SPCHOL_DETERMINISTIC", "1")
+    c = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, 0, 8).export()
+    for k in a:
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k

@@ -24,7 +24,7 @@ def checker(tmp_path_factory):
     return exe
 
 
-def _run(checker, tmp_path, n, cp, ri, perm, mode, z, nb):
+def _run(checker, tmp_path, n, cp, ri, perm, mode, z, nb, det=0):
     f = tmp_path / "pat.txt"
     perm = np.arange(n) if perm is None else perm
     with open(f, "w") as fh:
@@ -32,7 +32,7 @@ def _run(checker, tmp_path, n, cp, ri, perm, mode, z, nb):
         fh.write(" ".join(map(str, cp)) + "\n")
         fh.write(" ".join(map(str, ri)) + "\n")
         fh.write(" ".join(map(str, perm)) + "\n")
-    r = subprocess.run([checker, str(f), str(mode), str(z), str(nb)], capture_output=True, text=True)
+    r = subprocess.run([checker, str(f), str(mode), str(z), str(nb), str(det)], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     return r.stdout
 
@@ -121,3 +121,21 @@ def test_small_supernode_limits(checker, tmp_path, k, r, small):
     # the two leaves, and the parent block too when it fits
     parent = r > 0 and r <= 16 and (4 if r <= 4 else 16) + r <= 64
     assert nsmall == (2 if small else 0) + (1 if parent else 0), out
+
+
+@pytest.mark.parametrize("cfg,side,z,nb", [(0, 24, 0, 64), (1, 12, 8, 32), (1, 20, 8, 64), (2, 5, 8, 64)])
+def test_deterministic_schedule(checker, tmp_path, cfg, side, z, nb):
+    """Deterministic schedule: the same replay, and no launch holds two adds
+    into one entry (so atomic adds land in a fixed order); the scatter
+    launches are split by a colouring of each level's supernodes, the
+    backward solve never splits a panel, and no update runs on the second
+    stream."""
+    p = gen.make_config(cfg, side=side)
+    out = _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, z, nb, det=1)
+    assert int(out.split("split_bwd=")[1].split()[0]) == 0, out
+    colors = int(out.split("colors=")[1].split()[0])
+    assert 2 <= colors <= 64, out
+    base = _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, z, nb, det=0)
+    nl = lambda o: sum(int(x) for x in o.split("launches=")[1].split()[0].split("+"))
+    assert nl(out) > nl(base)
+    print(out)
