@@ -243,6 +243,24 @@ spchol_status spchol_refine(spchol_num num, const double *vals_dev, const double
 spchol_status spchol_solve(spchol_num num, double *B_dev, int64_t nrhs, int64_t ldb,
                            void *stream);
 
+/* spchol_solve for callers that cannot allocate device memory (code under
+ * hipGraph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and launch sequence, with the solve's work vectors in a
+ * static array of this library in device memory (3 x 2^21 doubles = 48 MiB
+ * per GPU, held by every GPU the call runs on until the process ends)
+ * instead of buffers of the handle.  Allocates nothing (no hipMalloc,
+ * hipFree, graph instantiation or event creation; per-launch profiling is
+ * off for the call) and enqueues every launch eagerly on `stream`, so it
+ * can itself be captured.  Requires n * nrhs <= 2^21 (SPCHOL_ERR_ARG
+ * otherwise, before any device work), the current device to be the one the
+ * factor lives on, and the handle's factor to exist.  Every call on one GPU
+ * shares that GPU's array: calls whose work overlaps on one GPU (two
+ * streams, two host threads, two handles) race and must be ordered by the
+ * caller.  Each call clears the part of the array that must start at zero.
+ * Arguments and result as spchol_solve. */
+spchol_status spchol_solve_noalloc(spchol_num num, double *B_dev, int64_t nrhs, int64_t ldb,
+                                   void *stream);
+
 /* Reverse mode of (logdet(A), X = A^{-1} B) with respect to the stored
  * lower values of A (each off-diagonal entry stands for a_ij and a_ji) and
  * to B, for cotangents gbar_logdet (scalar) and Xbar:

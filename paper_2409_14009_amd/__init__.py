@@ -264,6 +264,14 @@ class Factor:
         _check(capi.lib().spchol_solve(self._h, _dev_f64(Bt, "B"), nrhs, self.sym.n, _stream_ptr(stream)))
         return Bt
 
+    def solve_noalloc_(self, Bt, stream=None):
+        """solve_ with the library's static per-GPU work array instead of the
+        handle's buffers (spchol_solve_noalloc: allocates nothing; n * nrhs
+        at most 2^21; calls overlapping on one GPU race)."""
+        nrhs = Bt.shape[0] if Bt.dim() == 2 else 1
+        _check(capi.lib().spchol_solve_noalloc(self._h, _dev_f64(Bt, "B"), nrhs, self.sym.n, _stream_ptr(stream)))
+        return Bt
+
     def solve(self, B, stream=None):
         """Return A^{-1} B for B of shape (n,) or (n, nrhs)."""
         if B.dim() == 1:

@@ -59,6 +59,7 @@ PROTOTYPES = {
     "spchol_refactor_prec": (i32, [vp, vp, i32, vp, i64p]),
     "spchol_refine": (i32, [vp, vp, vp, vp, i64, i64, i64, f64, i32, vp, f64p, C.POINTER(i32), C.POINTER(i32)]),
     "spchol_solve": (i32, [vp, vp, i64, i64, vp]),
+    "spchol_solve_noalloc": (i32, [vp, vp, i64, i64, vp]),
     "spchol_berr": (i32, [vp, vp, vp, vp, i64, i64, i64, vp, f64p]),
     "spchol_logdet": (i32, [vp, f64p, vp]),
     "spchol_num_export": (i32, [vp, vp, vp]),

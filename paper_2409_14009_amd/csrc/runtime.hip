@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -44,6 +45,37 @@ hipError_t upload(T** dst, const std::vector<T>& v) {
   return e;
 }
 
+}  // namespace
+
+// Solve work vectors for callers that cannot allocate device memory
+// (spchol_solve_noalloc): one array per GPU in static device memory, kept
+// until the process ends, split into three fixed slices (permuted right-hand
+// sides, forward result, split-panel accumulators).  Host code never passes
+// `scratch` itself to a kernel: its device address comes from
+// hipGetSymbolAddress, taken once per device.
+constexpr int64_t kScratchSlice = int64_t(1) << 21;  // entries (n x nrhs) per slice
+constexpr int kScratchMaxDevices = 64;
+static __device__ __align__(256) double scratch[3 * kScratchSlice];  // 48 MiB
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kScratchMaxDevices] = {};
+
+// Device address of `scratch` on the current device (set up on first use).
+spchol_status scratch_address(double** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchMaxDevices) return fail(SPCHOL_ERR_ARG, "device ordinal out of range for the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(SPCHOL_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return SPCHOL_OK;
+}
 }  // namespace
 
 struct spchol_sym_s {
@@ -842,6 +874,35 @@ spchol_status spchol_solve(spchol_num num, double* B_dev, int64_t nrhs, int64_t 
   return cached_run(num, 1, B_dev, nrhs, ldb, st, [&] {
     return enqueue_solve(num, num->sw.y, num->sw.x, num->sw.acc, B_dev, nrhs, ldb, st);
   });
+}
+
+spchol_status spchol_solve_noalloc(spchol_num num, double* B_dev, int64_t nrhs, int64_t ldb, void* stream) {
+  if (!num) return fail(SPCHOL_ERR_ARG, "null handle");
+  const Symbolic& S = num->sym->S;
+  if (nrhs < 0 || ldb < S.n || ldb < 1) return fail(SPCHOL_ERR_ARG, "bad nrhs or ldb");
+  if (nrhs == 0 || S.n == 0) return SPCHOL_OK;
+  if (!B_dev) return fail(SPCHOL_ERR_ARG, "null right-hand side");
+  if (nrhs > kScratchSlice / S.n)
+    return fail(SPCHOL_ERR_ARG, "n * nrhs = " + std::to_string(S.n) + " * " + std::to_string(nrhs) +
+                                    " exceeds the static solve workspace (" + std::to_string(kScratchSlice) +
+                                    " entries)");
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur));
+  if (!num->sym->uploaded || cur != num->sym->device)
+    return fail(SPCHOL_ERR_ARG, "the factor lives on another device");
+  double* base = nullptr;
+  spchol_status s = scratch_address(&base);
+  if (s) return s;
+  double *y = base, *x = base + kScratchSlice, *acc = base + 2 * kScratchSlice;
+  hipStream_t st = (hipStream_t)stream;
+  // the array keeps whatever the last call left: clear the accumulators
+  HIP_TRY(launch_fill(acc, S.n * nrhs, 0.0, st));
+  // no per-launch events (creating them may allocate)
+  const bool prof = num->prof.on;
+  num->prof.on = false;
+  s = enqueue_solve(num, y, x, acc, B_dev, nrhs, ldb, st);
+  num->prof.on = prof;
+  return s;
 }
 
 // Preconditioned conjugate gradients on A (fp64, original ordering) with
