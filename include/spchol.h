@@ -93,11 +93,57 @@ typedef struct {
                               inversion workspaces); 0 = no limit.  A call
                               that would exceed it fails with SPCHOL_ERR_OOM
                               before allocating or enqueuing anything.       */
+  int32_t amalg_rule;      /* SPCHOL_AMALG_*: how supernodes are merged      */
+  int32_t amalg_cap_percent; /* SPCHOL_AMALG_GREEDY: largest increase of the
+                              factor's storage, percent of nnz(L) (25)        */
+  int32_t update_method;   /* SPCHOL_UPDATE_*: how a supernode's update
+                              reaches its ancestors                          */
+  int32_t partition_refinement; /* nonzero: reorder the columns inside each
+                              (unmerged) supernode so that the rows of its
+                              descendants form fewer, longer runs of
+                              consecutive indices (Sec. IV-A; same fill).
+                              The elimination order then differs from perm:
+                              spchol_sym_perm returns the one used.          */
 } spchol_options;
 
-/* Fill *opt with the defaults (fundamental, no amalgamation, panel 64,
- * atomic scatter, no workspace limit). */
+/* Update methods.  RL (Sec. II-A): the update L_RJ L_RJ^T in 64 x 64 tiles,
+ * each entry added into its ancestor through the relative index of its row.
+ * RLB (Sec. II-B): J's rows below its columns form blocks of consecutive
+ * indices inside one ancestor; every pair of blocks (B below or equal B')
+ * is a product added straight into the ancestor's storage, addressed by one
+ * relative index per block (tiles of at most 64 x 64 inside each pair). */
+enum { SPCHOL_UPDATE_RL = 0, SPCHOL_UPDATE_RLB = 1 };
+
+/* Amalgamation rules.  ZEROS: visit supernodes by first column, merge each
+ * into its parent when the parent's columns follow right after it and the
+ * merged dense storage holds at most amalg_max_zeros explicit zeros per
+ * column (0 = no merging).  GREEDY (Sec. IV-A): merge pairs (J, p(J)) in
+ * sequence, each step the pair adding the least new fill (explicit zeros of
+ * the merged trapezoid), ties to the smaller first column, until the
+ * cumulative increase would pass amalg_cap_percent of nnz(L); only pairs
+ * whose columns are consecutive qualify (the ordering is the caller's). */
+enum { SPCHOL_AMALG_ZEROS = 0, SPCHOL_AMALG_GREEDY = 1 };
+
+/* Fill *opt with the defaults (fundamental, no amalgamation (ZEROS rule,
+ * 0 zeros; GREEDY cap 25 %), panel 64, atomic scatter, no workspace
+ * limit). */
 spchol_status spchol_default_options(spchol_options *opt);
+
+/* Fill-reducing ordering of a general sparse symmetric pattern (host only):
+ * nested dissection by multilevel graph bisection, this library's stand-in
+ * for the METIS ordering of Sec. IV-A.  Coarsening by heavy-edge matching,
+ * bisection of the coarsest graph by greedy growing, Fiduccia-Mattheyses
+ * refinement while projecting back, a minimum vertex cover of the cut edges
+ * as the separator; parts of at most leaf_size vertices (0 = 64) ordered by
+ * minimum degree.  Same result for the same seed.
+ *   n, colptr, rowind: host, CSC pattern (lower triangle as in
+ *     spchol_analyze, or both triangles; the diagonal is ignored);
+ *   perm_out: host, n entries: perm_out[k] = the original index eliminated
+ *     k-th, ready to pass to spchol_analyze.
+ * Errors: SPCHOL_ERR_ARG, SPCHOL_ERR_PATTERN (row out of range),
+ * SPCHOL_ERR_OOM. */
+spchol_status spchol_order_nd(int64_t n, const int64_t *colptr, const int64_t *rowind, int64_t leaf_size,
+                              uint64_t seed, int64_t *perm_out);
 
 /* Symbolic analysis (host only, no device work): elimination tree (Sec. II),
  * column counts, supernode partition and amalgamation, supernodal elimination
@@ -126,6 +172,11 @@ spchol_status spchol_batch_analyze(int32_t count, const int64_t *n, const int64_
 /* Batch layout (host outputs, may be NULL): count; col_off[count+1];
  * nz_off[count+1].  A handle from spchol_analyze reports one matrix. */
 spchol_status spchol_batch_info(spchol_sym sym, int32_t *count, int64_t *col_off, int64_t *nz_off);
+
+/* The elimination order of the analysis (host output, n entries): perm
+ * as given, or the refined order when partition_refinement was set; the
+ * factor is that of C = P A P^T for this order. */
+spchol_status spchol_sym_perm(spchol_sym sym, int64_t *perm_out);
 
 /* Summary of a symbolic analysis (host output). */
 typedef struct {

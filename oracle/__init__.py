@@ -51,7 +51,7 @@ def lib():
         L = C.CDLL(_LIB)
         L.oracle_symbolic.restype = C.c_void_p
         L.oracle_symbolic.argtypes = [C.c_int64, _i64p, _i64p, C.c_void_p, C.c_int32, C.c_int64,
-                                      C.POINTER(C.c_int64)]
+                                      C.c_int32, C.c_int64, C.POINTER(C.c_int64)]
         L.oracle_free.argtypes = [C.c_void_p]
         L.oracle_sym_sizes.argtypes = [C.c_void_p, _i64p]
         L.oracle_sym_get.argtypes = [C.c_void_p] + [C.c_void_p] * 14
@@ -83,14 +83,15 @@ class Symbolic:
     paper's from-the-bottom convention).
     """
 
-    def __init__(self, n, colptr, rowind, perm=None, snode_mode=0, amalg_z=0):
+    def __init__(self, n, colptr, rowind, perm=None, snode_mode=0, amalg_z=0, amalg_rule=0, amalg_cap_percent=25):
         L = lib()
         colptr = np.ascontiguousarray(colptr, dtype=np.int64)
         rowind = np.ascontiguousarray(rowind, dtype=np.int64)
         self._perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
         st = C.c_int64(0)
         h = L.oracle_symbolic(int(n), colptr, rowind if rowind.size else np.zeros(1, np.int64),
-                              _ptr(self._perm), int(snode_mode), int(amalg_z), C.byref(st))
+                              _ptr(self._perm), int(snode_mode), int(amalg_z), int(amalg_rule),
+                              int(amalg_cap_percent), C.byref(st))
         if not h:
             raise OracleError(f"oracle_symbolic failed with status {st.value}")
         self._h = h

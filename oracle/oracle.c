@@ -18,7 +18,9 @@
  *              etree child of the next.  Relaxed amalgamation (Sec. IV-A
  *              merges a supernode with its parent; the acceptance rule here
  *              is the "<= z explicit zeros per column" rule of the 3D
- *              workloads).  Supernodal etree (Fig. 1).  Relative indices
+ *              workloads), or the greedy rule of Sec. IV-A: repeatedly the
+ *              merge adding the least new storage, up to a cap on the
+ *              cumulative increase).  Supernodal etree (Fig. 1).  Relative indices
  *              relind(J, P) (Sec. II-A, the distance of a row from the
  *              bottom of P's row list; the positional reading of the
  *              worked example of Fig. 1).
@@ -198,7 +200,14 @@ static int64_t merge_union(const int64_t *a, int64_t na, const int64_t *b, int64
   return k;
 }
 
-static int build_supernodes(osym *s, int mode, int64_t z) {
+/* storage of a dense lower trapezoid of k columns and m rows */
+static int64_t trapezoid(int64_t k, int64_t m) {
+  int64_t t = 0;
+  for (int64_t c = 0; c < k; ++c) t += m - c;
+  return t;
+}
+
+static int build_supernodes(osym *s, int mode, int64_t z, int rule, int64_t cap_percent) {
   int64_t n = s->n;
   /* base partition */
   int64_t *nchild = (int64_t *)calloc((size_t)(n ? n : 1), sizeof(int64_t));
@@ -243,7 +252,42 @@ static int build_supernodes(osym *s, int mode, int64_t z) {
   int64_t *gfirst = (int64_t *)malloc((size_t)(nb ? nb : 1) * sizeof(int64_t));
   int64_t *alive = (int64_t *)malloc((size_t)(nb ? nb : 1) * sizeof(int64_t));
   for (int64_t b = 0; b < nb; ++b) { gfirst[b] = bptr[b]; alive[b] = 1; }
-  if (z > 0) {
+  if (rule == 1) {
+    /* Greedy merging (Sec. IV-A): repeatedly merge the pair (group, group
+     * holding its parent column) whose merge adds the least new storage
+     * (explicit zeros), provided the parent group starts right after it;
+     * ties go to the group with the smaller first column; stop before the
+     * cumulative increase would pass cap_percent of nnz(L).  Everything is
+     * recomputed from the row lists at every step. */
+    int64_t nnzl = 0;
+    for (int64_t j = 0; j < n; ++j) nnzl += s->count[j];
+    const int64_t cap = nnzl * cap_percent / 100;
+    int64_t added = 0;
+    int64_t *u = (int64_t *)malloc((size_t)(n ? n : 1) * sizeof(int64_t));
+    for (;;) {
+      int64_t best = -1, bq = -1, bcost = 0;
+      for (int64_t e = 0; e < nb; ++e) {
+        if (!alive[e]) continue;
+        int64_t pc = s->parent[bptr[e + 1] - 1];
+        if (pc < 0) continue;
+        int64_t q = bsn[pc];
+        while (!alive[q]) ++q;  /* groups are intervals ending at their alive base */
+        if (gfirst[q] != bptr[e + 1]) continue;
+        int64_t m = merge_union(brows[e], bm[e], brows[q], bm[q], u);
+        int64_t ke = bptr[e + 1] - gfirst[e], kq = bptr[q + 1] - gfirst[q];
+        int64_t cost = trapezoid(ke + kq, m) - trapezoid(ke, bm[e]) - trapezoid(kq, bm[q]);
+        if (best < 0 || cost < bcost) { best = e; bq = q; bcost = cost; }
+      }
+      if (best < 0 || added + bcost > cap) break;
+      int64_t *w = (int64_t *)malloc((size_t)(bm[best] + bm[bq]) * sizeof(int64_t));
+      int64_t m = merge_union(brows[best], bm[best], brows[bq], bm[bq], w);
+      free(brows[bq]);
+      brows[bq] = w; bm[bq] = m; gfirst[bq] = gfirst[best];
+      alive[best] = 0;
+      added += bcost;
+    }
+    free(u);
+  } else if (z > 0) {
     for (int64_t b = 0; b < nb; ++b) {
       int64_t last = bptr[b + 1] - 1;
       int64_t pc = s->parent[last];
@@ -331,7 +375,7 @@ static int build_supernodes(osym *s, int mode, int64_t z) {
 /* status: 0 ok, -1 bad argument, -2 bad pattern, -4 out of memory */
 osym *oracle_symbolic(int64_t n, const int64_t *colptr, const int64_t *rowind,
                       const int64_t *perm, int32_t snode_mode, int64_t amalg_z,
-                      int64_t *status) {
+                      int32_t amalg_rule, int64_t amalg_cap_percent, int64_t *status) {
   *status = 0;
   if (n < 0 || !colptr || (n > 0 && !rowind)) { *status = -1; return NULL; }
   osym *s = (osym *)calloc(1, sizeof(osym));
@@ -351,7 +395,7 @@ osym *oracle_symbolic(int64_t n, const int64_t *colptr, const int64_t *rowind,
       }
   int rc = build_C(s, colptr, rowind);
   if (!rc) rc = build_L(s);
-  if (!rc) rc = build_supernodes(s, snode_mode, amalg_z);
+  if (!rc) rc = build_supernodes(s, snode_mode, amalg_z, amalg_rule, amalg_cap_percent);
   if (rc) { *status = rc; oracle_free(s); return NULL; }
   return s;
 }

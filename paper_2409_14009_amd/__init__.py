@@ -83,19 +83,40 @@ def _precision(p):
         raise ValueError(f"unknown update precision {p!r}") from None
 
 
+def _update_method(u):
+    """"rl" / "rlb" (or 0 / 1): how a supernode's update reaches its ancestors."""
+    m = {"rl": 0, "rlb": 1, 0: 0, 1: 1}
+    if u not in m:
+        raise ValueError(f"unknown update method {u!r}")
+    return m[u]
+
+
+def order_nd(n, colptr, rowind, leaf_size=64, seed=1):
+    """Nested-dissection ordering of a sparse symmetric pattern (host; the
+    library's multilevel bisection, spchol_order_nd): perm[k] = the original
+    index eliminated k-th."""
+    cp = np.ascontiguousarray(colptr, dtype=np.int64)
+    ri = np.ascontiguousarray(rowind, dtype=np.int64)
+    perm = np.zeros(int(n), np.int64)
+    _check(capi.lib().spchol_order_nd(int(n), _hptr(cp), _hptr(ri), int(leaf_size), int(seed), _hptr(perm)))
+    return perm
+
+
 class SparseCholesky:
     """Symbolic analysis of a sparse SPD pattern (host), bound to the device
     of its first factorization."""
 
     def __init__(self, n, colptr, rowind, perm=None, snode_mode=0, amalg_max_zeros=0, panel_width=64,
-                 deterministic=False, workspace_limit=0):
+                 deterministic=False, workspace_limit=0, amalg_rule=0, amalg_cap_percent=25, update_method=0,
+                 partition_refinement=False):
         L = capi.lib()
         self.n = int(n)
         self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
         self._rowind = np.ascontiguousarray(rowind, dtype=np.int64)
         self._perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
         opts = capi.Options(int(snode_mode), int(amalg_max_zeros), int(panel_width), int(bool(deterministic)),
-                            int(workspace_limit))
+                            int(workspace_limit), int(amalg_rule), int(amalg_cap_percent),
+                            _update_method(update_method), int(bool(partition_refinement)))
         h = C.c_void_p()
         _check(L.spchol_analyze(self.n, _hptr(self._colptr), _hptr(self._rowind), _hptr(self._perm),
                                 C.byref(opts), C.byref(h)))
@@ -142,6 +163,13 @@ class SparseCholesky:
         _check(capi.lib().spchol_batch_info(self._h, C.byref(cnt), _hptr(co), _hptr(no)))
         return cnt.value, co, no
 
+    def perm(self) -> np.ndarray:
+        """The elimination order the analysis used (the given perm, or the
+        partition-refined one)."""
+        out = np.zeros(self.n, np.int64)
+        _check(capi.lib().spchol_sym_perm(self._h, _hptr(out)))
+        return out
+
     def storage_offsets(self) -> np.ndarray:
         inf = self.info()
         off = np.zeros(inf["nsuper"] + 1, np.int64)
@@ -178,7 +206,7 @@ class BatchCholesky(SparseCholesky):
     and right-hand sides are the concatenation of the per-matrix ones."""
 
     def __init__(self, mats, snode_mode=0, amalg_max_zeros=0, panel_width=64, deterministic=False,
-                 workspace_limit=0):
+                 workspace_limit=0, amalg_rule=0, amalg_cap_percent=25, update_method=0, partition_refinement=False):
         L = capi.lib()
         self._keep = []
         cnt = len(mats)
@@ -190,7 +218,8 @@ class BatchCholesky(SparseCholesky):
         arr = lambda xs: (C.c_void_p * max(cnt, 1))(*[None if x is None else x.ctypes.data for x in xs])
         self._pa = (arr(cps), arr(ris), arr(pms))
         opts = capi.Options(int(snode_mode), int(amalg_max_zeros), int(panel_width), int(bool(deterministic)),
-                            int(workspace_limit))
+                            int(workspace_limit), int(amalg_rule), int(amalg_cap_percent),
+                            _update_method(update_method), int(bool(partition_refinement)))
         h = C.c_void_p()
         _check(L.spchol_batch_analyze(cnt, _hptr(ns), C.cast(self._pa[0], C.c_void_p), C.cast(self._pa[1], C.c_void_p),
                                       C.cast(self._pa[2], C.c_void_p), C.byref(opts), C.byref(h)))

@@ -18,7 +18,8 @@ STATUS = {
 
 class Options(C.Structure):
     _fields_ = [("snode_mode", i32), ("amalg_max_zeros", i32), ("panel_width", i32), ("deterministic", i32),
-                ("workspace_limit", i64)]
+                ("workspace_limit", i64), ("amalg_rule", i32), ("amalg_cap_percent", i32),
+                ("update_method", i32), ("partition_refinement", i32)]
 
 
 class SymInfo(C.Structure):
@@ -43,6 +44,7 @@ KERNEL_KINDS = ["fill", "scatter_a", "factor", "update_int", "update_ext", "fwd"
 PROTOTYPES = {
     "spchol_default_options": (i32, [C.POINTER(Options)]),
     "spchol_analyze": (i32, [i64, vp, vp, vp, C.POINTER(Options), C.POINTER(vp)]),
+    "spchol_order_nd": (i32, [i64, vp, vp, i64, C.c_uint64, vp]),
     "spchol_sym_info": (i32, [vp, C.POINTER(SymInfo)]),
     "spchol_batch_analyze": (i32, [i32, vp, vp, vp, vp, C.POINTER(Options), C.POINTER(vp)]),
     "spchol_batch_info": (i32, [vp, C.POINTER(i32), vp, vp]),
@@ -53,6 +55,7 @@ PROTOTYPES = {
     "spchol_graph_destroy": (None, [vp]),
     "spchol_sym_export": (i32, [vp] + [vp] * 12),
     "spchol_sym_storage": (i32, [vp, vp]),
+    "spchol_sym_perm": (i32, [vp, vp]),
     "spchol_factor": (i32, [vp, vp, vp, C.POINTER(vp), i64p]),
     "spchol_refactor": (i32, [vp, vp, vp, i64p]),
     "spchol_factor_prec": (i32, [vp, vp, i32, vp, C.POINTER(vp), i64p]),

@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libspchol.so")
 ARCH = os.environ.get("SPCHOL_OFFLOAD_ARCH", "gfx950")
 
 HIP_SOURCES = ["kernels.hip", "runtime.hip"]
-CXX_SOURCES = ["analyze.cpp"]
+CXX_SOURCES = ["analyze.cpp", "order.cpp"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

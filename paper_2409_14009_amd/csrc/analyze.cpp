@@ -24,6 +24,9 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <numeric>
+#include <queue>
+#include <tuple>
 
 namespace spchol {
 
@@ -33,20 +36,25 @@ constexpr int ERR_ARG = -1, ERR_PATTERN = -2, ERR_OOM = -4;
 
 }  // namespace
 
-int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64_t* perm,
-            int snode_mode, int amalg_max_zeros, int panel_width, int deterministic, Symbolic& S,
-            std::string& err) {
+int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64_t* perm, const AnalyzeOptions& o,
+            Symbolic& S, std::string& err) {
+  const int snode_mode = o.snode_mode, amalg_max_zeros = o.amalg_max_zeros, panel_width = o.panel_width;
+  const int deterministic = o.deterministic, amalg_rule = o.amalg_rule, amalg_cap_percent = o.amalg_cap_percent;
+  if (o.update_method != 0 && o.update_method != 1) { err = "analyze: bad update_method"; return ERR_ARG; }
   try {
     if (n < 0 || !colptr || (n > 0 && !rowind)) { err = "analyze: null pointer or n < 0"; return ERR_ARG; }
     if (n >= (int64_t(1) << 31) - 1) { err = "analyze: n too large (rows are stored as int32)"; return ERR_ARG; }
     if (snode_mode != 0 && snode_mode != 1) { err = "analyze: bad snode_mode"; return ERR_ARG; }
     if (amalg_max_zeros < 0) { err = "analyze: amalg_max_zeros < 0"; return ERR_ARG; }
+    if (amalg_rule != 0 && amalg_rule != 1) { err = "analyze: bad amalg_rule"; return ERR_ARG; }
+    if (amalg_cap_percent < 0) { err = "analyze: amalg_cap_percent < 0"; return ERR_ARG; }
     int nb = panel_width == 0 ? 64 : panel_width;
     if (nb < 16 || nb > kMaxPanel || nb % 16) { err = "analyze: panel_width must be 16, 32, 48 or 64"; return ERR_ARG; }
     S = Symbolic();
     S.n = n;
     S.nb = nb;
     S.deterministic = deterministic != 0;
+    S.update_method = o.update_method;
     if (colptr[0] != 0) { err = "analyze: colptr[0] != 0"; return ERR_PATTERN; }
     for (int64_t j = 0; j < n; ++j)
       if (colptr[j + 1] < colptr[j]) { err = "analyze: colptr not monotone"; return ERR_PATTERN; }
@@ -160,7 +168,67 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       for (int64_t j = bptr[b]; j < bptr[b + 1]; ++j) t += S.count[j];
       gtrue[b] = t;
     }
-    if (amalg_max_zeros > 0) {
+    if (amalg_rule == 1) {
+      // Sec. IV-A: merge supernode pairs (J, p(J)) in sequence, each step
+      // the pair adding the least new fill, until the cumulative increase
+      // of the factor's storage would pass amalg_cap_percent of nnz(L).
+      // Candidates: a group and the group holding its parent column, when
+      // that group starts right after it (merged columns stay consecutive).
+      // New fill of merging G (K_G, M_G) into Q (K_Q, M_Q): the merged
+      // trapezoid (K_G + K_Q columns, K_G + M_Q rows) minus both trapezoids,
+      // K_G (K_G + M_Q - M_G).  Ties: the group with the smaller first column.
+      std::vector<int64_t> gend(nbase);  // union-find: base -> end of its group
+      std::iota(gend.begin(), gend.end(), 0);
+      auto find = [&](int64_t b) {
+        while (gend[b] != b) { gend[b] = gend[gend[b]]; b = gend[b]; }
+        return b;
+      };
+      auto Kg = [&](int64_t e) { return bptr[e + 1] - gfirst[e]; };
+      auto Mg = [&](int64_t e) { return (bptr[e] - gfirst[e]) + S.count[bptr[e]]; };
+      // the candidate of group e (its end): the group q holding its parent
+      // column, if q starts right after e; -1 otherwise
+      auto target = [&](int64_t e) -> int64_t {
+        const int64_t pc = S.parent[bptr[e + 1] - 1];
+        if (pc < 0) return -1;
+        const int64_t q = find(bsn[pc]);
+        return gfirst[q] == bptr[e + 1] ? q : -1;
+      };
+      auto cost = [&](int64_t e, int64_t q) { return Kg(e) * (Kg(e) + Mg(q) - Mg(e)); };
+      std::vector<int64_t> stamp(nbase, 0);
+      using Cand = std::tuple<int64_t, int64_t, int64_t, int64_t>;  // cost, first column, end, stamp
+      std::priority_queue<Cand, std::vector<Cand>, std::greater<Cand>> pq;
+      auto push = [&](int64_t e) {
+        const int64_t q = target(e);
+        if (q >= 0) pq.push(Cand{cost(e, q), gfirst[e], e, stamp[e]});
+      };
+      for (int64_t b = 0; b < nbase; ++b) push(b);
+      int64_t nnzl = 0;
+      for (int64_t j = 0; j < n; ++j) nnzl += S.count[j];
+      const int64_t cap = nnzl * (int64_t)amalg_cap_percent / 100;
+      int64_t added = 0;
+      while (!pq.empty()) {
+        const auto [c, f, e, st] = pq.top();
+        pq.pop();
+        if (!alive[e] || st != stamp[e]) continue;
+        const int64_t q = target(e);
+        if (q < 0 || cost(e, q) != c) { ++stamp[e]; push(e); continue; }
+        if (added + c > cap) break;
+        added += c;
+        gfirst[q] = gfirst[e];
+        gtrue[q] += gtrue[e];
+        alive[e] = 0;
+        gend[e] = q;
+        // q's own candidate and that of the group ending just before it
+        // (whose parent may lie in q now) change
+        ++stamp[q];
+        push(q);
+        if (gfirst[q] > 0) {
+          const int64_t prev = find(bsn[gfirst[q] - 1]);
+          ++stamp[prev];
+          push(prev);
+        }
+      }
+    } else if (amalg_max_zeros > 0) {
       const int64_t z = amalg_max_zeros;
       for (int64_t b = 0; b < nbase; ++b) {
         int64_t last = bptr[b + 1] - 1;
@@ -257,6 +325,90 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       S.max_k = std::max(S.max_k, k);
       S.max_m = std::max(S.max_m, m);
       for (int64_t t = 0; t < k; ++t) S.flops_exec += double(m - t) * double(m - t);
+    }
+    // ---- partition refinement ----------------------------------------
+    // Reorder the columns inside every supernode P so that the rows of each
+    // descendant J lying in P's columns become consecutive: the columns of P
+    // are ordered by refining the partition {cols(P)} with those row sets,
+    // largest first, each part X splitting into X n S before X \ S (stable),
+    // which makes every set of a nested or disjoint family consecutive.  The
+    // supernodal structure is kept as it is, relabelled: the partition, the
+    // diagonal blocks (stored dense) and the sets of rows below each
+    // supernode do not depend on the order of the columns inside a
+    // supernode (block elimination on the same partition), so neither does
+    // the storage (Sec. IV-A: reordering within supernodes leaves the fill
+    // unchanged).  The elimination order becomes perm composed with the
+    // relabelling (S.perm); parent and count are the unrefined ones mapped
+    // through it.
+    if (o.partition_refinement) {
+      std::vector<std::vector<std::pair<int64_t, int64_t>>> sets(ns);  // (start in rows, length) per target
+      for (int64_t J = 0; J < ns; ++J) {
+        const int64_t k = S.sptr[J + 1] - S.sptr[J], m = S.rptr[J + 1] - S.rptr[J];
+        const int32_t* R = S.rows.data() + S.rptr[J];
+        for (int64_t a = k; a < m;) {
+          const int64_t P = S.snode_of[R[a]];
+          int64_t b = a;
+          while (b < m && R[b] < S.sptr[P + 1]) ++b;
+          sets[P].push_back({S.rptr[J] + a, b - a});
+          a = b;
+        }
+      }
+      std::vector<int64_t> newidx(n);
+      std::vector<char> in(n, 0);
+      std::vector<int64_t> cur, pid, ncur, npid;
+      for (int64_t P = 0; P < ns; ++P) {
+        const int64_t f = S.sptr[P], l = S.sptr[P + 1];
+        auto& st = sets[P];
+        std::stable_sort(st.begin(), st.end(), [](const std::pair<int64_t, int64_t>& a,
+                                                  const std::pair<int64_t, int64_t>& b) { return a.second > b.second; });
+        cur.resize(l - f);
+        pid.assign(l - f, 0);
+        for (int64_t c = f; c < l; ++c) cur[c - f] = c;
+        for (const auto& e : st) {
+          if (e.second == l - f) continue;  // the whole supernode: splits nothing
+          for (int64_t q = e.first; q < e.first + e.second; ++q) in[S.rows[q]] = 1;
+          ncur.clear();
+          npid.clear();
+          int64_t np = 0;
+          for (size_t i = 0; i < cur.size();) {
+            size_t j = i;
+            while (j < cur.size() && pid[j] == pid[i]) ++j;
+            for (int pass = 0; pass < 2; ++pass) {
+              bool any = false;
+              for (size_t q = i; q < j; ++q)
+                if ((bool)in[cur[q]] == (pass == 0)) { ncur.push_back(cur[q]); npid.push_back(np); any = true; }
+              if (any) ++np;
+            }
+            i = j;
+          }
+          cur.swap(ncur);
+          pid.swap(npid);
+          for (int64_t q = e.first; q < e.first + e.second; ++q) in[S.rows[q]] = 0;
+        }
+        for (int64_t i = 0; i < l - f; ++i) newidx[cur[i]] = f + i;
+      }
+      std::vector<int64_t> nperm(n), npar(n), ncnt(n);
+      for (int64_t c = 0; c < n; ++c) {
+        nperm[newidx[c]] = S.perm[c];
+        npar[newidx[c]] = S.parent[c] < 0 ? -1 : newidx[S.parent[c]];
+        ncnt[newidx[c]] = S.count[c];
+      }
+      S.perm.swap(nperm);
+      S.parent.swap(npar);
+      S.count.swap(ncnt);
+      for (int64_t c = 0; c < n; ++c) S.pinv[S.perm[c]] = c;
+      for (int64_t J = 0; J < ns; ++J) {
+        const int64_t k = S.sptr[J + 1] - S.sptr[J];
+        int32_t* R = S.rows.data() + S.rptr[J];
+        const int64_t m = S.rptr[J + 1] - S.rptr[J];
+        for (int64_t a = 0; a < m; ++a) R[a] = (int32_t)newidx[R[a]];
+        std::sort(R, R + k);
+        std::sort(R + k, R + m);
+      }
+    }
+    if (S.update_method == 1 && S.max_m >= (int64_t(1) << 25)) {
+      err = "analyze: a supernode has too many rows for the RLB task encoding";
+      return ERR_ARG;
     }
     // ---- relative indices ---------------------------------------------
     S.opair.resize(S.obase[ns]);
@@ -403,6 +555,15 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
           by += 8.0 * double(kk) * double((r1 - t.a) + (c1 - t.b)) + 16.0 * double(valid);
           break;
         }
+        case K_UPD_RLB: {
+          const int64_t r0 = t.a & ((1 << 25) - 1), nr = (t.a >> 25) + 1;
+          const int64_t c0 = t.b & ((1 << 25) - 1), nc = (t.b >> 25) + 1;
+          int64_t valid = 0;
+          for (int64_t c = c0; c < c0 + nc; ++c) valid += std::max<int64_t>(0, r0 + nr - std::max(r0, c));
+          fl += 2.0 * double(k) * double(valid);
+          by += 8.0 * double(k) * double(nr + nc) + 16.0 * double(valid);
+          break;
+        }
         case K_FWD2: {  // (two-panel tasks; single-panel ones are costed as K_FWD)
             // z_p, the coupling block (kp1 x kp), z_{p+1}; the tile's rows in
             // both panels' columns
@@ -541,9 +702,44 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       // second stream beside the next level's panel chain (a chain alone
       // leaves most of the GPU idle) and joins before the level after
       std::vector<Task> far;
-      open(S.factor_plan, K_UPD_EXT, (int32_t)l, -1);
+      const int32_t ext_kind = S.update_method == 1 ? K_UPD_RLB : K_UPD_EXT;
+      open(S.factor_plan, ext_kind, (int32_t)l, -1);
       for (int32_t J : lev) {
         const int32_t* R = S.rows.data() + S.rptr[J];
+        if (S.update_method == 1) {
+          // RLB (Sec. II-B): J's rows below its columns in blocks of
+          // consecutive indices inside one supernode; for every block B (the
+          // target columns, in supernode P) and every block B' at or below
+          // it, the product L_B'J L_BJ^T goes straight into P's storage at
+          // the rows of B' (consecutive there too) and the columns of B:
+          // one relative index (the position of B''s first row in P) per
+          // block.  Tiles of at most 64 x 64 inside each block pair.
+          std::vector<int64_t> bs;  // block starts (local rows), then M(J)
+          for (int64_t a = K(J); a < M(J); ++a)
+            if (a == K(J) || R[a] != R[a - 1] + 1 || S.snode_of[R[a]] != S.snode_of[R[a - 1]]) bs.push_back(a);
+          bs.push_back(M(J));
+          S.rlb_blocks += (int64_t)bs.size() - 1;
+          for (size_t bi = 0; bi + 1 < bs.size(); ++bi) {
+            const int64_t cb = bs[bi], ce = bs[bi + 1];
+            const int64_t P = S.snode_of[R[cb]];
+            const bool isfar = l + 2 < S.nlevels && !S.deterministic && S.level[P] > l + 1;
+            const int32_t* PR = S.rows.data() + S.rptr[P];
+            const int64_t mP = S.rptr[P + 1] - S.rptr[P];
+            for (size_t bj = bi; bj + 1 < bs.size(); ++bj) {
+              const int64_t rb = bs[bj], re = bs[bj + 1];
+              const int64_t pos_rb = std::lower_bound(PR, PR + mP, R[rb]) - PR;
+              for (int64_t c0 = cb; c0 < ce; c0 += kTile)
+                for (int64_t r0 = (bj == bi ? c0 : rb); r0 < re; r0 += kTile) {
+                  const int64_t nr = std::min<int64_t>(kTile, re - r0), nc = std::min<int64_t>(kTile, ce - c0);
+                  const Task t{J, (int32_t)(r0 | ((nr - 1) << 25)), (int32_t)(c0 | ((nc - 1) << 25)),
+                               (int32_t)(pos_rb + (r0 - rb))};
+                  if (isfar) far.push_back(t);
+                  else S.tasks.push_back(t);
+                }
+            }
+          }
+          continue;
+        }
         for (int64_t c0 = K(J); c0 < M(J); c0 += kTile) {
           bool isfar = l + 2 < S.nlevels && !S.deterministic;
           for (int64_t c = c0; c < std::min<int64_t>(c0 + kTile, M(J)) && isfar; ++c)
@@ -556,7 +752,7 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
         }
       }
       close(S.factor_plan);
-      open(S.factor_plan, K_UPD_EXT, (int32_t)l, -1);
+      open(S.factor_plan, ext_kind, (int32_t)l, -1);
       S.factor_plan.back().side = 1;
       S.tasks.insert(S.tasks.end(), far.begin(), far.end());
       close(S.factor_plan);
@@ -754,8 +950,8 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
             if (kind == K_SI_ZB) return t.b;
             return color[t.J];
           };
-          const bool adds = kind == K_SMALL || kind == K_UPD_EXT || kind == K_FWD || kind == K_FWD2 ||
-                            kind == K_FWD_SMALL || kind == K_SI_Y || kind == K_SI_ZB;
+          const bool adds = kind == K_SMALL || kind == K_UPD_EXT || kind == K_UPD_RLB || kind == K_FWD ||
+                            kind == K_FWD2 || kind == K_FWD_SMALL || kind == K_SI_Y || kind == K_SI_ZB;
           if (!adds) { out.push_back(L); continue; }
           Task* t0 = S.tasks.data() + L.off;
           std::stable_sort(t0, t0 + L.ntasks, [&](const Task& a, const Task& b) { return key(a) < key(b); });

@@ -20,6 +20,11 @@ namespace spchol {
 //   UPD_INT    J, first local row (target rows), first local col (target
 //              cols), panel (the K range)
 //   UPD_EXT    J, first local row, first local col, -1
+//   UPD_RLB    J, first local row | (rows - 1) << 25, first local col |
+//              (cols - 1) << 25, position of the first row in the target
+//              supernode's row list: a tile of one block pair (Sec. II-B),
+//              its rows consecutive in J and in the target, its columns
+//              consecutive in the target's columns
 //   SMALL      J, -, -, -  (factor, inverse block and external update of
 //              a supernode for which small_supernode holds)
 //   FWD        J, panel, first local row of a 64-row tile below the panel
@@ -53,6 +58,7 @@ enum Kind : int32_t {
   K_FWD2 = 14,   // forward solve round with two-panel tasks
   K_FWD_SMALL = 15,  // forward solve of small one-panel supernodes, one wavefront each
   K_BWD_SMALL = 16,  // backward solve of the same
+  K_UPD_RLB = 17,    // external update by block pairs (RLB)
 };
 
 // Supernodes done by one wavefront (K_SMALL): at most 16 columns, and with
@@ -131,11 +137,28 @@ struct Symbolic {
   // fixed order), so every run gives the same bits
   bool deterministic = false;
   int64_t max_colors = 0;  // most launches one scatter launch was split into
+  int update_method = 0;   // 0 RL, 1 RLB
+  int64_t rlb_blocks = 0;  // RLB: row blocks over all supernodes updated by tiles
 };
 
 // Returns 0, or a negative spchol_status with a message in err.
-int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64_t* perm,
-            int snode_mode, int amalg_max_zeros, int panel_width, int deterministic, Symbolic& S,
-            std::string& err);
+// Options of the analysis (the C ABI's spchol_options).
+struct AnalyzeOptions {
+  int snode_mode = 0;       // 0 fundamental, 1 maximal supernodes
+  int amalg_max_zeros = 0;  // amalg_rule 0: explicit zeros allowed per column
+  int panel_width = 64;
+  int deterministic = 0;    // schedule without two adds into one entry per launch
+  int amalg_rule = 0;       // 0: per-column zero cap; 1: greedy least-new-fill merging (Sec. IV-A)
+  int amalg_cap_percent = 25;  // amalg_rule 1: storage increase allowed, percent of nnz(L)
+  int update_method = 0;    // 0: RL (update tiles scattered row by row through
+                            // relative indices); 1: RLB (Sec. II-B: block pairs of
+                            // consecutive rows, one relative index per block)
+  int partition_refinement = 0;  // reorder the columns of every supernode so that the
+                                 // rows of its descendants form fewer, longer blocks
+};
+
+// Returns 0, or a negative spchol_status with a message in err.
+int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64_t* perm, const AnalyzeOptions& o,
+            Symbolic& S, std::string& err);
 
 }  // namespace spchol

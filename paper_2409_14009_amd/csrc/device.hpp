@@ -47,7 +47,8 @@ hipError_t launch_factor_panel(const DevSym& S, double* L, int64_t off, int32_t 
                                unsigned long long* status, double* winv, bool diag, hipStream_t st);
 // kind 1: internal tiles (plain read-modify-write); 2: external tiles,
 // fp64 atomic adds; 3: external tiles, plain read-modify-write (only for
-// launches whose tasks add into disjoint entries)
+// launches whose tasks add into disjoint entries); 4: RLB block-pair tiles,
+// fp64 atomic adds at addresses from one relative index per block
 hipError_t launch_update(const DevSym& S, double* L, int32_t kind, int64_t off, int32_t ntasks,
                          int32_t prec, hipStream_t st);
 hipError_t launch_factor_la(const DevSym& S, double* L, int64_t off, int32_t nfirst, int32_t ntasks,

@@ -654,13 +654,21 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
   double* __restrict__ Cs = smem;
   T* __restrict__ As = reinterpret_cast<T*>(smem);
   T* __restrict__ Bs = reinterpret_cast<T*>(smem + UKC * ALD);
-  const int J = t.J, row0 = t.a, col0 = t.b;
+  const int J = t.J;
   const int m = S.sm[J], k = S.sk[J];
-  int kb, ke, colEnd;
+  int kb, ke, colEnd, row0 = t.a, col0 = t.b, rowEnd = m;
   if constexpr (kind == 1) {
     kb = t.c * S.nb;
     ke = min(k, kb + S.nb);
     colEnd = k;
+  } else if constexpr (kind == 4) {
+    // a block-pair tile: rows row0 .. rowEnd - 1, columns col0 .. colEnd - 1
+    kb = 0;
+    ke = k;
+    row0 = t.a & ((1 << 25) - 1);
+    rowEnd = row0 + (t.a >> 25) + 1;
+    col0 = t.b & ((1 << 25) - 1);
+    colEnd = col0 + (t.b >> 25) + 1;
   } else {
     kb = 0;
     ke = k;
@@ -679,7 +687,7 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
   // staging: thread loads rows (tid & 63) of chunk columns (tid >> 6) + 4q
   // (bf16: columns 8 (tid >> 6) + q, packed into two 8-byte groups)
   const int sr = tid & 63, sc = tid >> 6;
-  const bool va = row0 + sr < m, vb = col0 + sr < colEnd;
+  const bool va = row0 + sr < rowEnd, vb = col0 + sr < colEnd;
   const double* pa = Lj + row0 + sr;
   const double* pb = Lj + col0 + sr;
   double ra[UKC / 4], rb[UKC / 4];
@@ -707,7 +715,13 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
   }
   int64_t cbase_l = 0, rel_l = 0;
   int a0_l = 0;
-  if constexpr (kind >= 2) {
+  if constexpr (kind == 4) {
+    // RLB: every column of the tile lies in one ancestor P, at consecutive
+    // columns of it; lane l holds the storage offset of tile column l
+    const int32_t* R = S.rows + S.rptr[J];
+    const int anc = S.snode_of[R[col0]];
+    cbase_l = S.loff[anc] + (int64_t)(R[min(col0 + lane, colEnd - 1)] - S.sfirst[anc]) * S.sm[anc];
+  } else if constexpr (kind >= 2) {
     const int64_t ob = S.obase[J];
     const int lc = min(col0 + lane, colEnd - 1) - k;
     const int pair_l = S.opair[ob + lc];
@@ -767,7 +781,12 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
   // only for an entry on or below the diagonal, whose row then lies in the
   // column's ancestor)
   int tpvs[TILE / 4];
-  if constexpr (kind >= 2) {
+  if constexpr (kind == 4) {
+    // the rows are consecutive in the ancestor too: one relative index (the
+    // position of the tile's first row, task field c) for all of them
+#pragma unroll
+    for (int j = 0; j < TILE / 4; ++j) tpvs[j] = t.c + lane;
+  } else if constexpr (kind >= 2) {
     const int gr = row0 + lane;
 #pragma unroll
     for (int j = 0; j < TILE / 4; ++j) {
@@ -803,7 +822,7 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
     // target of entry (gr, gc): the ancestor column of row gc at storage
     // offset ocbase, row position tpos[relptr[pair] + gr - k - pa0[pair]]
     // with pair = (J, ancestor), fetched above
-    const bool rowok = gr < m;
+    const bool rowok = gr < rowEnd;
     // the wavefront's 16 values of the lane's row, all read before the first
     // atomic (one LDS wait, not one per column)
     double cv[TILE / 4];
@@ -811,7 +830,7 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
     for (int j = 0; j < TILE / 4; ++j) cv[j] = Cs[(w + 4 * j) * CLD + lane];
 #pragma unroll
     for (int j = 0; j < TILE / 4; ++j) cv[j] = here(cv[j]);
-    if constexpr (kind == 2) {
+    if constexpr (kind == 2 || kind == 4) {
 #pragma unroll
       for (int j = 0; j < TILE / 4; ++j) {
         const int cc = w + 4 * j;
@@ -2088,6 +2107,10 @@ hipError_t launch_update(const DevSym& S, double* L, int32_t kind, int64_t off, 
     if (prec == 2) k_update<2, 1><<<ntasks, 256, 0, st>>>(S, L, off);
     else if (prec == 1) k_update<1, 1><<<ntasks, 256, 0, st>>>(S, L, off);
     else k_update<0, 1><<<ntasks, 256, 0, st>>>(S, L, off);
+  } else if (kind == 4) {
+    if (prec == 2) k_update<2, 4><<<ntasks, 256, 0, st>>>(S, L, off);
+    else if (prec == 1) k_update<1, 4><<<ntasks, 256, 0, st>>>(S, L, off);
+    else k_update<0, 4><<<ntasks, 256, 0, st>>>(S, L, off);
   } else if (kind == 3) {
     if (prec == 2) k_update<2, 3><<<ntasks, 256, 0, st>>>(S, L, off);
     else if (prec == 1) k_update<1, 3><<<ntasks, 256, 0, st>>>(S, L, off);

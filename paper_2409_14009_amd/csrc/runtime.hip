@@ -13,6 +13,7 @@
 
 #include "../../include/spchol.h"
 #include "analyze.hpp"
+#include "order.hpp"
 #include "device.hpp"
 
 using namespace spchol;
@@ -396,8 +397,9 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
       // fork: the side stream starts once everything before is done
       HIP_TRY(hipEventRecord(N->fork_ev, st));
       HIP_TRY(hipStreamWaitEvent(N->side, N->fork_ev, 0));
+      const int32_t uk = l.kind == K_UPD_RLB ? 4 : l.kind;
       HIP_TRY(timed_at(N, SPCHOL_KERNEL_UPDATE_EXT, l.level, 1, l.flops, l.bytes, N->side,
-                       [&] { return launch_update(D, N->L, l.kind, l.off, l.ntasks, prec, N->side); }));
+                       [&] { return launch_update(D, N->L, uk, l.off, l.ntasks, prec, N->side); }));
       HIP_TRY(hipEventRecord(N->side_ev[l.level], N->side));
       outstanding.push_back(l.level);
       continue;
@@ -423,7 +425,7 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
     } else {
       // deterministic schedule: an external launch's supernodes have
       // disjoint row lists, so its tiles read-modify-write (update kind 3)
-      const int32_t uk = (l.kind == K_UPD_EXT && S.deterministic) ? 3 : l.kind;
+      const int32_t uk = l.kind == K_UPD_RLB ? 4 : (l.kind == K_UPD_EXT && S.deterministic) ? 3 : l.kind;
       HIP_TRY(timed_at(N, l.kind == K_UPD_INT ? SPCHOL_KERNEL_UPDATE_INT : SPCHOL_KERNEL_UPDATE_EXT, l.level, 0,
                        l.flops, l.bytes, st,
                        [&] { return launch_update(D, N->L, uk, l.off, l.ntasks, prec, st); }));
@@ -649,6 +651,18 @@ spchol_status spchol_default_options(spchol_options* opt) {
   opt->panel_width = 64;
   opt->deterministic = 0;
   opt->workspace_limit = 0;
+  opt->amalg_rule = SPCHOL_AMALG_ZEROS;
+  opt->amalg_cap_percent = 25;
+  opt->update_method = SPCHOL_UPDATE_RL;
+  opt->partition_refinement = 0;
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_order_nd(int64_t n, const int64_t* colptr, const int64_t* rowind, int64_t leaf_size,
+                              uint64_t seed, int64_t* perm_out) {
+  std::string err;
+  const int rc = order_nd(n, colptr, rowind, leaf_size, seed, perm_out, err);
+  if (rc) return fail((spchol_status)rc, err);
   return SPCHOL_OK;
 }
 
@@ -667,7 +681,16 @@ spchol_status spchol_analyze(int64_t n, const int64_t* colptr, const int64_t* ro
   spchol_sym_s* h = new (std::nothrow) spchol_sym_s();
   if (!h) return fail(SPCHOL_ERR_OOM, "out of host memory");
   std::string err;
-  int rc = analyze(n, colptr, rowind, perm, o.snode_mode, o.amalg_max_zeros, o.panel_width, o.deterministic, h->S, err);
+  AnalyzeOptions ao;
+  ao.snode_mode = o.snode_mode;
+  ao.amalg_max_zeros = o.amalg_max_zeros;
+  ao.panel_width = o.panel_width;
+  ao.deterministic = o.deterministic;
+  ao.amalg_rule = o.amalg_rule;
+  ao.amalg_cap_percent = o.amalg_cap_percent;
+  ao.update_method = o.update_method;
+  ao.partition_refinement = o.partition_refinement;
+  int rc = analyze(n, colptr, rowind, perm, ao, h->S, err);
   if (rc) {
     delete h;
     return fail((spchol_status)rc, err);
@@ -777,6 +800,12 @@ spchol_status spchol_sym_export(spchol_sym sym, int64_t* parent, int64_t* count,
     }
   }
   cp(level, S.level);
+  return SPCHOL_OK;
+}
+
+spchol_status spchol_sym_perm(spchol_sym sym, int64_t* perm_out) {
+  if (!sym || !perm_out) return fail(SPCHOL_ERR_ARG, "null argument");
+  if (!sym->S.perm.empty()) std::memcpy(perm_out, sym->S.perm.data(), sym->S.perm.size() * sizeof(int64_t));
   return SPCHOL_OK;
 }
 

@@ -63,7 +63,7 @@ bool on_write(Access& A, int64_t e, int32_t task, bool atomic) {
 
 int main(int argc, char** argv) {
   if (argc < 5) {
-    std::fprintf(stderr, "usage: plan_check pattern.txt snode_mode amalg_z panel_width [deterministic]\n");
+    std::fprintf(stderr, "usage: plan_check pattern.txt snode_mode amalg_z panel_width [deterministic [amalg_rule [rlb [pr]]]]\n");
     return 2;
   }
   FILE* f = std::fopen(argv[1], "r");
@@ -78,8 +78,15 @@ int main(int argc, char** argv) {
   Symbolic S;
   std::string err;
   g_det = argc > 5 && std::atoi(argv[5]) != 0;
-  if (analyze(n, cp.data(), ri.data(), pm.data(), std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]),
-              g_det ? 1 : 0, S, err)) {
+  AnalyzeOptions ao;
+  ao.snode_mode = std::atoi(argv[2]);
+  ao.amalg_max_zeros = std::atoi(argv[3]);
+  ao.panel_width = std::atoi(argv[4]);
+  ao.deterministic = g_det ? 1 : 0;
+  ao.amalg_rule = argc > 6 ? std::atoi(argv[6]) : 0;
+  ao.update_method = argc > 7 ? std::atoi(argv[7]) : 0;
+  ao.partition_refinement = argc > 8 ? std::atoi(argv[8]) : 0;
+  if (analyze(n, cp.data(), ri.data(), pm.data(), ao, S, err)) {
     std::printf("analyze failed: %s\n", err.c_str());
     return 1;
   }
@@ -149,7 +156,7 @@ int main(int argc, char** argv) {
   for (const Launch* Lp : order) {
     const Launch& L = *Lp;
     ++g_launch;
-    if (L.side && L.kind != K_UPD_EXT) ok = fail("side launch that is not an external update");
+    if (L.side && L.kind != K_UPD_EXT && L.kind != K_UPD_RLB) ok = fail("side launch that is not an external update");
     for (int32_t q = 0; q < L.ntasks && ok; ++q) {
       const Task& t = S.tasks[L.off + q];
       int32_t kind = L.kind;
@@ -210,6 +217,31 @@ int main(int argc, char** argv) {
             if (!ok) break;
             const int64_t e = ext ? target(J, c, r) : idx(J, c, r);
             ok = on_write(acc, e, q, ext);
+            if (ok && solved[e]) ok = fail("update of an entry that is already solved");
+            got[e] += 1;
+          }
+      } else if (kind == K_UPD_RLB) {
+        // one block pair tile: rows and columns consecutive indices of J,
+        // its columns inside one ancestor P; every entry's address from the
+        // block's one relative index must be the entry's target by definition
+        const int64_t msk = (int64_t(1) << 25) - 1;
+        const int64_t r0 = t.a & msk, nr = (int64_t(t.a) >> 25) + 1, c0 = t.b & msk, nc = (int64_t(t.b) >> 25) + 1;
+        if (c0 < k || r0 + nr > m || c0 + nc > m || r0 < c0) { ok = fail("RLB tile outside the supernode's rows"); break; }
+        const int32_t* R = S.rows.data() + S.rptr[J];
+        const int64_t P = S.snode_of[R[c0]];
+        const int64_t mP = S.rptr[P + 1] - S.rptr[P];
+        for (int64_t c = c0 + 1; c < c0 + nc && ok; ++c)
+          if (R[c] != R[c - 1] + 1 || S.snode_of[R[c]] != P) ok = fail("RLB column block not consecutive in one supernode");
+        for (int64_t r = r0 + 1; r < r0 + nr && ok; ++r)
+          if (R[r] != R[r - 1] + 1) ok = fail("RLB row block not consecutive");
+        for (int64_t c = c0; c < c0 + nc && ok; ++c)
+          for (int64_t r = std::max(r0, c); r < r0 + nr && ok; ++r) {
+            for (int64_t s = 0; s < k && ok; ++s) ok = need_solved(idx(J, s, r), q) && need_solved(idx(J, s, c), q);
+            if (!ok) break;
+            const int64_t e = target(J, c, r);
+            const int64_t eb = S.loff[P] + (int64_t(R[c]) - S.sptr[P]) * mP + t.c + (r - r0);
+            if (e != eb) { ok = fail("RLB block address differs from the entry's target"); break; }
+            ok = on_write(acc, e, q, true);
             if (ok && solved[e]) ok = fail("update of an entry that is already solved");
             got[e] += 1;
           }
@@ -395,10 +427,13 @@ int main(int argc, char** argv) {
   double fwd_bytes = 0, bwd_bytes = 0;
   for (const Launch& L : S.fwd_plan) fwd_bytes += L.bytes;
   for (const Launch& L : S.bwd_plan) bwd_bytes += L.bytes;
+  int64_t rlb_tasks = 0;
+  for (const Launch& L : S.factor_plan)
+    if (L.kind == K_UPD_RLB) rlb_tasks += L.ntasks;
   std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld fwd2=%lld small=%lld small_solve=%lld fwd_bytes=%.0f "
-              "bwd_bytes=%.0f storage=%lld colors=%lld si_launches=%zu\n",
+              "bwd_bytes=%.0f storage=%lld colors=%lld si_launches=%zu rlb_blocks=%lld rlb_tasks=%lld\n",
               S.factor_plan.size(), S.fwd_plan.size(), S.bwd_plan.size(), (long long)bsplit, (long long)nfwd2,
               (long long)nsmall, (long long)nssolve, fwd_bytes, bwd_bytes, (long long)storage,
-              (long long)S.max_colors, S.si_plan.size());
+              (long long)S.max_colors, S.si_plan.size(), (long long)S.rlb_blocks, (long long)rlb_tasks);
   return 0;
 }

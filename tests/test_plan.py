@@ -24,7 +24,7 @@ def checker(tmp_path_factory):
     return exe
 
 
-def _run(checker, tmp_path, n, cp, ri, perm, mode, z, nb, det=0):
+def _run(checker, tmp_path, n, cp, ri, perm, mode, z, nb, det=0, rule=0, rlb=0, pr=0):
     f = tmp_path / "pat.txt"
     perm = np.arange(n) if perm is None else perm
     with open(f, "w") as fh:
@@ -32,7 +32,8 @@ def _run(checker, tmp_path, n, cp, ri, perm, mode, z, nb, det=0):
         fh.write(" ".join(map(str, cp)) + "\n")
         fh.write(" ".join(map(str, ri)) + "\n")
         fh.write(" ".join(map(str, perm)) + "\n")
-    r = subprocess.run([checker, str(f), str(mode), str(z), str(nb), str(det)], capture_output=True, text=True)
+    r = subprocess.run([checker, str(f), str(mode), str(z), str(nb), str(det), str(rule), str(rlb), str(pr)],
+                       capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     return r.stdout
 
@@ -139,3 +140,33 @@ def test_deterministic_schedule(checker, tmp_path, cfg, side, z, nb):
     nl = lambda o: sum(int(x) for x in o.split("launches=")[1].split()[0].split("+"))
     assert nl(out) > nl(base)
     print(out)
+
+
+@pytest.mark.parametrize("cfg,side,nb", [(1, 14, 64), (2, 6, 32), (0, 40, 64)])
+def test_greedy_amalgamation_with_nd_ordering(checker, tmp_path, cfg, side, nb):
+    """The schedule of a graph-ordered, greedily merged structure (the
+    general-pattern path: the library's nested dissection and the Sec. IV-A
+    merging with a 25 % cap), in both schedules."""
+    import paper_2409_14009_amd as sc
+    p = gen.make_config(cfg, side=side)
+    perm = sc.order_nd(p.n, p.colptr, p.rowind)
+    _run(checker, tmp_path, p.n, p.colptr, p.rowind, perm, 0, 0, nb, det=0, rule=1)
+    _run(checker, tmp_path, p.n, p.colptr, p.rowind, perm, 0, 0, nb, det=1, rule=1)
+
+
+@pytest.mark.parametrize("cfg,side,z,nb,pr", [(1, 12, 8, 64, 0), (1, 12, 8, 64, 1), (0, 64, 0, 32, 1),
+                                              (2, 5, 8, 64, 1), (4, 14, 8, 64, 1)])
+def test_rlb_schedule(checker, tmp_path, cfg, side, z, nb, pr):
+    """RLB (Sec. II-B): every block-pair tile's entries, addressed from the
+    block's one relative index, are exactly the targets the method defines,
+    each received once; with partition refinement the blocks get fewer."""
+    p = gen.make_config(cfg, side=side)
+    out = _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, z, nb, rlb=1, pr=pr)
+    assert int(out.split("rlb_tasks=")[1].split()[0]) > 0, out
+    _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, z, nb, det=1, rlb=1, pr=pr)
+    if pr:
+        plain = _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, z, nb, rlb=1, pr=0)
+        b1 = int(out.split("rlb_blocks=")[1].split()[0])
+        b0 = int(plain.split("rlb_blocks=")[1].split()[0])
+        print(f"blocks without / with partition refinement: {b0} / {b1}")
+        assert b1 <= b0
