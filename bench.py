@@ -23,7 +23,11 @@ same run:
               whether refinement converged within 10 iterations);
   fwd_bwd   - 3D 48^3 random-field workload: forward (factor + solve +
               logdet) and reverse (selected inversion + gradient) times;
-  batch     - 512 independent grids, factor + 4-RHS solve as one hipGraph.
+  batch     - 512 independent grids, factor + 4-RHS solve as one hipGraph;
+  variants  - the headline matrix analysed other ways and factored the same
+              way: RLB updates (with and without partition refinement), the
+              paper's greedy supernode merging (25 % cap), the deterministic
+              schedule, the library's own nested dissection.
 
 --copy-probe runs a plain device copy of the given size (the calibration
 run for the hardware byte counters) and nothing else.
@@ -376,28 +380,29 @@ def _fwd_bwd_body(args, p, S, info, vals, Bt, Xt, Xbar, stream, steps):
 
 
 def batch(args, dev):
-    """512 independent grids: factor + 4-RHS solve captured in one hipGraph."""
+    """512 independent grids: factor + 4-RHS solve captured in one hipGraph,
+    with the analysis (supernode granularity, panel width, update method)
+    chosen by the autotuner, and the untuned default beside it."""
     import torch
     import gen
     import scipy.sparse as sp
     import paper_2409_14009_amd as sc
+    from paper_2409_14009_amd import autotune
 
     log("batch setup (512 grids)")
     probs = gen.make_batch()
     z = probs[0].meta["amalg_z"]
     mats = [(q.n, q.colptr, q.rowind, q.perm) for q in probs]
-    S = sc.BatchCholesky(mats, amalg_max_zeros=z)
-    info = S.info()
-    cnt, co, _ = S.batch_info()
     vals = torch.tensor(np.concatenate([q.vals for q in probs]), device=dev)
     B0 = torch.tensor(np.ascontiguousarray(np.concatenate([q.B.T for q in probs], axis=1)), device=dev)
     X = torch.empty_like(B0)
     mats_a = [sp.csc_matrix((q.vals, q.rowind, q.colptr), shape=(q.n, q.n)) for q in probs]
     mats_a = [A + sp.tril(A, -1).T for A in mats_a]
 
-    def run(precision):
+    def run(S, precision):
         """factor + 4-RHS solve as one graph replay; per-matrix normwise
         backward error of the result (fp64, host)"""
+        cnt, co, _ = S.batch_info()
         F = S.factor(vals, precision=precision)
         gs = torch.cuda.Stream()
         with torch.cuda.stream(gs):
@@ -422,13 +427,30 @@ def batch(args, dev):
         del F
         return t["graph"], status, worst
 
-    ms64, st64, w64 = run("f64")
-    ms32, st32, w32 = run("f32")
-    return dict(workload=gen.CONFIG_DOC[3], matrices=cnt, n_total=int(info["n"]), nsuper=info["nsuper"],
-                levels=info["nlevels"], flops_alg=info["flops_alg"], graph_ms=ms64,
-                gflops=info["flops_alg"] / ms64 * 1e-6, matrices_per_s=cnt / (ms64 * 1e-3),
-                status=st64, worst_berr=w64, amalg_max_zeros=z,
-                f32=dict(note="fp32 update products, fp64 diagonal blocks and solves, no refinement",
+    S0 = sc.BatchCholesky(mats, amalg_max_zeros=z)
+    info0 = S0.info()
+    cnt = S0.batch_info()[0]
+    ms_def, st_def, w_def = run(S0, "f64")
+    del S0
+    log("batch autotuning (granularity, panel width, update method)")
+    t0 = time.perf_counter()
+    cfg, times = autotune.tune_batch_config(mats, vals, B0, "f64", reps=3, use_cache=False)
+    tune_s = time.perf_counter() - t0
+    kw = autotune.config_kwargs(cfg)
+    S = sc.BatchCholesky(mats, **kw)
+    info = S.info()
+    ms64, st64, w64 = run(S, "f64")
+    ms32, st32, w32 = run(S, "f32")
+    return dict(workload=gen.CONFIG_DOC[3], matrices=cnt, n_total=int(info["n"]), flops_alg=info["flops_alg"],
+                tuned=dict(config=dict(amalg=list(cfg["amalg"]), panel_width=cfg["panel_width"],
+                                       update=cfg["update"]), tuning_s=tune_s,
+                           candidates_ms={k: v * 1e3 for k, v in times.items()}, nsuper=info["nsuper"],
+                           levels=info["nlevels"], flops_exec=info["flops_exec"]),
+                graph_ms=ms64, gflops=info["flops_alg"] / ms64 * 1e-6, matrices_per_s=cnt / (ms64 * 1e-3),
+                status=st64, worst_berr=w64,
+                untuned=dict(amalg_max_zeros=z, panel_width=64, update="rl", nsuper=info0["nsuper"],
+                             levels=info0["nlevels"], graph_ms=ms_def, status=st_def, worst_berr=w_def),
+                f32=dict(note="fp32 update products, fp64 diagonal blocks and solves, no refinement; tuned config",
                          graph_ms=ms32, matrices_per_s=cnt / (ms32 * 1e-3), status=st32, worst_berr=w32))
 
 
@@ -443,6 +465,55 @@ def copy_probe(mib):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": n * 8}), flush=True)
+
+
+def variants(args, dev, p, z):
+    """Other analyses of the headline matrix, each factored through a
+    captured graph: RLB update (with partition refinement), the paper's
+    greedy supernode merging (25 % cap), the deterministic schedule, and
+    the library's own nested dissection with the greedy merging."""
+    import torch
+    import paper_2409_14009_amd as sc
+
+    log("variants of the headline analysis")
+    vals = torch.tensor(p.vals, device=dev)
+    Bt = torch.tensor(np.ascontiguousarray(p.B.T), device=dev)
+    t0 = time.perf_counter()
+    nd = sc.order_nd(p.n, p.colptr, p.rowind)
+    order_s = time.perf_counter() - t0
+    cases = [
+        ("rlb_pr", p.perm, dict(amalg_max_zeros=z, update_method="rlb", partition_refinement=True)),
+        ("rlb", p.perm, dict(amalg_max_zeros=z, update_method="rlb")),
+        ("greedy25", p.perm, dict(amalg_rule=1, amalg_cap_percent=25)),
+        ("deterministic", p.perm, dict(amalg_max_zeros=z, deterministic=True)),
+        ("own_nd_greedy25", nd, dict(amalg_rule=1, amalg_cap_percent=25)),
+    ]
+    out = {"own_nd_order_s": order_s}
+    for name, perm, kw in cases:
+        t0 = time.perf_counter()
+        S = sc.SparseCholesky(p.n, p.colptr, p.rowind, perm, 0, **kw)
+        an_s = time.perf_counter() - t0
+        info = S.info()
+        F = S.factor(vals)
+        gs = torch.cuda.Stream()
+        with torch.cuda.stream(gs):
+            G = F.capture(vals, stream=gs)
+            for _ in range(args.warmup):
+                G.replay(gs)
+            t = _timed_steps(max(3, args.steps // 2), gs, [("factor", lambda: G.replay(gs))])
+            st = F.status(gs)
+        G.close()
+        Xt = Bt.clone()
+        F.solve_(Xt)
+        eta = F.berr_(vals, Bt, Xt)
+        out[name] = dict(analysis_s=an_s, nsuper=info["nsuper"], nnz_l=info["nnz_l"], storage=info["storage"],
+                         flops_alg=info["flops_alg"], flops_exec=info["flops_exec"], factor_ms=t["factor"],
+                         gflops=info["flops_alg"] / (t["factor"] * 1e-3) / 1e9, status=st,
+                         backward_error=max(eta))
+        log(f"  {name}: factor {t['factor']:.2f} ms")
+        del F, S
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -476,6 +547,8 @@ def main():
         extras["fwd_bwd"] = fwd_bwd(args, dev)
         torch.cuda.empty_cache()
         extras["batch"] = batch(args, dev)
+        torch.cuda.empty_cache()
+        extras["variants"] = variants(args, dev, p, z)
         torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu_baseline:
