@@ -297,3 +297,32 @@ def test_graph_replay_many_rhs(nrhs):
         assert ex <= 1e-12, (r, ex)
         del junk
     G.close()
+
+
+def test_autotune_batch_config(tmp_path, monkeypatch):
+    """The tuner over supernode granularity, panel width and update method:
+    its choice lies in the search space, every candidate was timed (or
+    skipped by the axis-wise search), the tuned analysis passes the per-matrix
+    oracle gates, and the choice is cached per precision."""
+    from paper_2409_14009_amd import autotune
+    monkeypatch.setenv("SPCHOL_TUNE_CACHE", str(tmp_path / "tune.json"))
+    autotune._mem_cache.clear()
+    probs, mats, vals, Bt = _batch(16, nrhs=2)
+    v = torch.tensor(vals, device="cuda")
+    B = torch.tensor(Bt, device="cuda")
+    cfg, times = autotune.tune_batch_config(mats, v, B, "f64", reps=1)
+    assert tuple(cfg["amalg"]) in [tuple(a) for a in autotune.AMALG_CHOICES]
+    assert cfg["panel_width"] in autotune.WIDTH_CHOICES and cfg["update"] in autotune.UPDATE_CHOICES
+    assert len(times) == len(autotune.AMALG_CHOICES) + len(autotune.WIDTH_CHOICES) + len(autotune.UPDATE_CHOICES) - 2
+    assert all(math.isfinite(t) and t > 0 for t in times.values())
+    print(f"  tuned {cfg} from {times}", flush=True)
+    S = sc.BatchCholesky(mats, **autotune.config_kwargs(cfg))
+    cnt, co, _ = S.batch_info()
+    F = S.factor(v)
+    Xt = B.clone()
+    F.solve_(Xt)
+    _check_per_matrix(probs, co, F.logdet_batch().cpu().numpy(), Xt.cpu().numpy())
+    cfg2, _ = autotune.tune_batch_config(mats, v, B, "f64", reps=1)
+    assert cfg2 == cfg
+    cfg3, t3 = autotune.tune_batch_config(mats, v, B, "f32", reps=1)  # a new key: timed again
+    assert len(t3) == len(times)
