@@ -27,7 +27,9 @@ same run:
   variants  - the headline matrix analysed other ways and factored the same
               way: RLB updates (with and without partition refinement), the
               paper's greedy supernode merging (25 % cap), the deterministic
-              schedule, the library's own nested dissection.
+              schedule, the library's own nested dissection; and the
+              host-resident factorization (supernodes below the paper's
+              size threshold on the host, a 256 MiB device budget).
 
 --copy-probe runs a plain device copy of the given size (the calibration
 run for the hardware byte counters) and nothing else.
@@ -61,11 +63,18 @@ def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+def _host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count()
+
+
 def cpu_baseline(p, z, ncols=65536):
     """The oracle (plain single-thread C left-looking factorization) on a
     bounded sample: the first `ncols` columns of the same elimination order,
     which form a complete nested-dissection subtree (columns < t depend only
-    on columns < t)."""
+    on columns < t); ncols >= n times the whole factorization."""
     import oracle
     s = oracle.Symbolic(p.n, p.colptr, p.rowind, p.perm, 0, z)
     t = min(ncols, p.n)
@@ -74,10 +83,12 @@ def cpu_baseline(p, z, ncols=65536):
     dt = time.perf_counter() - t0
     assert f.info == 0
     fl = s.flops(t)
-    return dict(value=fl / dt / 1e9, unit="GFLOP/s", cores=1, kind="oracle",
-                sample=f"left-looking factorization of the first {t} columns (a complete ND subtree, "
-                       f"{fl:.3e} of {s.flops():.3e} algorithmic flops) of the same matrix and ordering, "
-                       f"{dt:.1f} s on 1 thread")
+    what = "the whole factorization" if t == p.n else f"the first {t} columns (a complete ND subtree, " \
+           f"{fl:.3e} of {s.flops():.3e} algorithmic flops)"
+    return dict(value=fl / dt / 1e9, unit="GFLOP/s", cores=1, host_cores=_host_cores(), kind="oracle",
+                seconds=dt,
+                sample=f"left-looking factorization of {what} of the same matrix and ordering, "
+                       f"{dt:.1f} s on 1 thread of {_host_cores()} host cores")
 
 
 def measured_traffic(kernel):
@@ -340,8 +351,6 @@ def fwd_bwd(args, dev):
 
     log("reverse mode setup (3D 48^3 random field)")
     p = gen.make_config(4)
-    S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, p.meta["snode_mode"], p.meta["amalg_z"])
-    info = S.info()
     vals = torch.tensor(p.vals, device=dev)
     Bt = torch.tensor(np.ascontiguousarray(p.B.T), device=dev)
     Xt = torch.empty_like(Bt)
@@ -351,8 +360,19 @@ def fwd_bwd(args, dev):
     # factorization and solve replay captured graphs
     stream = torch.cuda.Stream()
     steps = max(2, args.steps // 2)
+    # the workload's analysis (the paper's greedy merging), and the
+    # per-column zero cap z = 8 beside it
+    S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, p.meta["snode_mode"], p.meta["amalg_z"],
+                          amalg_rule=p.meta["amalg_rule"], amalg_cap_percent=p.meta["amalg_cap_percent"])
     with torch.cuda.stream(stream):
-        return _fwd_bwd_body(args, p, S, info, vals, Bt, Xt, Xbar, stream, steps)
+        out = _fwd_bwd_body(args, p, S, S.info(), vals, Bt, Xt, Xbar, stream, steps)
+    del S
+    S8 = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, p.meta["snode_mode"], 8)
+    with torch.cuda.stream(stream):
+        o8 = _fwd_bwd_body(args, p, S8, S8.info(), vals, Bt, Xt, Xbar, stream, steps)
+    out["amalgamation"] = "greedy merging, 25 % cap" if p.meta["amalg_rule"] == 1 else f"z={p.meta['amalg_z']}"
+    out["with_z8"] = {k: o8[k] for k in ("fwd_ms", "bwd_ms", "fwd_bwd_ms", "grads_finite")}
+    return out
 
 
 def _fwd_bwd_body(args, p, S, info, vals, Bt, Xt, Xbar, stream, steps):
@@ -513,6 +533,21 @@ def variants(args, dev, p, z):
         log(f"  {name}: factor {t['factor']:.2f} ms")
         del F, S
         torch.cuda.empty_cache()
+    # the host-resident factorization (the paper's architecture): supernodes
+    # with k m below the paper's RL threshold on the host, the others on the
+    # device within a 256 MiB budget, update blocks assembled by the host
+    S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, 0, z)
+    info = S.info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Lh, st_info, st = S.factor_streamed(p.vals, device_budget=256 << 20, host_threshold=600000)
+    dt = time.perf_counter() - t0
+    Ld = S.factor(vals).storage().cpu().numpy()
+    out["streamed"] = dict(host_threshold=600000, device_budget=256 << 20, seconds=dt,
+                           gflops=info["flops_alg"] / dt / 1e9, status=st_info,
+                           max_rel_diff_vs_device=float(np.abs(Ld - Lh).max() / np.abs(Ld).max()), **st)
+    log(f"  streamed: {dt:.2f} s ({st['gpu_supernodes']} supernodes on the device, {st['host_supernodes']} on the host)")
+    del Lh, Ld, S
     return out
 
 
@@ -524,6 +559,8 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--side", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="time the oracle on the whole headline factorization (about a minute) and exit")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB")
     args = ap.parse_args()
@@ -539,6 +576,12 @@ def main():
         copy_probe(args.copy_probe)
         return
 
+    if args.cpu_baseline_full:
+        import gen
+        p = gen.make_config(args.config, side=args.side)
+        log("cpu baseline: the whole factorization")
+        print(json.dumps({"cpu_baseline_full": cpu_baseline(p, p.meta["amalg_z"], ncols=p.n)}), flush=True)
+        return
     res, p, z = headline(args, dev)
     extras = {}
     if not args.no_extras:

@@ -354,11 +354,16 @@ CONFIG_DOC = {
     1: "3D 7-point Laplacian 64^3, w=10^U(-2,2), shift 1e-6, ND, amalgamation z=8, 1 RHS",
     2: "3D 27-point, 3 dofs, 40^3, rotated SPD 3x3 blocks (eig U[1,10]), delta 1e-2, ND, z=8, 8 RHS",
     3: "batch of 512 2D/3D grid Laplacians (2D side U{12..48}, 3D side U{8..20}), weights as cfg 0, z=8, 4 RHS",
-    4: "3D 7-point Laplacian 48^3, GRF log-conductivity (ell=4, std=1), shift 1e-2, ND, z=8, 1 RHS",
+    4: "3D 7-point Laplacian 48^3, GRF log-conductivity (ell=4, std=1), shift 1e-2, ND, "
+       "greedy supernode merging (25 % cap), 1 RHS",
 }
 
 DEFAULT_AMALG = {0: 0, 1: 8, 2: 8, 3: 8, 4: 8}
 DEFAULT_SNODE_MODE = {0: 0, 1: 0, 2: 0, 3: 0, 4: 0}
+# amalgamation rule per workload: (0, -) the per-column zero cap amalg_z,
+# (1, cap) greedy merging up to cap percent of nnz(L); the 48^3 random-field
+# workload does not fix a rule, so it takes the paper's (25 %)
+DEFAULT_AMALG_RULE = {0: (0, 25), 1: (0, 25), 2: (0, 25), 3: (0, 25), 4: (1, 25)}
 
 
 def make_config(i: int, seed: int | None = None, side: int | None = None) -> Problem:
@@ -392,8 +397,8 @@ def make_config(i: int, seed: int | None = None, side: int | None = None) -> Pro
     else:
         raise ValueError("config 3 is a batch: use make_batch")
     B = rng.standard_normal((nrhs, n)).T.copy(order="F")
-    meta = dict(config=i, seed=seed, side=s, amalg_z=DEFAULT_AMALG[i],
-                snode_mode=DEFAULT_SNODE_MODE[i], doc=CONFIG_DOC[i])
+    meta = dict(config=i, seed=seed, side=s, amalg_z=DEFAULT_AMALG[i], amalg_rule=DEFAULT_AMALG_RULE[i][0],
+                amalg_cap_percent=DEFAULT_AMALG_RULE[i][1], snode_mode=DEFAULT_SNODE_MODE[i], doc=CONFIG_DOC[i])
     return Problem(n, cp, ri, vv, perm, B, meta)
 
 

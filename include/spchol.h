@@ -283,6 +283,47 @@ spchol_status spchol_refine(spchol_num num, const double *vals_dev, const double
                             int32_t max_iter, void *stream, double *berr_out, int32_t *iters_out,
                             int32_t *path_out);
 
+/* Host-resident factorization (the paper's design, Sec. III): the factor
+ * lives in caller-owned host memory and the device holds only a bounded
+ * working set -- the memory-capped mode for factors that do not fit the
+ * device, and the host/device split by supernode size.  Supernodes with
+ * k * m (columns times rows) below host_threshold are factored on the host
+ * and their updates added into the ancestors there (the paper keeps them
+ * on the CPU: 600,000 for its RL variant); each larger supernode is copied
+ * to the device, factored by the same panel kernels, copied back, and its
+ * update matrix L_RJ L_RJ^T is computed on the device in column blocks that
+ * fit device_budget, each copied back and added into the ancestors by the
+ * host through the relative indices (the update-block streaming of the
+ * second GPU-RLB version).  host_threshold = 0 puts every supernode on the
+ * device; a threshold above every k * m makes no device call at all. */
+typedef struct {
+  int64_t device_budget;  /* bytes for the supernode, its inverted blocks and
+                             one update block (0 = 256 MiB); SPCHOL_ERR_OOM
+                             when the largest device supernode plus a
+                             64-column update block does not fit             */
+  int64_t host_threshold; /* k * m below this: host (0 = none on the host)  */
+  int32_t host_threads;   /* threads of the host parts (0 = hardware count)  */
+  int32_t reserved;
+} spchol_stream_options;
+
+typedef struct {
+  int64_t gpu_supernodes, host_supernodes;
+  int64_t update_blocks;  /* update column blocks copied back               */
+  int64_t h2d_bytes, d2h_bytes;
+  int64_t device_bytes;   /* device memory the call allocated (besides the
+                             analysis' device copy)                         */
+  int32_t host_threads;
+  int32_t reserved;
+} spchol_stream_stats;
+
+/* vals_host: host, fp64 values in the pattern's entry order; L_host: host,
+ * storage doubles (layout of spchol_sym_storage; pinned memory makes the
+ * copies faster), overwritten with the factor; info as spchol_factor;
+ * stats: host, may be NULL.  Synchronizes `stream` (the host work needs the
+ * device results).  No spchol_num is created: the factor is L_host. */
+spchol_status spchol_factor_streamed(spchol_sym sym, const double *vals_host, const spchol_stream_options *opt,
+                                     void *stream, double *L_host, int64_t *info, spchol_stream_stats *stats);
+
 /* Solve A X = B in place.  B_dev: device, n x nrhs column-major, leading
  * dimension ldb >= n, original (unpermuted) ordering.  Forward solve with L
  * leaves to root, backward solve with L^T root to leaves (Sec. II).  With

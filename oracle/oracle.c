@@ -207,6 +207,113 @@ static int64_t trapezoid(int64_t k, int64_t m) {
   return t;
 }
 
+/* A binary min-heap of merge candidates (cost, first column, group end,
+ * stamp), ordered by cost, then first column. */
+typedef struct { int64_t cost, first, end, stamp; } cand;
+typedef struct { cand *a; int64_t n, cap; } cheap;
+
+static int cand_less(const cand *x, const cand *y) {
+  return x->cost < y->cost || (x->cost == y->cost && x->first < y->first);
+}
+
+static void heap_push(cheap *h, cand c) {
+  if (h->n == h->cap) {
+    h->cap = h->cap ? 2 * h->cap : 64;
+    h->a = (cand *)realloc(h->a, (size_t)h->cap * sizeof(cand));
+  }
+  int64_t i = h->n++;
+  h->a[i] = c;
+  while (i > 0 && cand_less(&h->a[i], &h->a[(i - 1) / 2])) {
+    cand t = h->a[i]; h->a[i] = h->a[(i - 1) / 2]; h->a[(i - 1) / 2] = t;
+    i = (i - 1) / 2;
+  }
+}
+
+static cand heap_pop(cheap *h) {
+  cand top = h->a[0];
+  h->a[0] = h->a[--h->n];
+  for (int64_t i = 0;;) {
+    int64_t l = 2 * i + 1, r = l + 1, m = i;
+    if (l < h->n && cand_less(&h->a[l], &h->a[m])) m = l;
+    if (r < h->n && cand_less(&h->a[r], &h->a[m])) m = r;
+    if (m == i) break;
+    cand t = h->a[i]; h->a[i] = h->a[m]; h->a[m] = t;
+    i = m;
+  }
+  return top;
+}
+
+/* The group holding base supernode b: groups are runs of base supernodes
+ * ending at their one alive member, so it is the first alive base from b
+ * on (nxt links dead bases forward). */
+static int64_t group_of(int64_t *nxt, int64_t b) {
+  int64_t r = b;
+  while (nxt[r] != r) r = nxt[r];
+  while (nxt[b] != r && b != r) { int64_t t = nxt[b]; nxt[b] = r; b = t; }
+  return r;
+}
+
+/* Push the candidate of group e -- its merge into the group holding its
+ * parent column -- if that group starts right after it. */
+static void push_candidate(cheap *h, const osym *s, int64_t e, int64_t *nxt, const int64_t *bptr,
+                           const int64_t *bsn, int64_t **brows, const int64_t *bm, const int64_t *gfirst,
+                           const int64_t *stamp, int64_t *u) {
+  const int64_t pc = s->parent[bptr[e + 1] - 1];
+  if (pc < 0) return;
+  const int64_t q = group_of(nxt, bsn[pc]);
+  if (gfirst[q] != bptr[e + 1]) return;
+  const int64_t m = merge_union(brows[e], bm[e], brows[q], bm[q], u);
+  const int64_t ke = bptr[e + 1] - gfirst[e], kq = bptr[q + 1] - gfirst[q];
+  cand c = {trapezoid(ke + kq, m) - trapezoid(ke, bm[e]) - trapezoid(kq, bm[q]), gfirst[e], e, stamp[e]};
+  heap_push(h, c);
+}
+
+/* The greedy rule (Sec. IV-A): repeatedly merge the pair (group, group
+ * holding its parent column) whose merge adds the least new storage
+ * (explicit zeros of the merged trapezoid), if the parent group starts
+ * right after it; ties go to the group with the smaller first column; stop
+ * before the cumulative increase would pass cap_percent of nnz(L).  The
+ * cost of a candidate is counted from the explicit union of both row
+ * lists.  A merge changes two candidates: the merged group's own and that
+ * of the group ending right before it; they are pushed again with a new
+ * stamp, older entries are skipped. */
+static void greedy_merge(osym *s, int64_t nb, const int64_t *bptr, const int64_t *bsn, int64_t **brows,
+                         int64_t *bm, int64_t *gfirst, int64_t *alive, int64_t cap_percent) {
+  const int64_t n = s->n;
+  int64_t nnzl = 0;
+  for (int64_t j = 0; j < n; ++j) nnzl += s->count[j];
+  const int64_t cap = nnzl * cap_percent / 100;
+  int64_t added = 0;
+  int64_t *u = (int64_t *)malloc((size_t)(n ? n : 1) * sizeof(int64_t));
+  int64_t *nxt = (int64_t *)malloc(((size_t)nb + 1) * sizeof(int64_t));
+  int64_t *stamp = (int64_t *)calloc((size_t)(nb ? nb : 1), sizeof(int64_t));
+  for (int64_t b = 0; b <= nb; ++b) nxt[b] = b;
+  cheap h = {NULL, 0, 0};
+  for (int64_t e = 0; e < nb; ++e) push_candidate(&h, s, e, nxt, bptr, bsn, brows, bm, gfirst, stamp, u);
+  while (h.n > 0) {
+    cand c = heap_pop(&h);
+    const int64_t e = c.end;
+    if (!alive[e] || c.stamp != stamp[e]) continue;  /* stale */
+    if (added + c.cost > cap) break;
+    const int64_t q = group_of(nxt, bsn[s->parent[bptr[e + 1] - 1]]);
+    int64_t *w = (int64_t *)malloc((size_t)(bm[e] + bm[q]) * sizeof(int64_t));
+    int64_t m = merge_union(brows[e], bm[e], brows[q], bm[q], w);
+    free(brows[q]);
+    brows[q] = w; bm[q] = m; gfirst[q] = gfirst[e];
+    alive[e] = 0;
+    nxt[e] = e + 1;
+    added += c.cost;
+    ++stamp[q];
+    push_candidate(&h, s, q, nxt, bptr, bsn, brows, bm, gfirst, stamp, u);
+    if (gfirst[q] > 0) {
+      const int64_t pe = group_of(nxt, bsn[gfirst[q] - 1]);
+      ++stamp[pe];
+      push_candidate(&h, s, pe, nxt, bptr, bsn, brows, bm, gfirst, stamp, u);
+    }
+  }
+  free(h.a); free(stamp); free(nxt); free(u);
+}
+
 static int build_supernodes(osym *s, int mode, int64_t z, int rule, int64_t cap_percent) {
   int64_t n = s->n;
   /* base partition */
@@ -253,40 +360,7 @@ static int build_supernodes(osym *s, int mode, int64_t z, int rule, int64_t cap_
   int64_t *alive = (int64_t *)malloc((size_t)(nb ? nb : 1) * sizeof(int64_t));
   for (int64_t b = 0; b < nb; ++b) { gfirst[b] = bptr[b]; alive[b] = 1; }
   if (rule == 1) {
-    /* Greedy merging (Sec. IV-A): repeatedly merge the pair (group, group
-     * holding its parent column) whose merge adds the least new storage
-     * (explicit zeros), provided the parent group starts right after it;
-     * ties go to the group with the smaller first column; stop before the
-     * cumulative increase would pass cap_percent of nnz(L).  Everything is
-     * recomputed from the row lists at every step. */
-    int64_t nnzl = 0;
-    for (int64_t j = 0; j < n; ++j) nnzl += s->count[j];
-    const int64_t cap = nnzl * cap_percent / 100;
-    int64_t added = 0;
-    int64_t *u = (int64_t *)malloc((size_t)(n ? n : 1) * sizeof(int64_t));
-    for (;;) {
-      int64_t best = -1, bq = -1, bcost = 0;
-      for (int64_t e = 0; e < nb; ++e) {
-        if (!alive[e]) continue;
-        int64_t pc = s->parent[bptr[e + 1] - 1];
-        if (pc < 0) continue;
-        int64_t q = bsn[pc];
-        while (!alive[q]) ++q;  /* groups are intervals ending at their alive base */
-        if (gfirst[q] != bptr[e + 1]) continue;
-        int64_t m = merge_union(brows[e], bm[e], brows[q], bm[q], u);
-        int64_t ke = bptr[e + 1] - gfirst[e], kq = bptr[q + 1] - gfirst[q];
-        int64_t cost = trapezoid(ke + kq, m) - trapezoid(ke, bm[e]) - trapezoid(kq, bm[q]);
-        if (best < 0 || cost < bcost) { best = e; bq = q; bcost = cost; }
-      }
-      if (best < 0 || added + bcost > cap) break;
-      int64_t *w = (int64_t *)malloc((size_t)(bm[best] + bm[bq]) * sizeof(int64_t));
-      int64_t m = merge_union(brows[best], bm[best], brows[bq], bm[bq], w);
-      free(brows[bq]);
-      brows[bq] = w; bm[bq] = m; gfirst[bq] = gfirst[best];
-      alive[best] = 0;
-      added += bcost;
-    }
-    free(u);
+    greedy_merge(s, nb, bptr, bsn, brows, bm, gfirst, alive, cap_percent);
   } else if (z > 0) {
     for (int64_t b = 0; b < nb; ++b) {
       int64_t last = bptr[b + 1] - 1;

@@ -176,6 +176,33 @@ class SparseCholesky:
         _check(capi.lib().spchol_sym_storage(self._h, _hptr(off)))
         return off
 
+    def factor_streamed(self, vals, device_budget=256 << 20, host_threshold=600000, host_threads=0, stream=None,
+                        check=True):
+        """Host-resident factorization (spchol_factor_streamed): vals is a
+        host float64 array; returns (L storage as a host numpy array, info,
+        stats dict).  Supernodes with k * m below host_threshold are done
+        on the host, the others on the device within device_budget bytes."""
+        v = np.ascontiguousarray(vals, dtype=np.float64)
+        if v.size != self.nnz_a:
+            raise ValueError("vals has the wrong length")
+        L = np.empty(max(int(self.info()["storage"]), 1), np.float64)
+        opts = capi.StreamOptions(int(device_budget), int(host_threshold), int(host_threads), 0)
+        st = capi.StreamStats()
+        info = C.c_int64(0)
+        if stream is None:
+            import torch
+            sp = _stream_ptr(None) if torch.cuda.is_available() else C.c_void_p(None)
+        else:
+            sp = _stream_ptr(stream)
+        rc = capi.lib().spchol_factor_streamed(self._h, _hptr(v) if v.size else None, C.byref(opts), sp, _hptr(L),
+                                               C.byref(info), C.byref(st))
+        stats = {name: getattr(st, name) for name, _ in st._fields_ if name != "reserved"}
+        if rc == -3 and check:
+            raise NotPositiveDefinite(rc, capi.lib().spchol_last_error().decode(), int(info.value))
+        if rc != -3:
+            _check(rc)
+        return L[: int(self.info()["storage"])], int(info.value), stats
+
     def factor(self, vals, stream=None, check=True, precision="f64") -> "Factor":
         """Numeric factorization of the values `vals` (float64 CUDA tensor in
         the pattern's entry order).  precision: "f64", "f32" or "bf16" for the

@@ -40,6 +40,15 @@ class LaunchRecord(C.Structure):
 KERNEL_KINDS = ["fill", "scatter_a", "factor", "update_int", "update_ext", "fwd", "bwd", "perm", "logdet",
                 "selinv"]
 
+class StreamOptions(C.Structure):
+    _fields_ = [("device_budget", i64), ("host_threshold", i64), ("host_threads", i32), ("reserved", i32)]
+
+
+class StreamStats(C.Structure):
+    _fields_ = [("gpu_supernodes", i64), ("host_supernodes", i64), ("update_blocks", i64), ("h2d_bytes", i64),
+                ("d2h_bytes", i64), ("device_bytes", i64), ("host_threads", i32), ("reserved", i32)]
+
+
 # name -> (restype, argtypes)
 PROTOTYPES = {
     "spchol_default_options": (i32, [C.POINTER(Options)]),
@@ -63,6 +72,7 @@ PROTOTYPES = {
     "spchol_refine": (i32, [vp, vp, vp, vp, i64, i64, i64, f64, i32, vp, f64p, C.POINTER(i32), C.POINTER(i32)]),
     "spchol_solve": (i32, [vp, vp, i64, i64, vp]),
     "spchol_solve_noalloc": (i32, [vp, vp, i64, i64, vp]),
+    "spchol_factor_streamed": (i32, [vp, vp, C.POINTER(StreamOptions), vp, vp, i64p, C.POINTER(StreamStats)]),
     "spchol_berr": (i32, [vp, vp, vp, vp, i64, i64, i64, vp, f64p]),
     "spchol_logdet": (i32, [vp, f64p, vp]),
     "spchol_num_export": (i32, [vp, vp, vp]),

@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libspchol.so")
 ARCH = os.environ.get("SPCHOL_OFFLOAD_ARCH", "gfx950")
 
 HIP_SOURCES = ["kernels.hip", "runtime.hip"]
-CXX_SOURCES = ["analyze.cpp", "order.cpp"]
+CXX_SOURCES = ["analyze.cpp", "order.cpp", "host_factor.cpp"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
@@ -29,7 +29,7 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
-CXX_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-Wall"]
+CXX_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-Wall", "-pthread"]
 
 
 def _hipcc():
@@ -64,7 +64,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         list(ex.map(lambda c: _run(c, verbose), jobs))
     tmp = LIB + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -648,7 +648,7 @@ static_assert(TILE * G2 * sizeof(s4) <= UKC * ALD * sizeof(double), "bf16 stagin
 
 template <int P, int kind>
 __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict__ L, const DevTask t,
-                                            double* __restrict__ smem) {
+                                            double* __restrict__ smem, double* __restrict__ aux = nullptr) {
   using Pr = UpdPrec<P>;
   using T = typename Pr::T;
   double* __restrict__ Cs = smem;
@@ -721,7 +721,7 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
     const int32_t* R = S.rows + S.rptr[J];
     const int anc = S.snode_of[R[col0]];
     cbase_l = S.loff[anc] + (int64_t)(R[min(col0 + lane, colEnd - 1)] - S.sfirst[anc]) * S.sm[anc];
-  } else if constexpr (kind >= 2) {
+  } else if constexpr (kind == 2 || kind == 3) {
     const int64_t ob = S.obase[J];
     const int lc = min(col0 + lane, colEnd - 1) - k;
     const int pair_l = S.opair[ob + lc];
@@ -786,7 +786,7 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
     // position of the tile's first row, task field c) for all of them
 #pragma unroll
     for (int j = 0; j < TILE / 4; ++j) tpvs[j] = t.c + lane;
-  } else if constexpr (kind >= 2) {
+  } else if constexpr (kind == 2 || kind == 3) {
     const int gr = row0 + lane;
 #pragma unroll
     for (int j = 0; j < TILE / 4; ++j) {
@@ -817,6 +817,16 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
     for (int j = 0; j < TILE / 4; ++j) {
       const int cc = w + 4 * j, gc = col0 + cc;
       if (cc < cmax && gr < m && gr >= gc) Lj[(int64_t)gc * m + gr] = cold[j] - Cs[cc * CLD + lane];
+    }
+  } else if constexpr (kind == 5) {
+    // the update matrix itself, not scattered: rows cb .. m - 1 of its
+    // columns cb .. (a column block, cb = task field c) go to aux,
+    // column-major with leading dimension m - cb, lower part
+    const int cb = t.c;
+#pragma unroll
+    for (int j = 0; j < TILE / 4; ++j) {
+      const int cc = w + 4 * j, gc = col0 + cc;
+      if (cc < cmax && gr < m && gr >= gc) aux[(int64_t)(gr - cb) + (int64_t)(gc - cb) * (m - cb)] = Cs[cc * CLD + lane];
     }
   } else {
     // target of entry (gr, gc): the ancestor column of row gc at storage
@@ -870,9 +880,9 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
 // some apply their scatter, the others keep the matrix cores busy.
 template <int P, int kind>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_update(DevSym S, double* __restrict__ L,
-                                                                                          int64_t off) {
+                                                                                          int64_t off, double* aux) {
   __shared__ __attribute__((aligned(16))) double smem[UPD_SMEM];
-  update_body<P, kind>(S, L, S.tasks[off + blockIdx.x], smem);
+  update_body<P, kind>(S, L, S.tasks[off + blockIdx.x], smem, aux);
 }
 
 // One-panel lookahead: workgroups below nfirst factor panel p (panel_body),
@@ -2100,25 +2110,31 @@ hipError_t launch_factor_la(const DevSym& S, double* L, int64_t off, int32_t nfi
   return hipGetLastError();
 }
 
+hipError_t launch_update_dense(const DevSym& S, double* L, int64_t off, int32_t ntasks, double* U, hipStream_t st) {
+  if (ntasks <= 0) return hipSuccess;
+  k_update<0, 5><<<ntasks, 256, 0, st>>>(S, L, off, U);
+  return hipGetLastError();
+}
+
 hipError_t launch_update(const DevSym& S, double* L, int32_t kind, int64_t off, int32_t ntasks,
                          int32_t prec, hipStream_t st) {
   if (ntasks <= 0) return hipSuccess;
   if (kind == 1) {
-    if (prec == 2) k_update<2, 1><<<ntasks, 256, 0, st>>>(S, L, off);
-    else if (prec == 1) k_update<1, 1><<<ntasks, 256, 0, st>>>(S, L, off);
-    else k_update<0, 1><<<ntasks, 256, 0, st>>>(S, L, off);
+    if (prec == 2) k_update<2, 1><<<ntasks, 256, 0, st>>>(S, L, off, nullptr);
+    else if (prec == 1) k_update<1, 1><<<ntasks, 256, 0, st>>>(S, L, off, nullptr);
+    else k_update<0, 1><<<ntasks, 256, 0, st>>>(S, L, off, nullptr);
   } else if (kind == 4) {
-    if (prec == 2) k_update<2, 4><<<ntasks, 256, 0, st>>>(S, L, off);
-    else if (prec == 1) k_update<1, 4><<<ntasks, 256, 0, st>>>(S, L, off);
-    else k_update<0, 4><<<ntasks, 256, 0, st>>>(S, L, off);
+    if (prec == 2) k_update<2, 4><<<ntasks, 256, 0, st>>>(S, L, off, nullptr);
+    else if (prec == 1) k_update<1, 4><<<ntasks, 256, 0, st>>>(S, L, off, nullptr);
+    else k_update<0, 4><<<ntasks, 256, 0, st>>>(S, L, off, nullptr);
   } else if (kind == 3) {
-    if (prec == 2) k_update<2, 3><<<ntasks, 256, 0, st>>>(S, L, off);
-    else if (prec == 1) k_update<1, 3><<<ntasks, 256, 0, st>>>(S, L, off);
-    else k_update<0, 3><<<ntasks, 256, 0, st>>>(S, L, off);
+    if (prec == 2) k_update<2, 3><<<ntasks, 256, 0, st>>>(S, L, off, nullptr);
+    else if (prec == 1) k_update<1, 3><<<ntasks, 256, 0, st>>>(S, L, off, nullptr);
+    else k_update<0, 3><<<ntasks, 256, 0, st>>>(S, L, off, nullptr);
   } else {
-    if (prec == 2) k_update<2, 2><<<ntasks, 256, 0, st>>>(S, L, off);
-    else if (prec == 1) k_update<1, 2><<<ntasks, 256, 0, st>>>(S, L, off);
-    else k_update<0, 2><<<ntasks, 256, 0, st>>>(S, L, off);
+    if (prec == 2) k_update<2, 2><<<ntasks, 256, 0, st>>>(S, L, off, nullptr);
+    else if (prec == 1) k_update<1, 2><<<ntasks, 256, 0, st>>>(S, L, off, nullptr);
+    else k_update<0, 2><<<ntasks, 256, 0, st>>>(S, L, off, nullptr);
   }
   return hipGetLastError();
 }

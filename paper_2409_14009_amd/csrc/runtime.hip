@@ -9,10 +9,12 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/spchol.h"
 #include "analyze.hpp"
+#include "host_factor.hpp"
 #include "order.hpp"
 #include "device.hpp"
 
@@ -314,6 +316,29 @@ struct spchol_num_s {
   }
 };
 
+// The handle's second stream.  The external updates it runs fill every
+// compute unit, and the panel chain's launches on the caller's stream (few
+// workgroups each, on the critical path) would then wait for free slots: the
+// second stream is restricted to all but `reserve` compute units, spread
+// evenly over the device (a CU mask, not a priority), which stay free for
+// the chain.  SPCHOL_SIDE_CU_RESERVE overrides the count (0: no mask).
+constexpr int kSideReserveDefault = 0;
+
+static hipError_t create_side_stream(hipStream_t* out) {
+  int reserve = kSideReserveDefault;
+  if (const char* ev = std::getenv("SPCHOL_SIDE_CU_RESERVE")) reserve = std::atoi(ev);
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if (reserve <= 0 || reserve >= cus) return hipStreamCreateWithFlags(out, hipStreamNonBlocking);
+  std::vector<uint32_t> mask((cus + 31) / 32, 0u);
+  const int stride = cus / reserve;
+  for (int i = 0; i < cus; ++i)
+    if (i % stride != stride - 1 || i / stride >= reserve) mask[i / 32] |= 1u << (i % 32);
+  return hipExtStreamCreateWithCUMask(out, (uint32_t)mask.size(), mask.data());
+}
+
 // Run `launch` (returning hipError_t), bracketed by events when profiling;
 // level / side: the launch's level in the schedule (-1: outside it) and
 // whether it runs on the second stream.
@@ -385,7 +410,7 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
                 [&] { return launch_scatter_values(D, vals, N->L, st); }));
   if (!N->side) {
     // created before any capture (stream and event creation is not captured)
-    HIP_TRY(hipStreamCreateWithFlags(&N->side, hipStreamNonBlocking));
+    HIP_TRY(create_side_stream(&N->side));
     HIP_TRY(hipEventCreateWithFlags(&N->fork_ev, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&N->join_ev, hipEventDisableTiming));
     N->side_ev.assign(S.nlevels + 1, nullptr);
@@ -848,7 +873,7 @@ spchol_status spchol_factor_prec(spchol_sym sym, const double* vals_dev, int32_t
   if (e == hipSuccess) e = hipMalloc((void**)&N->red, (size_t)(logdet_partials(sym->S.n) + 1) * sizeof(double));
   if (e == hipSuccess)
     e = hipMalloc((void**)&N->winv, (size_t)(sym->S.wbase[sym->S.ns] > 0 ? sym->S.wbase[sym->S.ns] : 1) * sizeof(double));
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&N->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = create_side_stream(&N->side);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&N->fork_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&N->join_ev, hipEventDisableTiming);
   if (e == hipSuccess) {
@@ -864,6 +889,51 @@ spchol_status spchol_factor_prec(spchol_sym sym, const double* vals_dev, int32_t
   N->prec = update_precision;
   *out = N;
   return run_factor(N, vals_dev, (hipStream_t)stream, info);
+}
+
+// ---------------------------------------------------------------------------
+// Host-resident factorization (the paper's architecture, Sec. III): the
+// factor lives in caller-owned host memory; supernodes with k m below the
+// threshold are factored and applied on the host; each other supernode is
+// copied to the device, factored there by its panel rounds (the same
+// kernels), copied back, and its update matrix is computed on the device in
+// column blocks that fit the device budget, each copied back and added into
+// the ancestors by the host.  Device memory: one supernode, its inverted
+// diagonal blocks, one update block and the task lists (plus the analysis'
+// device copy).
+// ---------------------------------------------------------------------------
+
+// Task lists of one supernode's numeric step on the device: per panel a
+// diagonal task, the row tiles of the triangular solve and the trailing
+// internal update tiles; then the update matrix's tiles by column block.
+static void stream_plan(const Symbolic& S, int64_t J, int64_t wc, std::vector<DevTask>& tasks,
+                        std::vector<std::pair<int32_t, std::pair<int64_t, int32_t>>>& launches) {
+  const int64_t nb = S.nb, k = S.sptr[J + 1] - S.sptr[J], m = S.rptr[J + 1] - S.rptr[J];
+  auto open = [&](int32_t kind) { launches.push_back({kind, {(int64_t)tasks.size(), 0}}); };
+  auto close = [&] {
+    auto& l = launches.back();
+    l.second.second = (int32_t)((int64_t)tasks.size() - l.second.first);
+    if (l.second.second == 0) launches.pop_back();
+  };
+  for (int64_t p = 0; p * nb < k; ++p) {
+    const int64_t kp = std::min<int64_t>(nb, k - p * nb);
+    open(K_FACTOR);
+    tasks.push_back({(int32_t)J, (int32_t)p, (int32_t)m, 0});
+    close();
+    open(K_TRSM);
+    for (int64_t r0 = p * nb + kp; r0 < m; r0 += kTile) tasks.push_back({(int32_t)J, (int32_t)p, (int32_t)r0, 0});
+    close();
+    open(K_UPD_INT);
+    for (int64_t c0 = (p + 1) * nb; c0 < k; c0 += kTile)
+      for (int64_t r0 = c0; r0 < m; r0 += kTile) tasks.push_back({(int32_t)J, (int32_t)r0, (int32_t)c0, (int32_t)p});
+    close();
+  }
+  for (int64_t cb = k; cb < m; cb += wc) {
+    open(-1);  // dense update block
+    for (int64_t c0 = cb; c0 < std::min<int64_t>(cb + wc, m); c0 += kTile)
+      for (int64_t r0 = c0; r0 < m; r0 += kTile) tasks.push_back({(int32_t)J, (int32_t)r0, (int32_t)c0, (int32_t)cb});
+    close();
+  }
 }
 
 spchol_status spchol_refactor(spchol_num num, const double* vals_dev, void* stream, int64_t* info) {
@@ -882,6 +952,157 @@ spchol_status spchol_refactor_prec(spchol_num num, const double* vals_dev, int32
   spchol_status s = num->sym->ensure_device();
   if (s) return s;
   return run_factor(num, vals_dev, (hipStream_t)stream, info);
+}
+
+spchol_status spchol_factor_streamed(spchol_sym sym, const double* vals_host, const spchol_stream_options* opt,
+                                     void* stream, double* L_host, int64_t* info, spchol_stream_stats* stats) {
+  if (!sym || !L_host || (!vals_host && sym->S.nnzA > 0)) return fail(SPCHOL_ERR_ARG, "null argument");
+  spchol_stream_options o{};
+  o.device_budget = int64_t(256) << 20;
+  o.host_threshold = 600000;
+  if (opt) o = *opt;
+  if (o.device_budget <= 0) o.device_budget = int64_t(256) << 20;
+  if (o.host_threshold < 0) return fail(SPCHOL_ERR_ARG, "host_threshold < 0");
+  int threads = o.host_threads > 0 ? o.host_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+  const Symbolic& S = sym->S;
+  const int64_t nb = S.nb;
+  if (info) *info = 0;
+  spchol_stream_stats st{};
+  auto on_gpu = [&](int64_t J) {
+    const int64_t k = S.sptr[J + 1] - S.sptr[J], m = S.rptr[J + 1] - S.rptr[J];
+    return k * m >= o.host_threshold;
+  };
+  // device buffers: the largest GPU supernode, its inverse blocks, an
+  // update block of at least 64 columns, status
+  int64_t maxst = 0, maxw = 0, maxr = 0;
+  for (int64_t J = 0; J < S.ns; ++J) {
+    if (!on_gpu(J)) continue;
+    const int64_t k = S.sptr[J + 1] - S.sptr[J], m = S.rptr[J + 1] - S.rptr[J];
+    maxst = std::max(maxst, k * m);
+    maxw = std::max(maxw, S.wbase[J + 1] - S.wbase[J]);
+    maxr = std::max(maxr, m - k);
+  }
+  const bool any_gpu = maxst > 0;
+  const int64_t fixed = 8 * (maxst + maxw) + 8;
+  const int64_t ubytes = o.device_budget - fixed;
+  if (any_gpu && (ubytes < 8 * maxr * std::min<int64_t>(kTile, std::max<int64_t>(maxr, 1))))
+    return fail(SPCHOL_ERR_OOM, "device budget of " + std::to_string(o.device_budget) +
+                                    " bytes holds no supernode with one update block (needs " +
+                                    std::to_string(fixed + 8 * maxr * kTile) + ")");
+  try {
+    host_scatter_values(S, vals_host, L_host);
+    int64_t fail_col = -1;
+    hipStream_t hs = (hipStream_t)stream;
+    // device buffers of the call, freed on every way out
+    struct Bufs {
+      double *L = nullptr, *W = nullptr, *U = nullptr;
+      unsigned long long* status = nullptr;
+      DevTask* tasks = nullptr;
+      ~Bufs() {
+        for (void* q : {(void*)L, (void*)W, (void*)U, (void*)status, (void*)tasks})
+          if (q) (void)hipFree(q);
+      }
+    } bufs;
+    double *&dL = bufs.L, *&dW = bufs.W, *&dU = bufs.U;
+    unsigned long long*& dstatus = bufs.status;
+    DevTask*& dtasks = bufs.tasks;
+    spchol_status status = SPCHOL_OK;
+    DevSym D{};
+    std::vector<double> hU;
+    if (any_gpu) {
+      spchol_status s = sym->ensure_device();
+      if (s) return s;
+      D = sym->dev;
+      // the update block: as many 64-column groups as the budget holds
+      // for the tallest supernode
+      const int64_t wc_all = std::max<int64_t>(kTile, (ubytes / 8 / std::max<int64_t>(maxr, 1)) / kTile * kTile);
+      HIP_TRY(hipMalloc((void**)&dL, (size_t)maxst * 8));
+      HIP_TRY(hipMalloc((void**)&dW, (size_t)std::max<int64_t>(maxw, 1) * 8));
+      HIP_TRY(hipMalloc((void**)&dU, (size_t)std::max<int64_t>(maxr * std::min(wc_all, maxr), 1) * 8));
+      HIP_TRY(hipMalloc((void**)&dstatus, sizeof(unsigned long long)));
+      st.device_bytes = 8 * (maxst + std::max<int64_t>(maxw, 1) + maxr * std::min(wc_all, maxr)) + 8;
+      HIP_TRY(launch_status_init(dstatus, hs));
+      hU.resize((size_t)(maxr * std::min(wc_all, maxr)));
+      std::vector<DevTask> tasks;
+      std::vector<std::pair<int32_t, std::pair<int64_t, int32_t>>> launches;
+      std::vector<int64_t> wcol(S.ns, kTile);  // update block width (columns) per supernode
+      std::vector<std::vector<std::pair<int32_t, std::pair<int64_t, int32_t>>>> plan(S.ns);
+      for (int64_t J = 0; J < S.ns; ++J) {
+        if (!on_gpu(J)) continue;
+        const int64_t k = S.sptr[J + 1] - S.sptr[J], m = S.rptr[J + 1] - S.rptr[J];
+        const int64_t r = m - k;
+        wcol[J] = std::max<int64_t>(kTile, r > 0 ? std::min(wc_all, (r + kTile - 1) / kTile * kTile) : kTile);
+        stream_plan(S, J, wcol[J], tasks, plan[J]);
+      }
+      HIP_TRY(hipMalloc((void**)&dtasks, std::max<size_t>(tasks.size(), 1) * sizeof(DevTask)));
+      HIP_TRY(hipMemcpy(dtasks, tasks.data(), tasks.size() * sizeof(DevTask), hipMemcpyHostToDevice));
+      st.device_bytes += (int64_t)(std::max<size_t>(tasks.size(), 1) * sizeof(DevTask));
+      D.tasks = dtasks;
+      for (int64_t J = 0; J < S.ns; ++J) {
+        const int64_t k = S.sptr[J + 1] - S.sptr[J], m = S.rptr[J + 1] - S.rptr[J];
+        if (!on_gpu(J)) {
+          const int64_t f = host_factor_supernode(S, J, L_host);
+          if (f >= 0 && (fail_col < 0 || f < fail_col)) fail_col = f;
+          host_update_supernode(S, J, L_host, threads);
+          st.host_supernodes += 1;
+          continue;
+        }
+        // the supernode to the device (its updates from descendants are in)
+        double* base = dL - S.loff[J];  // kernels address L + loff[J] + ...
+        double* wb = dW - S.wbase[J];
+        HIP_TRY(hipMemcpyAsync(dL, L_host + S.loff[J], (size_t)(k * m) * 8, hipMemcpyHostToDevice, hs));
+        st.h2d_bytes += 8 * k * m;
+        for (const auto& l : plan[J]) {
+          const int32_t kind = l.first;
+          const int64_t off = l.second.first;
+          const int32_t nt = l.second.second;
+          if (kind == K_FACTOR || kind == K_TRSM) {
+            HIP_TRY(launch_factor_panel(D, base, off, nt, dstatus, wb, kind == K_FACTOR, hs));
+          } else if (kind == K_UPD_INT) {
+            HIP_TRY(launch_update(D, base, 1, off, nt, 0, hs));
+          } else {
+            // an update column block: compute, copy back, add on the host
+            const int64_t cb = tasks[off].c;
+            const int64_t ce = std::min<int64_t>(m, cb + wcol[J]);
+            const int64_t ldu = m - cb;
+            HIP_TRY(launch_update_dense(D, base, off, nt, dU, hs));
+            HIP_TRY(hipMemcpyAsync(hU.data(), dU, (size_t)(ldu * (ce - cb)) * 8, hipMemcpyDeviceToHost, hs));
+            HIP_TRY(hipStreamSynchronize(hs));
+            st.d2h_bytes += 8 * ldu * (ce - cb);
+            host_assemble_block(S, J, cb, ce, hU.data(), L_host, threads);
+            st.update_blocks += 1;
+          }
+        }
+        // the factored supernode back to the host
+        HIP_TRY(hipMemcpyAsync(L_host + S.loff[J], dL, (size_t)(k * m) * 8, hipMemcpyDeviceToHost, hs));
+        HIP_TRY(hipStreamSynchronize(hs));
+        st.d2h_bytes += 8 * k * m;
+        st.gpu_supernodes += 1;
+      }
+      unsigned long long hstat = ~0ULL;
+      HIP_TRY(hipMemcpy(&hstat, dstatus, sizeof(hstat), hipMemcpyDeviceToHost));
+      if (hstat != ~0ULL && (fail_col < 0 || (int64_t)hstat < fail_col)) fail_col = (int64_t)hstat;
+    } else {
+      // every supernode below the threshold: no device work at all
+      for (int64_t J = 0; J < S.ns; ++J) {
+        const int64_t f = host_factor_supernode(S, J, L_host);
+        if (f >= 0 && (fail_col < 0 || f < fail_col)) fail_col = f;
+        host_update_supernode(S, J, L_host, threads);
+        st.host_supernodes += 1;
+      }
+    }
+    st.host_threads = threads;
+    if (stats) *stats = st;
+    if (fail_col >= 0) {
+      if (info) *info = fail_col + 1;
+      return fail(SPCHOL_ERR_NOT_SPD, "matrix is not positive definite at permuted column " + std::to_string(fail_col + 1));
+    }
+    (void)nb;
+    (void)status;
+    return SPCHOL_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(SPCHOL_ERR_OOM, "out of host memory");
+  }
 }
 
 spchol_status spchol_solve(spchol_num num, double* B_dev, int64_t nrhs, int64_t ldb, void* stream) {

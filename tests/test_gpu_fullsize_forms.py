@@ -153,8 +153,10 @@ def test_batch_512_every_matrix():
 def grf():
     p = gen.make_config(4)
     print(f"48^3 random field: n={p.n} nnz_lower={p.colptr[-1]}", flush=True)
-    S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, 0, p.meta["amalg_z"])
-    osym = oracle.Symbolic(p.n, p.colptr, p.rowind, p.perm, 0, p.meta["amalg_z"])
+    rule = dict(amalg_rule=p.meta["amalg_rule"], amalg_cap_percent=p.meta["amalg_cap_percent"])
+    S = sc.SparseCholesky(p.n, p.colptr, p.rowind, p.perm, 0, p.meta["amalg_z"], **rule)
+    osym = oracle.Symbolic(p.n, p.colptr, p.rowind, p.perm, 0, p.meta["amalg_z"], **rule)
+    assert S.info()["nsuper"] == osym.nsuper
     of = osym.factor(p.vals)
     assert of.info == 0
     return p, S, of
