@@ -316,29 +316,6 @@ struct spchol_num_s {
   }
 };
 
-// The handle's second stream.  The external updates it runs fill every
-// compute unit, and the panel chain's launches on the caller's stream (few
-// workgroups each, on the critical path) would then wait for free slots: the
-// second stream is restricted to all but `reserve` compute units, spread
-// evenly over the device (a CU mask, not a priority), which stay free for
-// the chain.  SPCHOL_SIDE_CU_RESERVE overrides the count (0: no mask).
-constexpr int kSideReserveDefault = 0;
-
-static hipError_t create_side_stream(hipStream_t* out) {
-  int reserve = kSideReserveDefault;
-  if (const char* ev = std::getenv("SPCHOL_SIDE_CU_RESERVE")) reserve = std::atoi(ev);
-  int dev = 0, cus = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) return e;
-  if (reserve <= 0 || reserve >= cus) return hipStreamCreateWithFlags(out, hipStreamNonBlocking);
-  std::vector<uint32_t> mask((cus + 31) / 32, 0u);
-  const int stride = cus / reserve;
-  for (int i = 0; i < cus; ++i)
-    if (i % stride != stride - 1 || i / stride >= reserve) mask[i / 32] |= 1u << (i % 32);
-  return hipExtStreamCreateWithCUMask(out, (uint32_t)mask.size(), mask.data());
-}
-
 // Run `launch` (returning hipError_t), bracketed by events when profiling;
 // level / side: the launch's level in the schedule (-1: outside it) and
 // whether it runs on the second stream.
@@ -410,7 +387,7 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
                 [&] { return launch_scatter_values(D, vals, N->L, st); }));
   if (!N->side) {
     // created before any capture (stream and event creation is not captured)
-    HIP_TRY(create_side_stream(&N->side));
+    HIP_TRY(hipStreamCreateWithFlags(&N->side, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&N->fork_ev, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&N->join_ev, hipEventDisableTiming));
     N->side_ev.assign(S.nlevels + 1, nullptr);
@@ -873,7 +850,7 @@ spchol_status spchol_factor_prec(spchol_sym sym, const double* vals_dev, int32_t
   if (e == hipSuccess) e = hipMalloc((void**)&N->red, (size_t)(logdet_partials(sym->S.n) + 1) * sizeof(double));
   if (e == hipSuccess)
     e = hipMalloc((void**)&N->winv, (size_t)(sym->S.wbase[sym->S.ns] > 0 ? sym->S.wbase[sym->S.ns] : 1) * sizeof(double));
-  if (e == hipSuccess) e = create_side_stream(&N->side);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&N->side, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&N->fork_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&N->join_ev, hipEventDisableTiming);
   if (e == hipSuccess) {
