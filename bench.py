@@ -55,8 +55,8 @@ PEAK_HBM_GBS = 8000.0
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, scales from a plain 1 GiB copy;
 # profiles/update_ext_grid3d_64.md), valid for the kernel source they were
 # taken with: reported only while the source hash matches.
-MEASURED_TRAFFIC = {"kernel": "update_ext", "bytes_per_launch": 450642681,
-                    "kernels_sha256_16": "7f2a4de120d7d8fa"}
+MEASURED_TRAFFIC = {"kernel": "update_ext", "bytes_per_launch": 450875051,
+                    "update_source_sha256_16": "915276b325a67ec0"}
 
 
 def log(msg):
@@ -91,14 +91,26 @@ def cpu_baseline(p, z, ncols=65536):
                        f"{dt:.1f} s on 1 thread of {_host_cores()} host cores")
 
 
+UPDATE_REGION = ("// update: C[i, c] -= sum_t", "// One-panel lookahead")
+
+
+def update_source_sha(text):
+    """sha256[:16] of the update kernel's source (from its header comment to
+    the next kernel), or None when the anchors are missing."""
+    import hashlib
+    a, b = text.find(UPDATE_REGION[0]), text.find(UPDATE_REGION[1])
+    if a < 0 or b < a:
+        return None
+    return hashlib.sha256(text[a:b].encode()).hexdigest()[:16]
+
+
 def measured_traffic(kernel):
     """Counter-measured HBM bytes per launch of `kernel`, or None when the
-    kernels changed since the counters were taken."""
-    import hashlib
-    with open(os.path.join(ROOT, "paper_2409_14009_amd", "csrc", "kernels.hip"), "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    kernel's source changed since the counters were taken."""
+    with open(os.path.join(ROOT, "paper_2409_14009_amd", "csrc", "kernels.hip")) as f:
+        sha = update_source_sha(f.read())
     t = MEASURED_TRAFFIC
-    if kernel != t["kernel"] or sha != t["kernels_sha256_16"]:
+    if kernel != t["kernel"] or sha is None or sha != t["update_source_sha256_16"]:
         return None
     return t["bytes_per_launch"]
 
