@@ -110,6 +110,31 @@ def test_dense(n):
              0, 0, 64)
 
 
+@pytest.mark.parametrize("n,nb", [(150, 64), (150, 32), (300, 48)])
+def test_dense_odd_panels(n, nb):
+    """One supernode whose panel count is odd: the backward rounds take the
+    panels in pairs, the first round (the last panel) alone."""
+    rng = np.random.default_rng(n + nb)
+    G = rng.standard_normal((n, n))
+    M = G @ G.T / n + np.eye(n)
+    Ls = sp.csc_matrix(np.tril(M))
+    Ls.sort_indices()
+    B = rng.standard_normal((n, 5))
+    run_case(n, Ls.indptr.astype(np.int64), Ls.indices.astype(np.int64), Ls.data, rng.permutation(n), B,
+             0, 0, nb)
+
+
+@pytest.mark.parametrize("side,nb,nrhs", [(14, 16, 1), (16, 48, 6), (14, 32, 9)])
+def test_backward_pair_rounds(side, nb, nrhs):
+    """Separators of many panels with hundreds of rows below them: two-panel
+    backward tasks with the coupling block, split into far row tiles a round
+    ahead and a finishing task, odd panel counts, several blocks of four
+    right-hand sides."""
+    p = gen.make_config(2, side=side)
+    B = np.random.default_rng(side * nb + nrhs).standard_normal((p.n, nrhs))
+    run_case(p.n, p.colptr, p.rowind, p.vals, p.perm, B, 0, 8, nb)
+
+
 @pytest.mark.parametrize("cfg,side", [(1, 16), (2, 7), (4, 16)])
 def test_reduced_configs(cfg, side):
     """The 3D recipes on smaller grids: multi-panel separators, amalgamation."""
