@@ -576,19 +576,6 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
                   ((t.c & 1) ? 8.0 * double(kp * (kp + 1) / 2 + kp1 * (kp1 + 1) / 2 + kp1 * kp) : 0.0);
             break;
           }
-        case K_BWD2: {  // (two-panel tasks; single-panel ones are costed as K_BWD)
-          // the rows the task covers in both panels' columns; a finishing
-          // task also the coupling block and both inverted diagonal blocks
-          const int64_t kp = std::min<int64_t>(nb, k - int64_t(t.a) * nb);
-          const int64_t kp1 = std::min<int64_t>(nb, k - int64_t(t.a) * nb - kp);
-          const int64_t nr = t.c < 0 ? m - t.b : (t.c == 0 ? std::min<int64_t>(t.b + kTile, m) - t.b : int64_t(t.c) - 1);
-          const bool once = t.c != 0;
-          fl += 2.0 * double(nr) * double(kp + kp1) +
-                (once ? double(kp) * double(kp) + 2.0 * double(kp1) * double(kp) + double(kp1) * double(kp1) : 0.0);
-          by += 8.0 * double(nr) * double(kp + kp1) + 16.0 * double(nr) +
-                (once ? 8.0 * double(kp * (kp + 1) / 2 + kp1 * (kp1 + 1) / 2 + kp1 * kp) : 0.0);
-          break;
-        }
         case K_FWD_SMALL:
         case K_BWD_SMALL: {
           const int64_t nr = m - k;
@@ -626,8 +613,6 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
         int32_t kind = L.kind == K_FACTOR_LA ? (q - L.off < L.nfirst ? K_FACTOR : K_UPD_INT) : L.kind;
         // a single-panel task of a two-panel forward round does what a K_FWD task does
         if (kind == K_FWD2 && !(S.tasks[q].c & 2)) kind = K_FWD;
-        // likewise a pair of a two-panel backward round that has one panel
-        if (kind == K_BWD2 && (int64_t(S.tasks[q].a) + 1) * nb >= K(S.tasks[q].J)) kind = K_BWD;
         cost(kind, S.tasks[q], L.flops, L.bytes);
       }
     };
@@ -818,61 +803,45 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       }
     }
     // backward solve: root to leaves, panels descending, one launch per
-    // round of two panels (a task finishes panel p + 1, then panel p with
-    // the coupling block; a supernode whose last panel is p single-panel
-    // tasks; rounds of single panels only are K_BWD launches).  A pair with
-    // at most kBwdRows rows below is done by one task (c = -1: gather, then
-    // the inverted diagonal blocks).  A taller one is split with a one-pair
-    // lookahead: its far rows (past the next pair, whose solution is final
-    // one round earlier) are added into an accumulator by 64-row tiles
-    // (c = 0) in the launch of the round before, and its finishing task
-    // (c = 1 + n) gathers the n rows of the next pair, subtracts the
-    // accumulator and applies the inverses.  The far tiles of a level's
-    // first round run in a launch of their own.  Task field a is the pair's
-    // first panel.
+    // round.  A panel with at most kBwdRows rows below is done by one task
+    // (c = -1: gather, then the inverted diagonal block).  A taller one is
+    // split with a one-panel lookahead: its far rows (past the next panel,
+    // whose solution is final one round earlier) are added into an
+    // accumulator by 64-row tiles (c = 0) in the launch of the round before,
+    // and its finishing task (c = 1 + n) gathers the n rows of the next
+    // panel, subtracts the accumulator and applies the inverse.  The far
+    // tiles of a level's first round run in a launch of their own.
     for (int64_t l = S.nlevels - 1; l >= 0; --l) {
       small_launch(S.bwd_plan, K_BWD_SMALL, l);
-      auto npair = [&](int32_t J) { return (npan(J) + 1) / 2; };
-      int64_t maxq = 0;
-      for (int32_t J : rest[l]) maxq = std::max(maxq, npair(J));
-      // first row below pair q
-      auto below = [&](int32_t J, int64_t q) {
-        const int64_t p1 = std::min(2 * q + 1, npan(J) - 1);
-        return p1 * nb + kpan(J, p1);
-      };
+      int64_t maxp = 0;
+      for (int32_t J : rest[l]) maxp = std::max(maxp, npan(J));
+      auto below = [&](int32_t J, int64_t p) { return p * nb + kpan(J, p); };
       // (deterministic: never split, the accumulator would take several adds per entry)
-      auto split = [&](int32_t J, int64_t q) {
-        return !S.deterministic && q >= 0 && q < npair(J) && M(J) - below(J, q) > kBwdRows;
+      auto split = [&](int32_t J, int64_t p) {
+        return !S.deterministic && p >= 0 && p < npan(J) && M(J) - below(J, p) > kBwdRows;
       };
-      auto near = [&](int32_t J, int64_t q) { return q + 1 < npair(J) ? below(J, q + 1) - below(J, q) : int64_t(0); };
-      auto far_tiles = [&](int32_t J, int64_t q) {
-        for (int64_t r0 = below(J, q) + near(J, q); r0 < M(J); r0 += kTile)
-          S.tasks.push_back({J, (int32_t)(2 * q), (int32_t)r0, 0});
-      };
-      auto kind_of = [&](int64_t q) {
-        for (int32_t J : rest[l])
-          if (npan(J) > 2 * q + 1) return K_BWD2;
-        return K_BWD;
+      auto near = [&](int32_t J, int64_t p) { return p + 1 < npan(J) ? kpan(J, p + 1) : int64_t(0); };
+      auto far_tiles = [&](int32_t J, int64_t p) {
+        for (int64_t r0 = below(J, p) + near(J, p); r0 < M(J); r0 += kTile)
+          S.tasks.push_back({J, (int32_t)p, (int32_t)r0, 0});
       };
       bool pro = false;
-      for (int32_t J : rest[l]) pro = pro || split(J, maxq - 1);
+      for (int32_t J : rest[l]) pro = pro || split(J, maxp - 1);
       if (pro) {
-        open(S.bwd_plan, kind_of(maxq - 1), (int32_t)l, (int32_t)(2 * maxq));
+        open(S.bwd_plan, K_BWD, (int32_t)l, (int32_t)maxp);
         for (int32_t J : rest[l])
-          if (split(J, maxq - 1)) far_tiles(J, maxq - 1);
+          if (split(J, maxp - 1)) far_tiles(J, maxp - 1);
         close(S.bwd_plan);
       }
-      for (int64_t q = maxq - 1; q >= 0; --q) {
-        // (a K_BWD2 launch's far tiles of pair q - 1 may be two-panel ones)
-        const int32_t kd = kind_of(q) == K_BWD2 || (q > 0 && kind_of(q - 1) == K_BWD2) ? K_BWD2 : K_BWD;
-        open(S.bwd_plan, kd, (int32_t)l, (int32_t)(2 * q));
+      for (int64_t p = maxp - 1; p >= 0; --p) {
+        open(S.bwd_plan, K_BWD, (int32_t)l, (int32_t)p);
         for (int32_t J : rest[l]) {
-          if (npair(J) <= q) continue;
-          if (split(J, q)) S.tasks.push_back({J, (int32_t)(2 * q), (int32_t)below(J, q), (int32_t)(1 + near(J, q))});
-          else S.tasks.push_back({J, (int32_t)(2 * q), (int32_t)below(J, q), -1});
+          if (npan(J) <= p) continue;
+          if (split(J, p)) S.tasks.push_back({J, (int32_t)p, (int32_t)below(J, p), (int32_t)(1 + near(J, p))});
+          else S.tasks.push_back({J, (int32_t)p, (int32_t)below(J, p), -1});
         }
         for (int32_t J : rest[l])
-          if (split(J, q - 1)) far_tiles(J, q - 1);
+          if (split(J, p - 1)) far_tiles(J, p - 1);
         close(S.bwd_plan);
       }
     }

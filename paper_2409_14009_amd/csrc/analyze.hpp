@@ -59,7 +59,6 @@ enum Kind : int32_t {
   K_FWD_SMALL = 15,  // forward solve of small one-panel supernodes, one wavefront each
   K_BWD_SMALL = 16,  // backward solve of the same
   K_UPD_RLB = 17,    // external update by block pairs (RLB)
-  K_BWD2 = 18,       // backward solve round with two-panel tasks
 };
 
 // Supernodes done by one wavefront (K_SMALL): at most 16 columns, and with

@@ -1526,127 +1526,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
   for (int64_t cb = 4; cb < nrhs; cb += 4) block(cb);
 }
 
-// Backward round over a pair of panels p0 = t.a and p1 = p0 + 1 (p1 = p0
-// when the supernode has no panel after p0), the fields otherwise as in
-// k_bwd with "the pair" for "the panel": c = -1 gathers all rows below the
-// pair, c = 0 adds one 64-row tile's share into acc of both panels (a round
-// ahead), c = 1 + n gathers the n rows from rb, then subtracts acc.  A
-// finishing task completes p1 first, x_p1 = W_p1^T (x_p1 - gathered), then
-// p0, whose gather also takes the coupling block (the rows of panel p1 in
-// the columns of p0) with the x_p1 just formed:
-// x_p0 = W_p0^T (x_p0 - gathered - L_{p1,p0}^T x_p1).  A wide supernode
-// takes half the rounds of one panel per round.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_bwd2(DevSym S, const double* __restrict__ L, const double* __restrict__ winv,
-                                              int64_t off, double* __restrict__ x, double* __restrict__ acc,
-                                              int64_t nrhs) {
-  __shared__ double Ls[TILE][NBMAX + 1];
-  __shared__ double xs[4][TILE];
-  __shared__ double red[4][4][NBMAX];
-  __shared__ double vs[4][NBMAX];
-  const DevTask t = S.tasks[off + blockIdx.x];
-  const int J = t.J, nb = S.nb, rb = t.b;
-  const bool fin = t.c != 0, useacc = t.c > 0;
-  const int m = S.sm[J], k = S.sk[J];
-  const int p0 = t.a, cA = p0 * nb;
-  const bool two = cA + nb < k;  // panel p1 = p0 + 1 exists
-  const int kp0 = min(nb, k - cA), kp1 = two ? min(nb, k - cA - nb) : 0;
-  const double* __restrict__ Lj = L + S.loff[J];
-  const int32_t* __restrict__ R = S.rows + S.rptr[J];
-  const int64_t fcol = S.sfirst[J] + cA;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int re = t.c < 0 ? m : (t.c == 0 ? min(m, rb + TILE) : rb + t.c - 1);
-  // a finishing task loads the inverse blocks at the start (thread tid
-  // holds entries u * 256 + tid, column-major; replaced past kp when staged)
-  double wv0[NBMAX * NBMAX / 256], wv1[NBMAX * NBMAX / 256];
-  if (fin) {
-    const double* __restrict__ W0 = winv + S.wbase[J] + (int64_t)p0 * nb * nb;
-#pragma unroll
-    for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
-      const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;
-      wv0[u] = W0[min(c, kp0 - 1) * kp0 + min(r, kp0 - 1)];
-    }
-    if (two) {
-      const double* __restrict__ W1 = W0 + (int64_t)nb * nb;
-#pragma unroll
-      for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
-        const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;
-        wv1[u] = W1[min(c, kp1 - 1) * kp1 + min(r, kp1 - 1)];
-      }
-    }
-  }
-  // adds to a[q] the sums over local rows [r0, r1) of L[r, cb0 + lane] x(r, q)
-  // for the four right-hand sides q of the block, xrow(r, q) giving x;
-  // each 64-row chunk is staged in LDS, thread (lane, w) takes rows
-  // 16 w .. 16 w + 15 of it
-  auto gather = [&](int cb0, int kpc, int r0, int r1, double (&a)[4], auto&& xrow) {
-    for (int c0 = r0; c0 < r1; c0 += TILE) {
-      const int nr = min(TILE, r1 - c0);
-      double lv[TILE * NBMAX / 256];
-#pragma unroll
-      for (int u = 0; u < TILE * NBMAX / 256; ++u) {
-        const int idx = u * 256 + tid, r = idx & (TILE - 1), tt = idx / TILE;
-        lv[u] = Lj[(int64_t)(cb0 + min(tt, kpc - 1)) * m + c0 + min(r, nr - 1)];
-      }
-      const double xv = lane < nr ? xrow(c0 + lane, w) : 0.0;
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < TILE * NBMAX / 256; ++u) {
-        const int idx = u * 256 + tid, r = idx & (TILE - 1), tt = idx / TILE;
-        Ls[r][tt] = (r < nr && tt < kpc) ? here(lv[u]) : 0.0;
-      }
-      xs[w][lane] = xv;
-      __syncthreads();
-      if (lane < kpc)
-        for (int r = 16 * w; r < 16 * w + 16; ++r) {
-          const double l = Ls[r][lane];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) a[q] = fma(l, xs[q][r], a[q]);
-        }
-    }
-  };
-  for (int64_t cb = 0; cb < nrhs; cb += 4) {
-    const int64_t cq = cb + w;
-    auto xglob = [&](int r, int q) { return cb + q < nrhs ? x[R[r] + (cb + q) * S.n] : 0.0; };
-    // one panel of the pair (s = 1: p1, s = 0: p0) for this block
-    auto panel = [&](int s, const double (&wv)[NBMAX * NBMAX / 256]) {
-      const int cs = cA + s * nb, kps = s ? kp1 : kp0;
-      const bool okq = lane < kps && cq < nrhs;
-      const int64_t eq = fcol + s * nb + (okq ? lane + cq * S.n : 0);
-      const double xq = fin ? x[eq] : 0.0;
-      const double aq = useacc ? acc[eq] : 0.0;
-      double a[4] = {0.0, 0.0, 0.0, 0.0};
-      gather(cs, kps, rb, re, a, xglob);
-      // the coupling block, with x_p1 of this task (in vs, from s = 1;
-      // thread (lane, w) wrote vs[w][lane] itself)
-      if (fin && s == 0 && two) gather(cs, kps, cA + nb, cA + nb + kp1, a, [&](int r, int q) { return vs[q][r - cA - nb]; });
-      // reduce: thread (lane, w) takes column lane, right-hand side cb + w
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 4; ++q) red[w][q][lane] = a[q];
-      __syncthreads();
-      const double v = (red[0][w][lane] + red[1][w][lane]) + (red[2][w][lane] + red[3][w][lane]);
-      if (!fin) {
-        if (okq) atomicAdd(acc + eq, v);
-        return;
-      }
-      if (useacc && okq) acc[eq] = 0.0;
-#pragma unroll
-      for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
-        const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;
-        Ls[c][r] = (c < kps && r < kps) ? here(wv[u]) : 0.0;
-      }
-      vs[w][lane] = okq ? xq - (v + aq) : 0.0;
-      __syncthreads();
-      const double xn = apply_wt(Ls, vs[w], lane);
-      if (okq) x[eq] = xn;
-      __syncthreads();
-      vs[w][lane] = okq ? xn : 0.0;  // x_p1 for the coupling of p0
-    };
-    if (two) panel(1, wv1);
-    panel(0, wv0);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // logdet = 2 sum_j log L_jj: per-block tree sums, then one block.
 // ---------------------------------------------------------------------------
@@ -2291,7 +2170,6 @@ hipError_t launch_solve_step(const DevSym& S, const double* L, const double* win
   else if (kind == 14) k_fwd2<<<ntasks, 256, 0, st>>>(S, L, winv, off, y, x, nrhs);
   else if (kind == 15) k_fwd_small<<<(ntasks + 3) / 4, 256, 0, st>>>(S, L, winv, off, ntasks, y, x, nrhs);
   else if (kind == 16) k_bwd_small<<<(ntasks + 3) / 4, 256, 0, st>>>(S, L, winv, off, ntasks, x, nrhs);
-  else if (kind == 18) k_bwd2<<<ntasks, 256, 0, st>>>(S, L, winv, off, x, acc, nrhs);
   else k_bwd<<<ntasks, 256, 0, st>>>(S, L, winv, off, x, acc, nrhs);
   return hipGetLastError();
 }

@@ -341,31 +341,21 @@ int main(int argc, char** argv) {
     }
     for (int64_t i = 0; i < N && ok; ++i)
       if (!xdone[i] || yg[i] != ye[i]) ok = fail("forward solve incomplete");
-    // backward: a unit -- a panel, or in a two-panel launch (K_BWD2) the
-    // panel t.a with the next one when the supernode has it -- is done by
-    // its single task (c = -1) or, when split, by 64-row tiles (c = 0)
-    // summed into its accumulator and a finishing task (c = 1 + n, n rows
-    // of its own) in a later launch; every task of a unit sees the same
-    // panels; every row below the unit is gathered exactly once; tasks read
-    // x below the unit, which must be done, and not in the same launch
+    // backward: a panel is done by its single task (c = -1) or, when split,
+    // by 64-row tiles (c = 0) summed into its accumulator and a finishing
+    // task (c = 1 + n, n rows of its own) in a later launch; every row below
+    // the panel is gathered exactly once; tasks read x below the panel,
+    // which must be done, and not in the same launch
     std::vector<char> bdone(N, 0);
-    std::vector<int64_t> fin_launch(N, -1), tile_launch(N, -1), unit_w(N, 0);
+    std::vector<int64_t> fin_launch(N, -1), tile_launch(N, -1);
     std::vector<std::vector<char>> gathered(N);
     for (const Launch& L : S.bwd_plan) {
       ++g_launch;
-      if (L.kind != K_BWD && L.kind != K_BWD2 && L.kind != K_BWD_SMALL) {
-        ok = fail("unknown launch kind in the backward plan");
-        break;
-      }
+      if (L.kind != K_BWD && L.kind != K_BWD_SMALL) { ok = fail("unknown launch kind in the backward plan"); break; }
       for (int32_t q = 0; q < L.ntasks && ok; ++q) {
         const Task& t = S.tasks[L.off + q];
-        const int64_t J = t.J, c0 = int64_t(t.a) * nb;
-        if (t.a < 0 || c0 >= K(J)) { ok = fail("backward task for a panel the supernode does not have"); break; }
-        const int64_t kp0 = std::min<int64_t>(nb, K(J) - c0);
-        const int64_t kp = kp0 + (L.kind == K_BWD2 && c0 + nb < K(J) ? std::min<int64_t>(nb, K(J) - c0 - nb) : 0);
+        const int64_t J = t.J, c0 = int64_t(t.a) * nb, kp = std::min<int64_t>(nb, K(J) - c0);
         const int64_t f0 = S.sptr[J] + c0, below = c0 + kp;
-        if (unit_w[f0] == 0) unit_w[f0] = kp;
-        else if (unit_w[f0] != kp) { ok = fail("the tasks of one backward unit disagree on its panels"); break; }
         std::vector<char>& seen = gathered[f0];
         if (seen.empty()) seen.assign(M(J) - below + 1, 0);
         auto finish = [&]() {
@@ -421,14 +411,10 @@ int main(int argc, char** argv) {
     std::printf("violation (launch %lld): %s\n", (long long)g_launch, g_err.c_str());
     return 1;
   }
-  int64_t bsplit = 0, nbwd2 = 0;
+  int64_t bsplit = 0;
   for (const Launch& L : S.bwd_plan)
-    if (L.kind == K_BWD || L.kind == K_BWD2)
-      for (int32_t q = 0; q < L.ntasks; ++q) {
-        const Task& t = S.tasks[L.off + q];
-        bsplit += t.c > 0;
-        nbwd2 += L.kind == K_BWD2 && t.c != 0 && (int64_t(t.a) + 1) * nb < K(t.J);
-      }
+    if (L.kind == K_BWD)
+      for (int32_t q = 0; q < L.ntasks; ++q) bsplit += S.tasks[L.off + q].c > 0;
   int64_t nsmall = 0, nfwd2 = 0, nssolve = 0;
   for (const Launch& L : S.factor_plan)
     if (L.kind == K_SMALL) nsmall += L.ntasks;
@@ -444,10 +430,10 @@ int main(int argc, char** argv) {
   int64_t rlb_tasks = 0;
   for (const Launch& L : S.factor_plan)
     if (L.kind == K_UPD_RLB) rlb_tasks += L.ntasks;
-  std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld fwd2=%lld bwd2=%lld small=%lld small_solve=%lld fwd_bytes=%.0f "
+  std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld fwd2=%lld small=%lld small_solve=%lld fwd_bytes=%.0f "
               "bwd_bytes=%.0f storage=%lld colors=%lld si_launches=%zu rlb_blocks=%lld rlb_tasks=%lld\n",
               S.factor_plan.size(), S.fwd_plan.size(), S.bwd_plan.size(), (long long)bsplit, (long long)nfwd2,
-              (long long)nbwd2, (long long)nsmall, (long long)nssolve, fwd_bytes, bwd_bytes, (long long)storage,
+              (long long)nsmall, (long long)nssolve, fwd_bytes, bwd_bytes, (long long)storage,
               (long long)S.max_colors, S.si_plan.size(), (long long)S.rlb_blocks, (long long)rlb_tasks);
   return 0;
 }

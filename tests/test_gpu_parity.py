@@ -112,8 +112,8 @@ def test_dense(n):
 
 @pytest.mark.parametrize("n,nb", [(150, 64), (150, 32), (300, 48)])
 def test_dense_odd_panels(n, nb):
-    """One supernode whose panel count is odd: the backward rounds take the
-    panels in pairs, the first round (the last panel) alone."""
+    """One supernode whose panel count is odd, a ragged last panel, several
+    blocks of right-hand sides."""
     rng = np.random.default_rng(n + nb)
     G = rng.standard_normal((n, n))
     M = G @ G.T / n + np.eye(n)
@@ -125,11 +125,10 @@ def test_dense_odd_panels(n, nb):
 
 
 @pytest.mark.parametrize("side,nb,nrhs", [(14, 16, 1), (16, 48, 6), (14, 32, 9)])
-def test_backward_pair_rounds(side, nb, nrhs):
-    """Separators of many panels with hundreds of rows below them: two-panel
-    backward tasks with the coupling block, split into far row tiles a round
-    ahead and a finishing task, odd panel counts, several blocks of four
-    right-hand sides."""
+def test_backward_split_rounds(side, nb, nrhs):
+    """Separators of many panels with hundreds of rows below them: backward
+    panels split into far row tiles a round ahead and a finishing task,
+    several blocks of four right-hand sides."""
     p = gen.make_config(2, side=side)
     B = np.random.default_rng(side * nb + nrhs).standard_normal((p.n, nrhs))
     run_case(p.n, p.colptr, p.rowind, p.vals, p.perm, B, 0, 8, nb)
