@@ -318,6 +318,31 @@ def mixed_ir(args, dev):
         return _mixed_ir_body(args, p, S, info, vals, Bt, Xt, stream, steps)
 
 
+# dense matrix-core peaks of the update products by precision (TFLOP/s)
+PEAK_UPDATE_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+
+
+def _update_roofline(F, S, vals, prec):
+    """One eager factorization with per-launch events: the external update's
+    algorithmic rate against the matrix-core peak of its product precision,
+    all levels and the wide-supernode levels."""
+    F.profile(True)
+    F.refactor(vals, precision=prec)
+    recs = F.profile_launches()
+    F.profile(False)
+    peak = PEAK_UPDATE_TFLOPS[prec]
+    up = [r for r in recs if r["kind"] == "update_ext"]
+    wl = wide_update_levels(S)
+    wr = [r for r in up if r["level"] in wl]
+
+    def rate(rs):
+        ms, fl = sum(r["ms"] for r in rs), sum(r["flops"] for r in rs)
+        a = fl / (ms * 1e-3) / 1e12 if ms > 0 else None
+        return dict(launches=len(rs), ms=ms, achieved=a, frac=a / peak if a is not None else None)
+
+    return dict(precision=prec, peak=peak, unit="TFLOP/s", all=rate(up), wide=rate(wr))
+
+
 def _mixed_ir_body(args, p, S, info, vals, Bt, Xt, stream, steps):
     F = S.factor(vals)
     for _ in range(args.warmup):
@@ -327,10 +352,11 @@ def _mixed_ir_body(args, p, S, info, vals, Bt, Xt, stream, steps):
     t64 = _timed_steps(steps, stream, [("factor", lambda: F.refactor(vals)),
                                        ("solve", lambda: (Xt.copy_(Bt), F.solve_(Xt)))])
     eta64 = F.berr_(vals, Bt, Xt)
+    roof64 = _update_roofline(F, S, vals, "f64")
     del F
     out = dict(workload=p.meta["doc"], n=p.n, nrhs=int(p.B.shape[1]), flops_alg=info["flops_alg"],
                fp64=dict(factor_ms=t64["factor"], factor_solve_ms=t64["factor"] + t64["solve"],
-                         gflops=info["flops_alg"] / t64["factor"] * 1e-6, berr=eta64))
+                         gflops=info["flops_alg"] / t64["factor"] * 1e-6, berr=eta64, update_roofline=roof64))
     for prec in ("f32", "bf16"):
         Fm = S.factor(vals, precision=prec)
         it_box = {}
@@ -346,10 +372,12 @@ def _mixed_ir_body(args, p, S, info, vals, Bt, Xt, stream, steps):
                                           ("solve_ir", refine)])
         total = tm["factor"] + tm["solve_ir"]
         ok = bool(max(it_box["berr"]) <= 1e-12)
+        roof = _update_roofline(Fm, S, vals, prec)
         out[prec + "_ir"] = dict(factor_ms=tm["factor"], solve_ir_ms=tm["solve_ir"], total_ms=total,
                                  gflops=info["flops_alg"] / tm["factor"] * 1e-6, iterations=it_box["it"],
                                  path="pcg" if Fm.last_refine_path else "ir", converged=ok, berr=it_box["berr"],
-                                 speedup_vs_fp64=out["fp64"]["factor_solve_ms"] / total if ok else None)
+                                 speedup_vs_fp64=out["fp64"]["factor_solve_ms"] / total if ok else None,
+                                 update_roofline=roof)
         del Fm
     return out
 
