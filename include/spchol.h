@@ -380,7 +380,8 @@ spchol_status spchol_berr(spchol_num num, const double *vals_dev, const double *
 
 /* Selected inverse Z = C^{-1} (C = P A P^T) on the supernodal pattern,
  * written to caller-owned device memory in the layout of the factor
- * (spchol_sym_storage); upper triangles of the diagonal blocks unspecified. */
+ * (spchol_sym_storage); the upper triangles of the diagonal blocks are zero,
+ * as in the factor. */
 spchol_status spchol_selinv_export(spchol_num num, double *dst_dev, void *stream);
 
 /* log det(A) = 2 sum_j log L_jj, reduced on the device (pairwise tree);

@@ -1295,8 +1295,11 @@ static spchol_status run_selinv(spchol_num_s* N, hipStream_t st) {
     if (s) return s;
     if ((s = grow(N, &N->Z, &N->zcap, storage, st))) return s;
     if ((s = grow(N, &N->sibuf, &N->sicap, ws, st))) return s;
-    // Y blocks and T accumulators: zero here (a kernel, stream-ordered),
-    // and left zero by their readers
+    // Z: zero once (the selected inversion writes the lower part of every
+    // block; above the diagonal of the diagonal blocks stays zero, as in L).
+    // Y blocks and T accumulators: zero here (kernels, stream-ordered), and
+    // left zero by their readers
+    HIP_TRY(launch_fill(N->Z, std::max<int64_t>(storage, 1), 0.0, st));
     HIP_TRY(launch_fill(N->sibuf, std::max<int64_t>(ws, 1), 0.0, st));
   }
   double* ybuf = N->sibuf;
