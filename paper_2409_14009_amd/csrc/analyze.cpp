@@ -22,6 +22,7 @@
 #include "analyze.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -536,9 +537,25 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
             if (t.c == 1) {  // update of the diagonal block by the previous panel
               fl += 2.0 * double(nb) * double(kp * (kp + 1) / 2);
               by += 8.0 * double(nb) * double(kp);
+            } else if (t.c >= 3) {
+              // the block's rows in panel p-1: (c = 4: panel p-2's update,)
+              // the solve with W_{p-1} (read, triangle), the rows written; the
+              // diagonal block's update by one or two panels
+              const double np = t.c == 4 ? 2.0 : 1.0;
+              if (t.c == 4) {
+                fl += 2.0 * double(nb) * double(nb) * double(kp);
+                by += 16.0 * double(nb) * double(kp);
+              }
+              fl += double(kp) * double(nb) * double(nb) + np * 2.0 * double(nb) * double(kp * (kp + 1) / 2);
+              by += 16.0 * double(nb) * double(kp) + 8.0 * double(nb * (nb + 1) / 2);
             }
           } else {
             by += 8.0 * double(kp * (kp + 1) / 2);
+            if (t.c == 1) {  // the previous panel's update of the tile, its rows of both panels read
+              const int64_t kq = std::min<int64_t>(nb, k - c0);
+              fl += 2.0 * double(nb) * double(nr) * double(kq);
+              by += 8.0 * double(nb) * double(nr + kq);
+            }
           }
           fl += double(nr) * double(kp) * double(kp);
           by += 16.0 * double(nr * kp);
@@ -610,12 +627,17 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       L.ntasks = (int32_t)((int64_t)S.tasks.size() - L.off);
       if (L.ntasks == 0) { plan.pop_back(); return; }
       for (int64_t q = L.off; q < L.off + L.ntasks; ++q) {
-        int32_t kind = L.kind == K_FACTOR_LA ? (q - L.off < L.nfirst ? K_FACTOR : K_UPD_INT) : L.kind;
+        int32_t kind = L.kind;
+        if (kind == K_FACTOR_LA)
+          kind = q - L.off < L.nfirst ? K_FACTOR : q - L.off < L.nfirst + L.ntrsm ? K_TRSM : K_UPD_INT;
         // a single-panel task of a two-panel forward round does what a K_FWD task does
         if (kind == K_FWD2 && !(S.tasks[q].c & 2)) kind = K_FWD;
         cost(kind, S.tasks[q], L.flops, L.bytes);
       }
     };
+    // (SPCHOL_PANEL_ROUNDS=2: the two-launch panel rounds everywhere)
+    const char* pr_env = std::getenv("SPCHOL_PANEL_ROUNDS");
+    const bool fp_rounds = !(pr_env && std::atoi(pr_env) == 2);
     for (int64_t l = 0; l < S.nlevels; ++l) {
       // supernodes small enough for one wavefront: their whole step in one
       // launch; the panel rounds and tiled updates below take the others
@@ -654,7 +676,46 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       // diagonal task of round p + 1 applies it to its diagonal block first
       // (task field c = 1), the tiles below run beside it
       auto merged = [&](int64_t p) { return nb == kTile && p + 1 < maxp && inl_of[p + 1] == 0; };
-      for (int64_t p = 0; p < maxp; ++p) {
+      // One launch per panel round (levels of few wide supernodes, whose
+      // diagonal tasks solve no rows inline; 64-column panels): round p holds
+      //   the diagonal tasks of panel p, which first solve the rows of their
+      //     own block in panel p-1's columns (with panel p-2's update of
+      //     them) and apply panels p-2 and p-1 to their diagonal block (task
+      //     field c = 3: panel p-1 only, c = 4: both);
+      //   the row tiles of panel p-1 below those rows (with panel p-2's
+      //     update, c = 1);
+      //   panel p-2's update tiles of the column blocks from p on (below the
+      //     diagonal block in block p).
+      // A round's three sets touch disjoint entries and read only entries
+      // the rounds before completed; round maxp holds the last row tiles.
+      bool one_launch = fp_rounds && nb == kTile && maxp >= 2;
+      for (int64_t p = 0; p < maxp && one_launch; ++p) one_launch = inl_of[p] != kTrsmRows;
+      if (one_launch) {
+        for (int64_t p = 0; p <= maxp; ++p) {
+          open(S.factor_plan, K_FACTOR_LA, (int32_t)l, (int32_t)p);
+          for (int32_t J : lev)
+            if (npan(J) > p) S.tasks.push_back({J, (int32_t)p, (int32_t)M(J), p == 0 ? 0 : (p == 1 ? 3 : 4)});
+          Launch& LL = S.factor_plan.back();
+          LL.nfirst = (int32_t)((int64_t)S.tasks.size() - LL.off);
+          if (p >= 1)
+            for (int32_t J : lev) {
+              if (npan(J) <= p - 1) continue;
+              const int64_t s0 = npan(J) > p ? p * nb + kpan(J, p) : (p - 1) * nb + kpan(J, p - 1);
+              for (int64_t r0 = s0; r0 < M(J); r0 += kTile)
+                S.tasks.push_back({J, (int32_t)(p - 1), (int32_t)r0, p - 1 >= 1 ? 1 : 0});
+            }
+          LL.ntrsm = (int32_t)((int64_t)S.tasks.size() - LL.off) - LL.nfirst;
+          if (p >= 2)
+            for (int32_t J : lev)
+              for (int64_t cb = p; cb < npan(J); ++cb) {
+                const int64_t c0 = cb * nb;
+                for (int64_t r0 = cb == p ? c0 + kpan(J, p) : c0; r0 < M(J); r0 += kTile)
+                  S.tasks.push_back({J, (int32_t)r0, (int32_t)c0, (int32_t)(p - 2)});
+              }
+          close(S.factor_plan);
+        }
+      }
+      for (int64_t p = 0; p < maxp && !one_launch; ++p) {
         const int64_t inl = inl_of[p];
         open(S.factor_plan, K_FACTOR, (int32_t)l, (int32_t)p);
         for (int32_t J : lev) {

@@ -85,6 +85,8 @@ struct Launch {
   int64_t slot_base = 0;  // selected inversion: first entry of si_yoff for this round
   int32_t seg = 0;        // SI_Y: rows of B per task (64, 128 or kSiSeg)
   int32_t nfirst = 0;     // FACTOR_LA: number of leading FACTOR tasks
+  int32_t ntrsm = 0;      // FACTOR_LA: number of TRSM tasks after them (the one-launch
+                          // panel rounds; the rest are internal update tiles)
   int32_t side = 0;       // UPD_EXT of level l whose targets lie above level l+1: may run
                           // beside level l+1's launches, must finish before level l+2's
 };

@@ -55,7 +55,9 @@ hipError_t launch_update(const DevSym& S, double* L, int32_t kind, int64_t off, 
 // cb.. of L_RJ L_RJ^T written to U (column-major, leading dimension m_J - cb,
 // lower part; fp64), not scattered: the host-resident factorization
 hipError_t launch_update_dense(const DevSym& S, double* L, int64_t off, int32_t ntasks, double* U, hipStream_t st);
-hipError_t launch_factor_la(const DevSym& S, double* L, int64_t off, int32_t nfirst, int32_t ntasks,
+// tasks [0, nfirst): diagonal tasks; then ntrsm row tiles; the rest internal
+// update tiles
+hipError_t launch_factor_la(const DevSym& S, double* L, int64_t off, int32_t nfirst, int32_t ntrsm, int32_t ntasks,
                             unsigned long long* status, double* winv, int32_t prec, hipStream_t st);
 hipError_t launch_si(const DevSym& S, int32_t kind, int64_t off, int32_t ntasks, const double* L, const double* winv,
                      double* Z, const int64_t* yoff, double* ybuf, double* tbuf, int32_t seglen, hipStream_t st);

@@ -277,13 +277,124 @@ __device__ __forceinline__ void invert_diag_block(const double* __restrict__ Dc,
 //   4. W is stored (winv) for the row-tile launch and the solves.
 constexpr int PANEL_SMEM = 2 * NBMAX * DLD;  // doubles: Dc, Wc
 
+// X = A V^T as tile_mfma_acc computes it, with A staged in LDS and V read
+// from registers in the MFMA B-operand layout: bv[ks] = V[16 w + li][4 ks + lk].
+__device__ __forceinline__ void tile_mfma_acc_rv(const double* __restrict__ As, const double (&bv)[NBMAX / 4], int lane,
+                                                 d4 (&acc)[4]) {
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < NBMAX / 4; ++ks) {
+    double av[4];
+#pragma unroll
+    for (int rb2 = 0; rb2 < 4; ++rb2) av[rb2] = As[(4 * ks + lk) * DLD + 16 * rb2 + li];
+#pragma unroll
+    for (int rb2 = 0; rb2 < 4; ++rb2) acc[rb2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rb2], bv[ks], acc[rb2], 0, 0, 0);
+  }
+}
+
+// One-launch panel rounds (task field c = 3, 4; 64-column panels): the
+// rows of panel p's diagonal block in panel p-1's columns,
+// B = L[c0 .. c0+kp, c0-64 .. c0], are solved by the diagonal task itself:
+// (c = 4) B -= A2 C2^T with A2 = L[c0.., c0-128 .. c0-64] and
+// C2 = L[c0-64 .., c0-128 .. c0-64] (panel p-2's update of B), then
+// X = B W_{p-1}^T (W the stored inverse of panel p-1's diagonal block),
+// stored in place of B.  The diagonal block, staged in Dc from v
+// (identity-padded past kp), takes panel p-2's update A2 A2^T here (c = 4);
+// on return Wc holds X in the layout of store_rows, for the pre-update
+// D -= X X^T of c = 1 that follows.  All 256 threads; rows of X past kp
+// zero.
+__device__ __forceinline__ void fused_prologue(const DevSym& S, double* __restrict__ L, int J, int p, int m, int kp,
+                                               bool two, const double (&v)[NBMAX * NBMAX / 256],
+                                               const double* __restrict__ winv, double* __restrict__ Dc,
+                                               double* __restrict__ Wc, int tid) {
+  constexpr int nb = NBMAX;
+  const int c0 = p * nb;
+  const int lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int col = MB * w + li;  // this thread's output column (accumulator layout)
+  double* __restrict__ P1 = L + S.loff[J] + (int64_t)(c0 - nb) * m;  // panel p-1's columns
+  const double* __restrict__ P2 = P1 - (int64_t)nb * m;               // panel p-2's (c = 4)
+  const double* __restrict__ W1 = winv + S.wbase[J] + (int64_t)(p - 1) * nb * nb;
+  // every load issued together: B in the accumulator layout (rows
+  // 16 rb2 + 4 q + lk, column col; rows past kp clamped, zeroed when
+  // staged), W_{p-1} and C2 in the B-operand layout, A2 for LDS
+  double bq[4][4], wb[NBMAX / 4], cb[NBMAX / 4], a2[NBMAX * NBMAX / 256];
+#pragma unroll
+  for (int rb2 = 0; rb2 < 4; ++rb2)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bq[rb2][q] = P1[(int64_t)col * m + c0 + min(16 * rb2 + 4 * q + lk, kp - 1)];
+#pragma unroll
+  for (int ks = 0; ks < NBMAX / 4; ++ks) wb[ks] = W1[(4 * ks + lk) * nb + col];
+  if (two) {
+#pragma unroll
+    for (int ks = 0; ks < NBMAX / 4; ++ks) cb[ks] = P2[(int64_t)(4 * ks + lk) * m + c0 - nb + col];
+    load_rows(a2, P2, m, nb, c0, tid);
+  }
+#pragma unroll
+  for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+    const int idx = u * 256 + tid, i = idx & 63, c = idx >> 6;
+    Dc[c * DLD + i] = (i < kp && c <= i) ? here(v[u]) : (i == c ? 1.0 : 0.0);
+  }
+  d4 acc[4];
+  if (two) {
+    store_rows(Wc, a2, m, nb, c0, tid);
+    __syncthreads();
+    // the diagonal block less A2 A2^T (each thread its own entries)
+    tile_mfma_acc(Wc, Wc, nb, lane, w, acc);
+#pragma unroll
+    for (int rb2 = 0; rb2 < 4; ++rb2)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * rb2 + 4 * q + lk;
+        if (r < kp && col <= r) Dc[col * DLD + r] -= acc[rb2][q];
+      }
+    // B less A2 C2^T
+    tile_mfma_acc_rv(Wc, cb, lane, acc);
+#pragma unroll
+    for (int rb2 = 0; rb2 < 4; ++rb2)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bq[rb2][q] -= acc[rb2][q];
+    __syncthreads();
+  }
+  // X = B W^T: B (rows past kp zero) staged as the A operand
+#pragma unroll
+  for (int rb2 = 0; rb2 < 4; ++rb2)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 16 * rb2 + 4 * q + lk;
+      Wc[col * DLD + r] = r < kp ? bq[rb2][q] : 0.0;
+    }
+  __syncthreads();
+  tile_mfma_acc_rv(Wc, wb, lane, acc);
+#pragma unroll
+  for (int rb2 = 0; rb2 < 4; ++rb2)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 16 * rb2 + 4 * q + lk;
+      if (r < kp) P1[(int64_t)col * m + c0 + r] = acc[rb2][q];
+    }
+  __syncthreads();
+  // Wc <- X
+#pragma unroll
+  for (int rb2 = 0; rb2 < 4; ++rb2)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 16 * rb2 + 4 * q + lk;
+      Wc[col * DLD + r] = r < kp ? acc[rb2][q] : 0.0;
+    }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__ L, const DevTask t,
                                            unsigned long long* __restrict__ status, double* __restrict__ winv,
                                            double* __restrict__ smem) {
   double* __restrict__ Dc = smem;
   double* __restrict__ Wc = smem + NBMAX * DLD;
   const int J = t.J, p = t.a, rb = t.b;
-  const bool pre = t.c == 1;
+  // c = 1: panel p-1's update of the diagonal block from its solved rows;
+  // c = 3, 4: those rows solved here first (one-launch rounds)
+  const bool pre = t.c != 0, fused = t.c >= 3;
   const int m = S.sm[J], k = S.sk[J];
   const int c0 = p * S.nb;
   const int kp = min(S.nb, k - c0);
@@ -300,11 +411,17 @@ __device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__
     const int idx = u * 256 + tid, i = idx & 63, c = idx >> 6;
     v[u] = Lp[(int64_t)min(c, kp - 1) * m + c0 + min(i, kp - 1)];
   }
-  if (pre) load_rows(va, L + S.loff[J] + (int64_t)(c0 - S.nb) * m, m, S.nb, c0, tid);
+  if (fused) {
+    fused_prologue(S, L, J, p, m, kp, t.c == 4, v, winv, Dc, Wc, tid);
+  } else {
+    if (pre) load_rows(va, L + S.loff[J] + (int64_t)(c0 - S.nb) * m, m, S.nb, c0, tid);
 #pragma unroll
-  for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
-    const int idx = u * 256 + tid, i = idx & 63, c = idx >> 6;
-    Dc[c * DLD + i] = (i < kp && c <= i) ? here(v[u]) : (i == c ? 1.0 : 0.0);
+    for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
+      const int idx = u * 256 + tid, i = idx & 63, c = idx >> 6;
+      Dc[c * DLD + i] = (i < kp && c <= i) ? here(v[u]) : (i == c ? 1.0 : 0.0);
+    }
+    // (c = 1) the previous panel's rows, for the pre-update
+    if (pre) store_rows(Wc, va, m, S.nb, c0, tid);
   }
 
   const int li = lane & 15, lk = lane >> 4;
@@ -401,7 +518,6 @@ __device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__
       for (int v = 0; v < 4; ++v) Wc[(MB * b + li) * DLD + MB * i + 4 * v + lk] = -O[v];
     };
     if (pre) {
-      store_rows(Wc, va, m, S.nb, c0, tid);
       __syncthreads();
       pre_tile(w, 0);  // block column 0, one block per wavefront
     }
@@ -452,7 +568,6 @@ __device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__
     //    D -= A A^T with A = rows c0..c0+kp of panel p - 1, on the matrix
     //    cores (A staged in Wc, which is cleared again afterwards)
     if (pre) {
-      store_rows(Wc, va, m, S.nb, c0, tid);
       __syncthreads();
       d4 acc[4];
       tile_mfma_acc(Wc, Wc, S.nb, lane, w, acc);
@@ -465,8 +580,9 @@ __device__ __forceinline__ void panel_body(const DevSym& S, double* __restrict__
           if (r < kp && c <= r) Dc[c * DLD + r] -= acc[rb2][q];
         }
       // a last, narrower panel: rows kp..63 of the tile lie below its
-      // diagonal block, in storage (the row-tile launch reads them next)
-      if (kp < NBMAX) {
+      // diagonal block, in storage (the row-tile launch reads them next;
+      // in one-launch rounds the row tiles apply this update themselves)
+      if (kp < NBMAX && !fused) {
 #pragma unroll
         for (int rb2 = 0; rb2 < 4; ++rb2)
 #pragma unroll
@@ -545,18 +661,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 
 // Panel step, row tiles not solved by the diagonal task: X = B W^T with the
 // inverted diagonal block W the diagonal task stored (256 threads, one
-// 64-row tile each).
-__global__ __launch_bounds__(256) void k_panel_rows(DevSym S, double* __restrict__ L, int64_t off,
-                                                    const double* __restrict__ winv) {
-  __shared__ __attribute__((aligned(16))) double As[NBMAX * DLD];
-  __shared__ __attribute__((aligned(16))) double Wc[NBMAX * DLD];
-  const DevTask t = S.tasks[off + blockIdx.x];
+// 64-row tile each).  c = 1 (one-launch rounds): the tile first takes panel
+// p-1's update, B -= A C^T with A its rows of panel p-1 and C the rows of
+// panel p's diagonal block in panel p-1's columns (solved a round before).
+__device__ __forceinline__ void rows_body(const DevSym& S, double* __restrict__ L, const DevTask t,
+                                          const double* __restrict__ winv, double* __restrict__ smem) {
+  double* __restrict__ As = smem;
+  double* __restrict__ Wc = smem + NBMAX * DLD;
   const int J = t.J, p = t.a, R0 = t.b;
   const int m = S.sm[J], k = S.sk[J];
   const int c0 = p * S.nb;
   const int kp = min(S.nb, k - c0);
   double* __restrict__ Lp = L + S.loff[J] + (int64_t)c0 * m;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
   const double* __restrict__ src = winv + S.wbase[J] + (int64_t)p * S.nb * S.nb;
   // the inverse block and the tile's rows: both loads in flight together
   double v[NBMAX * NBMAX / 256], vr[NBMAX * NBMAX / 256];
@@ -565,15 +682,51 @@ __global__ __launch_bounds__(256) void k_panel_rows(DevSym S, double* __restrict
     const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;  // idx = c * 64 + r
     v[u] = src[min(c, kp - 1) * kp + min(r, kp - 1)];
   }
-  load_rows(vr, Lp, m, kp, R0, tid);
+  if (t.c == 1) {
+    // B in the accumulator layout of tile_mfma_acc (wavefront w: column
+    // 16 w + li, rows 16 rb2 + 4 q + lk of the tile), A and C of panel p-1
+    const double* __restrict__ P1 = Lp - (int64_t)S.nb * m;
+    double bq[4][4], ca[NBMAX * NBMAX / 256];
+#pragma unroll
+    for (int rb2 = 0; rb2 < 4; ++rb2)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * rb2 + 4 * q + lk;
+        bq[rb2][q] = Lp[(int64_t)min(MB * w + li, kp - 1) * m + min(R0 + r, m - 1)];
+      }
+    load_rows(vr, P1, m, S.nb, R0, tid);
+    load_rows(ca, P1, m, S.nb, c0, tid);
+    store_rows(As, vr, m, S.nb, R0, tid);
+    store_rows(Wc, ca, m, S.nb, c0, tid);
+    __syncthreads();
+    d4 acc[4];
+    tile_mfma_acc(As, Wc, S.nb, lane, w, acc);
+    __syncthreads();
+    const int c = MB * w + li;
+#pragma unroll
+    for (int rb2 = 0; rb2 < 4; ++rb2)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * rb2 + 4 * q + lk;
+        As[c * DLD + r] = (c < kp && R0 + r < m) ? bq[rb2][q] - acc[rb2][q] : 0.0;
+      }
+  } else {
+    load_rows(vr, Lp, m, kp, R0, tid);
+  }
 #pragma unroll
   for (int u = 0; u < NBMAX * NBMAX / 256; ++u) {
     const int idx = u * 256 + tid, c = idx >> 6, r = idx & 63;
     Wc[c * DLD + r] = (r < kp && c < kp) ? here(v[u]) : 0.0;
   }
-  store_rows(As, vr, m, kp, R0, tid);
+  if (t.c != 1) store_rows(As, vr, m, kp, R0, tid);
   __syncthreads();
   tile_mfma(As, Wc, kp, lane, w, Lp, m, R0, m, false, 1.0);
+}
+
+__global__ __launch_bounds__(256) void k_panel_rows(DevSym S, double* __restrict__ L, int64_t off,
+                                                    const double* __restrict__ winv) {
+  __shared__ __attribute__((aligned(16))) double smem[2 * NBMAX * DLD];
+  rows_body(S, L, S.tasks[off + blockIdx.x], winv, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -888,13 +1041,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 // One-panel lookahead: workgroups below nfirst factor panel p (panel_body),
 // the others apply internal update tiles of panel p-1 to columns right of
 // panel p.  The two sets touch disjoint columns.
+// One-launch panel rounds: workgroups below nfirst are diagonal tasks,
+// those below ntrsm_end row tiles (rows_body), the rest internal update
+// tiles; the sets touch disjoint entries.
 template <int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_panel_la(DevSym S, double* __restrict__ L, int64_t off, int32_t nfirst,
-                                                  unsigned long long* __restrict__ status,
+                                                  int32_t ntrsm_end, unsigned long long* __restrict__ status,
                                                   double* __restrict__ winv) {
   __shared__ __attribute__((aligned(16))) double smem[PANEL_SMEM > UPD_SMEM ? PANEL_SMEM : UPD_SMEM];
   const DevTask t = S.tasks[off + blockIdx.x];
   if ((int)blockIdx.x < nfirst) panel_body(S, L, t, status, winv, smem);
+  else if ((int)blockIdx.x < ntrsm_end) rows_body(S, L, t, winv, smem);
   else update_body<P, 1>(S, L, t, smem);
 }
 
@@ -2101,12 +2258,13 @@ hipError_t launch_factor_panel(const DevSym& S, double* L, int64_t off, int32_t 
   return hipGetLastError();
 }
 
-hipError_t launch_factor_la(const DevSym& S, double* L, int64_t off, int32_t nfirst, int32_t ntasks,
+hipError_t launch_factor_la(const DevSym& S, double* L, int64_t off, int32_t nfirst, int32_t ntrsm, int32_t ntasks,
                             unsigned long long* status, double* winv, int32_t prec, hipStream_t st) {
   if (ntasks <= 0) return hipSuccess;
-  if (prec == 2) k_panel_la<2><<<ntasks, 256, 0, st>>>(S, L, off, nfirst, status, winv);
-  else if (prec == 1) k_panel_la<1><<<ntasks, 256, 0, st>>>(S, L, off, nfirst, status, winv);
-  else k_panel_la<0><<<ntasks, 256, 0, st>>>(S, L, off, nfirst, status, winv);
+  const int32_t te = nfirst + ntrsm;
+  if (prec == 2) k_panel_la<2><<<ntasks, 256, 0, st>>>(S, L, off, nfirst, te, status, winv);
+  else if (prec == 1) k_panel_la<1><<<ntasks, 256, 0, st>>>(S, L, off, nfirst, te, status, winv);
+  else k_panel_la<0><<<ntasks, 256, 0, st>>>(S, L, off, nfirst, te, status, winv);
   return hipGetLastError();
 }
 

@@ -417,7 +417,7 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
       }));
     } else if (l.kind == K_FACTOR_LA) {
       HIP_TRY(timed_at(N, SPCHOL_KERNEL_FACTOR, l.level, 0, l.flops, l.bytes, st, [&] {
-        return launch_factor_la(D, N->L, l.off, l.nfirst, l.ntasks, N->status, N->winv, prec, st);
+        return launch_factor_la(D, N->L, l.off, l.nfirst, l.ntrsm, l.ntasks, N->status, N->winv, prec, st);
       }));
     } else if (l.kind == K_FACTOR || l.kind == K_TRSM) {
       const bool diag = l.kind == K_FACTOR;

@@ -160,7 +160,7 @@ int main(int argc, char** argv) {
     for (int32_t q = 0; q < L.ntasks && ok; ++q) {
       const Task& t = S.tasks[L.off + q];
       int32_t kind = L.kind;
-      if (kind == K_FACTOR_LA) kind = q < L.nfirst ? K_FACTOR : K_UPD_INT;
+      if (kind == K_FACTOR_LA) kind = q < L.nfirst ? K_FACTOR : q < L.nfirst + L.ntrsm ? K_TRSM : K_UPD_INT;
       const int64_t J = t.J, k = K(J), m = M(J);
       if (kind == K_FACTOR || kind == K_TRSM) {
         const int64_t c0 = int64_t(t.a) * nb, kp = std::min<int64_t>(nb, k - c0);
@@ -176,6 +176,28 @@ int main(int argc, char** argv) {
                 if (r >= c0 + kp) ok = ok && on_write(acc, idx(J, c, r), q, false);
                 got[idx(J, c, r)] += 1;
               }
+          } else if (t.c == 3 || t.c == 4) {
+            // one-launch rounds: the block's rows in panel p-1's columns are
+            // solved here (after panel p-2's update of them, c = 4), then
+            // panels p-2 (c = 4) and p-1 update the diagonal block
+            if (t.a < (t.c == 3 ? 1 : 2)) ok = fail("fused diagonal task without its previous panels");
+            if (kp > nb || c0 - nb < 0) ok = fail("fused diagonal task outside the supernode");
+            const int64_t c1 = c0 - nb, c2 = c0 - 2 * nb;
+            for (int64_t s1 = c1; s1 < c0 && ok; ++s1)
+              for (int64_t r = c0; r < c0 + kp && ok; ++r) {
+                const int64_t e = idx(J, s1, r);
+                if (t.c == 4) {
+                  for (int64_t s2 = c2; s2 < c1 && ok; ++s2) ok = need_solved(idx(J, s2, r), q) && need_solved(idx(J, s2, s1), q);
+                  got[e] += 1;
+                }
+                ok = ok && need_complete(e, q) && solve_entry(e, q);
+              }
+            for (int64_t c = c0; c < c0 + kp && ok; ++c)
+              for (int64_t r = c; r < c0 + kp && ok; ++r) {
+                for (int64_t s2 = (t.c == 4 ? c2 : c1); s2 < c0 && ok; ++s2)
+                  ok = need_solved(idx(J, s2, r), q) && need_solved(idx(J, s2, c), q);
+                got[idx(J, c, r)] += t.c == 4 ? 2 : 1;
+              }
           } else if (t.c != 0) {
             ok = fail("unexpected FACTOR task flag");
           }
@@ -188,6 +210,18 @@ int main(int argc, char** argv) {
           for (int64_t c = c0; c < c0 + kp && ok; ++c)
             for (int64_t r = c; r < c0 + kp && ok; ++r) ok = need_solved(idx(J, c, r), q);
           const int64_t re = std::min<int64_t>(int64_t(t.b) + kTile, m);
+          if (t.c == 1) {  // the previous panel's update of the tile first
+            if (t.a < 1) ok = fail("fused row tile without a previous panel");
+            if (t.b < c0 + kp) ok = fail("fused row tile inside the diagonal block");
+            for (int64_t c = c0; c < c0 + kp && ok; ++c)
+              for (int64_t r = t.b; r < re && ok; ++r) {
+                for (int64_t s1 = c0 - nb; s1 < c0 && ok; ++s1)
+                  ok = need_solved(idx(J, s1, r), q) && need_solved(idx(J, s1, c), q);
+                got[idx(J, c, r)] += 1;
+              }
+          } else if (t.c != 0) {
+            ok = fail("unexpected TRSM task flag");
+          }
           for (int64_t c = c0; c < c0 + kp && ok; ++c)
             for (int64_t r = t.b; r < re && ok; ++r) ok = need_complete(idx(J, c, r), q) && solve_entry(idx(J, c, r), q);
         }
@@ -427,13 +461,17 @@ int main(int argc, char** argv) {
   double fwd_bytes = 0, bwd_bytes = 0;
   for (const Launch& L : S.fwd_plan) fwd_bytes += L.bytes;
   for (const Launch& L : S.bwd_plan) bwd_bytes += L.bytes;
-  int64_t rlb_tasks = 0;
-  for (const Launch& L : S.factor_plan)
+  int64_t rlb_tasks = 0, fused_diag = 0;
+  for (const Launch& L : S.factor_plan) {
     if (L.kind == K_UPD_RLB) rlb_tasks += L.ntasks;
+    if (L.kind == K_FACTOR_LA)
+      for (int32_t q = 0; q < L.nfirst; ++q) fused_diag += S.tasks[L.off + q].c >= 3;
+  }
   std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld fwd2=%lld small=%lld small_solve=%lld fwd_bytes=%.0f "
-              "bwd_bytes=%.0f storage=%lld colors=%lld si_launches=%zu rlb_blocks=%lld rlb_tasks=%lld\n",
+              "bwd_bytes=%.0f storage=%lld colors=%lld si_launches=%zu rlb_blocks=%lld rlb_tasks=%lld fused_diag=%lld\n",
               S.factor_plan.size(), S.fwd_plan.size(), S.bwd_plan.size(), (long long)bsplit, (long long)nfwd2,
               (long long)nsmall, (long long)nssolve, fwd_bytes, bwd_bytes, (long long)storage,
-              (long long)S.max_colors, S.si_plan.size(), (long long)S.rlb_blocks, (long long)rlb_tasks);
+              (long long)S.max_colors, S.si_plan.size(), (long long)S.rlb_blocks, (long long)rlb_tasks,
+              (long long)fused_diag);
   return 0;
 }

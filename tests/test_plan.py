@@ -24,7 +24,7 @@ def checker(tmp_path_factory):
     return exe
 
 
-def _run(checker, tmp_path, n, cp, ri, perm, mode, z, nb, det=0, rule=0, rlb=0, pr=0):
+def _run(checker, tmp_path, n, cp, ri, perm, mode, z, nb, det=0, rule=0, rlb=0, pr=0, env=None):
     f = tmp_path / "pat.txt"
     perm = np.arange(n) if perm is None else perm
     with open(f, "w") as fh:
@@ -33,7 +33,7 @@ def _run(checker, tmp_path, n, cp, ri, perm, mode, z, nb, det=0, rule=0, rlb=0, 
         fh.write(" ".join(map(str, ri)) + "\n")
         fh.write(" ".join(map(str, perm)) + "\n")
     r = subprocess.run([checker, str(f), str(mode), str(z), str(nb), str(det), str(rule), str(rlb), str(pr)],
-                       capture_output=True, text=True)
+                       capture_output=True, text=True, env=None if env is None else dict(os.environ, **env))
     assert r.returncode == 0, r.stdout + r.stderr
     return r.stdout
 
@@ -54,6 +54,11 @@ def test_grid3d(checker, tmp_path, side, z, nb):
         assert int(out.split("split_bwd=")[1].split()[0]) > 0, out
         # supernodes of several panels: two-panel forward tasks
         assert int(out.split("fwd2=")[1].split()[0]) > 0, out
+        # levels of few wide supernodes: one launch per panel round
+        assert int(out.split("fused_diag=")[1].split()[0]) > 0, out
+        # and the two-launch rounds everywhere instead
+        out2 = _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, z, nb, env={"SPCHOL_PANEL_ROUNDS": "2"})
+        assert int(out2.split("fused_diag=")[1].split()[0]) == 0, out2
     # the algorithmic bytes the solve plans charge: each sweep reads every
     # stored entry of L below the diagonal blocks once and the lower
     # triangle of each inverted diagonal block once (plus 16 bytes per row
