@@ -442,7 +442,8 @@ typedef struct {
  * schedule of the supernodal elimination tree (Fig. 1; -1 for launches
  * outside it: fills, permutations, log-determinant, selected inversion);
  * side: 1 for external updates that ran on the second stream beside the
- * next level's panel chain, else 0. */
+ * level's near updates and the next level's panel chain, else 0 (always 0
+ * when every launch runs alone, profiling mode 2). */
 typedef struct {
   int32_t kind;     /* SPCHOL_KERNEL_*                                         */
   int32_t level;
@@ -453,7 +454,13 @@ typedef struct {
   double bytes;     /* algorithmic HBM bytes                                   */
 } spchol_launch_record;
 
-/* enable != 0 starts collecting (clearing earlier records), 0 stops. */
+/* enable 1 or 2 starts collecting (clearing earlier records), 0 stops.
+ * 1: the launches run as they do unprofiled, the external updates of a level
+ * on the second stream beside other work, so their records include time
+ * shared with it.  2: every launch runs alone, all on the caller's stream in
+ * plan order, so each record is that launch's own duration (the factorization
+ * as a whole takes longer).  SPCHOL_ERR_ARG for a null handle or another
+ * value of enable. */
 spchol_status spchol_profile(spchol_num num, int32_t enable);
 
 /* Synchronize the streams the records were made on, sum the records per

@@ -442,9 +442,11 @@ class Factor:
         _check(capi.lib().spchol_logdet(self._h, C.byref(out), _stream_ptr(stream)))
         return float(out.value)
 
-    def profile(self, enable: bool = True):
-        """Start (clearing earlier records) or stop per-launch event timing."""
-        _check(capi.lib().spchol_profile(self._h, 1 if enable else 0))
+    def profile(self, enable: bool = True, alone: bool = False):
+        """Start (clearing earlier records) or stop per-launch event timing;
+        alone: every launch runs by itself on the caller's stream (no second
+        stream), so each record is that launch's own duration."""
+        _check(capi.lib().spchol_profile(self._h, (2 if alone else 1) if enable else 0))
 
     def profile_read(self) -> dict:
         """Per kernel kind: launches, ms, flops, bytes summed over the records

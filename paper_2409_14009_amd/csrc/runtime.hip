@@ -185,6 +185,7 @@ struct Profiler {
     double flops, bytes;
   };
   bool on = false;
+  bool serial = false;  // every launch alone: the far updates on the main stream
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<Rec> recs;
@@ -394,10 +395,16 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
     for (hipEvent_t& e : N->side_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   std::vector<int64_t> outstanding;  // levels whose side launch is not joined yet
-  for (const Launch& l : S.factor_plan) {
-    if (l.side) {
+  bool forked = false;
+  // profiling with every launch alone: the far updates run on st in plan
+  // order (right after the near ones), so each record is one launch's own time
+  const bool one_stream = N->prof.on && N->prof.serial;
+  for (size_t li = 0; li < S.factor_plan.size(); ++li) {
+    const Launch& l = S.factor_plan[li];
+    if (l.side && !one_stream) {
       // fork: the side stream starts once everything before is done
-      HIP_TRY(hipEventRecord(N->fork_ev, st));
+      if (!forked) HIP_TRY(hipEventRecord(N->fork_ev, st));
+      forked = false;
       HIP_TRY(hipStreamWaitEvent(N->side, N->fork_ev, 0));
       const int32_t uk = l.kind == K_UPD_RLB ? 4 : l.kind;
       HIP_TRY(timed_at(N, SPCHOL_KERNEL_UPDATE_EXT, l.level, 1, l.flops, l.bytes, N->side,
@@ -405,6 +412,14 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
       HIP_TRY(hipEventRecord(N->side_ev[l.level], N->side));
       outstanding.push_back(l.level);
       continue;
+    }
+    // the far updates of a level fork before its near ones: both read the
+    // level's finished panels and add into disjoint ancestors, so the far
+    // tiles fill the CUs the near launch leaves idle
+    if (!one_stream && (l.kind == K_UPD_EXT || l.kind == K_UPD_RLB) && li + 1 < S.factor_plan.size() &&
+        S.factor_plan[li + 1].side && S.factor_plan[li + 1].level == l.level) {
+      HIP_TRY(hipEventRecord(N->fork_ev, st));
+      forked = true;
     }
     // join: a side launch of level v must be done before level v + 2
     while (!outstanding.empty() && l.level >= outstanding.front() + 2) {
@@ -1480,7 +1495,9 @@ spchol_status spchol_num_export(spchol_num num, double* dst_dev, void* stream) {
 
 spchol_status spchol_profile(spchol_num num, int32_t enable) {
   if (!num) return fail(SPCHOL_ERR_ARG, "null handle");
+  if (enable < 0 || enable > 2) return fail(SPCHOL_ERR_ARG, "profile mode must be 0, 1 or 2");
   num->prof.on = enable != 0;
+  num->prof.serial = enable == 2;
   if (num->prof.on) {
     num->prof.recs.clear();
     num->prof.used = 0;

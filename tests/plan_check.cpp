@@ -143,18 +143,46 @@ int main(int argc, char** argv) {
   // a launch marked `side` (external updates of level v) runs beside the
   // launches of level v + 1 and is joined before level v + 2: it is replayed
   // at that point, after everything it may overlap with
-  std::vector<const Launch*> order, pending;
-  for (const Launch& L : S.factor_plan) {
-    if (L.side) { pending.push_back(&L); continue; }
+  // The side stream forks before the near external launch of the same level
+  // when that launch directly precedes it (both read the same finished
+  // panels and write disjoint ancestors): a probe entry at the fork point
+  // checks that every column the side launch reads is solved by then.
+  std::vector<std::pair<const Launch*, bool>> order;  // (launch, probe)
+  std::vector<const Launch*> pending;
+  const auto& FP = S.factor_plan;
+  for (size_t i = 0; i < FP.size(); ++i) {
+    const Launch& L = FP[i];
+    if (L.side) {
+      const bool early = i > 0 && !FP[i - 1].side && (FP[i - 1].kind == K_UPD_EXT || FP[i - 1].kind == K_UPD_RLB) &&
+                         FP[i - 1].level == L.level;
+      if (!early) order.push_back({&L, true});
+      pending.push_back(&L);
+      continue;
+    }
     while (!pending.empty() && L.level >= pending.front()->level + 2) {
-      order.push_back(pending.front());
+      order.push_back({pending.front(), false});
       pending.erase(pending.begin());
     }
-    order.push_back(&L);
+    if (i + 1 < FP.size() && FP[i + 1].side && (L.kind == K_UPD_EXT || L.kind == K_UPD_RLB) &&
+        FP[i + 1].level == L.level)
+      order.push_back({&FP[i + 1], true});
+    order.push_back({&L, false});
   }
-  for (const Launch* Lp : pending) order.push_back(Lp);
-  for (const Launch* Lp : order) {
-    const Launch& L = *Lp;
+  for (const Launch* Lp : pending) order.push_back({Lp, false});
+  int64_t fork_probes = 0;
+  for (const auto& op : order) {
+    const Launch& L = *op.first;
+    if (op.second) {  // fork point of a side launch: its sources are final
+      ++fork_probes;
+      for (int32_t q = 0; q < L.ntasks && ok; ++q) {
+        const int64_t J = S.tasks[L.off + q].J, k = K(J), m = M(J);
+        for (int64_t s = 0; s < k && ok; ++s)
+          for (int64_t r = k; r < m && ok; ++r)
+            if (!solved[idx(J, s, r)]) ok = fail("side stream forked before the panel it reads is solved");
+      }
+      if (!ok) break;
+      continue;
+    }
     ++g_launch;
     if (L.side && L.kind != K_UPD_EXT && L.kind != K_UPD_RLB) ok = fail("side launch that is not an external update");
     for (int32_t q = 0; q < L.ntasks && ok; ++q) {
@@ -468,10 +496,10 @@ int main(int argc, char** argv) {
       for (int32_t q = 0; q < L.nfirst; ++q) fused_diag += S.tasks[L.off + q].c >= 3;
   }
   std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld fwd2=%lld small=%lld small_solve=%lld fwd_bytes=%.0f "
-              "bwd_bytes=%.0f storage=%lld colors=%lld si_launches=%zu rlb_blocks=%lld rlb_tasks=%lld fused_diag=%lld\n",
+              "bwd_bytes=%.0f storage=%lld colors=%lld si_launches=%zu rlb_blocks=%lld rlb_tasks=%lld fused_diag=%lld fork_probes=%lld\n",
               S.factor_plan.size(), S.fwd_plan.size(), S.bwd_plan.size(), (long long)bsplit, (long long)nfwd2,
               (long long)nsmall, (long long)nssolve, fwd_bytes, bwd_bytes, (long long)storage,
               (long long)S.max_colors, S.si_plan.size(), (long long)S.rlb_blocks, (long long)rlb_tasks,
-              (long long)fused_diag);
+              (long long)fused_diag, (long long)fork_probes);
   return 0;
 }

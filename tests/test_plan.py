@@ -56,6 +56,8 @@ def test_grid3d(checker, tmp_path, side, z, nb):
         assert int(out.split("fwd2=")[1].split()[0]) > 0, out
         # levels of few wide supernodes: one launch per panel round
         assert int(out.split("fused_diag=")[1].split()[0]) > 0, out
+        # far external updates on the second stream, forked at their level
+        assert int(out.split("fork_probes=")[1].split()[0]) > 0, out
         # and the two-launch rounds everywhere instead
         out2 = _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, z, nb, env={"SPCHOL_PANEL_ROUNDS": "2"})
         assert int(out2.split("fused_diag=")[1].split()[0]) == 0, out2
