@@ -1356,22 +1356,31 @@ __global__ __launch_bounds__(256) void k_fwd_small(DevSym S, const double* __res
   for (int u = 0; u < kSmallSolveCols; ++u) wr[u] = W[min(u, k - 1) * k + il];
   SmallRows rw;
   small_rows(S, Lj, J, m, k, lane, rw);
-  for (int64_t c = 0; c < nrhs; ++c) {
-    const double yv = own ? y[fcol + lane + c * S.n] : 0.0;
-    double z = 0.0;
+  // right-hand sides four at a time: the group's entries of y_J are all
+  // loaded before the first product (one memory round trip per group)
+  for (int64_t cb = 0; cb < nrhs; cb += 4) {
+    double yv[4];
 #pragma unroll
-    for (int u = 0; u < kSmallSolveCols; ++u) z = fma(u < k ? wr[u] : 0.0, readlane_d(yv, u), z);
-    z = own ? z : 0.0;
-    if (own) x[fcol + lane + c * S.n] = z;
-    double a0 = 0.0, a1 = 0.0;
+    for (int q = 0; q < 4; ++q) yv[q] = (own && cb + q < nrhs) ? y[fcol + lane + (cb + q) * S.n] : 0.0;
 #pragma unroll
-    for (int u = 0; u < kSmallSolveCols; ++u) {
-      const double zu = readlane_d(z, u);
-      a0 = fma(u < k ? rw.l0[u] : 0.0, zu, a0);
-      a1 = fma(u < k ? rw.l1[u] : 0.0, zu, a1);
+    for (int q = 0; q < 4; ++q) {
+      const int64_t c = cb + q;
+      if (c >= nrhs) break;
+      double z = 0.0;
+#pragma unroll
+      for (int u = 0; u < kSmallSolveCols; ++u) z = fma(u < k ? wr[u] : 0.0, readlane_d(yv[q], u), z);
+      z = own ? z : 0.0;
+      if (own) x[fcol + lane + c * S.n] = z;
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int u = 0; u < kSmallSolveCols; ++u) {
+        const double zu = readlane_d(z, u);
+        a0 = fma(u < k ? rw.l0[u] : 0.0, zu, a0);
+        a1 = fma(u < k ? rw.l1[u] : 0.0, zu, a1);
+      }
+      if (rw.ok0) atomicAdd(y + rw.g0 + c * S.n, -a0);
+      if (rw.ok1) atomicAdd(y + rw.g1 + c * S.n, -a1);
     }
-    if (rw.ok0) atomicAdd(y + rw.g0 + c * S.n, -a0);
-    if (rw.ok1) atomicAdd(y + rw.g1 + c * S.n, -a1);
   }
 }
 
