@@ -525,6 +525,14 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
           by += 16.0 * double(k * m) + 8.0 * double(k * (k + 1) / 2) + 16.0 * double(r * (r + 1) / 2);
           break;
         }
+        case K_MEDIUM: {
+          // factor of the K columns, the inverse block, the r rows below solved
+          const int64_t r = m - k;
+          for (int64_t j = 0; j < k; ++j) fl += double(k - j) * double(k - j);
+          fl += double(r) * double(k) * double(k) + double(k) * double(k) * double(k) / 3.0;
+          by += 16.0 * double(k * m) + 8.0 * double(k * (k + 1) / 2);
+          break;
+        }
         case K_FACTOR:
         case K_TRSM: {
           const int64_t c0 = int64_t(t.a) * nb, kp = std::min<int64_t>(nb, k - c0);
@@ -641,10 +649,24 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
     for (int64_t l = 0; l < S.nlevels; ++l) {
       // supernodes small enough for one wavefront: their whole step in one
       // launch; the panel rounds and tiled updates below take the others
-      std::vector<int32_t> lev;
+      // then the one-panel supernodes of at most 16 columns that are too
+      // tall for that: one wavefront each factors them, their update goes to
+      // the external update tiles with the others'
+      std::vector<int32_t> lev, upd;
       open(S.factor_plan, K_SMALL, (int32_t)l, -1);
       for (int32_t J : bylev[l]) {
         if (small_supernode(K(J), M(J))) S.tasks.push_back({J, 0, 0, 0});
+        else upd.push_back(J);
+      }
+      close(S.factor_plan);
+      // (a launch of its own only when it takes the level's panel rounds
+      // away altogether or holds enough tasks to pay for the extra launch)
+      int64_t nmed = 0;
+      for (int32_t J : upd) nmed += medium_supernode(K(J), M(J), nb);
+      const bool med = nmed > 0 && (nmed == (int64_t)upd.size() || nmed >= kMediumMin);
+      open(S.factor_plan, K_MEDIUM, (int32_t)l, -1);
+      for (int32_t J : upd) {
+        if (med && medium_supernode(K(J), M(J), nb)) S.tasks.push_back({J, 0, 0, 0});
         else lev.push_back(J);
       }
       close(S.factor_plan);
@@ -765,7 +787,7 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       std::vector<Task> far;
       const int32_t ext_kind = S.update_method == 1 ? K_UPD_RLB : K_UPD_EXT;
       open(S.factor_plan, ext_kind, (int32_t)l, -1);
-      for (int32_t J : lev) {
+      for (int32_t J : upd) {
         const int32_t* R = S.rows.data() + S.rptr[J];
         if (S.update_method == 1) {
           // RLB (Sec. II-B): J's rows below its columns in blocks of

@@ -59,6 +59,8 @@ enum Kind : int32_t {
   K_FWD_SMALL = 15,  // forward solve of small one-panel supernodes, one wavefront each
   K_BWD_SMALL = 16,  // backward solve of the same
   K_UPD_RLB = 17,    // external update by block pairs (RLB)
+  K_MEDIUM = 18,     // a one-panel supernode of at most 16 columns too tall for K_SMALL:
+                     // factor, inverse block and all rows below in one wavefront
 };
 
 // Supernodes done by one wavefront (K_SMALL): at most 16 columns, and with
@@ -66,6 +68,18 @@ enum Kind : int32_t {
 // rows below and one unit row per column (for the inverse block) fit the
 // wavefront's 64 lanes.
 inline bool small_supernode(int64_t k, int64_t m) { return k <= 16 && (k <= 4 ? 4 : 16) + m <= 64; }
+
+// Supernodes factored by one wavefront without their update (K_MEDIUM): at
+// most 16 columns (one panel), at most kMediumRows rows below, too tall for
+// K_SMALL; the diagonal block, the inverse block and every row below are
+// done by the wavefront (the rows past its sweep 64 at a time, in
+// sequence: taller panels go to the row tiles, which run in parallel), the
+// update goes to the external update tiles.
+constexpr int64_t kMediumRows = 160;
+constexpr int64_t kMediumMin = 128;  // fewer in a level that also has panel rounds: they join those
+inline bool medium_supernode(int64_t k, int64_t m, int64_t nb) {
+  return k <= 16 && k <= nb && m - k <= kMediumRows && !small_supernode(k, m);
+}
 
 // Supernodes solved by one wavefront (K_FWD_SMALL, K_BWD_SMALL): one panel
 // of at most 16 columns and at most 128 rows below it (two per lane).  A

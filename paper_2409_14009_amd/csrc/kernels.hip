@@ -1174,6 +1174,75 @@ __global__ __launch_bounds__(256) void k_small(DevSym S, double* __restrict__ L,
   }
 }
 
+// One wavefront per supernode of at most 16 columns (one panel) that is too
+// tall for k_small (Sec. II: the diagonal block's Cholesky factor and the
+// panel solve, here without the update, which the external update tiles
+// do).  The sweep takes, as in k_small, the block padded to 4 or 16 columns,
+// the first rows below it and k unit rows: those come out as rows of
+// L_JJ^{-T} (stored as the inverse block W = L_JJ^{-1}).  The remaining rows
+// below follow 64 at a time, each row a times L_JJ^{-T} (a L_JJ^{-T} L_JJ^T =
+// a), the entries of L_JJ^{-T} broadcast from the unit lanes.
+__global__ __launch_bounds__(256) void k_medium(DevSym S, double* __restrict__ L, int64_t off, int32_t ntasks,
+                                                unsigned long long* __restrict__ status,
+                                                double* __restrict__ winv) {
+  const int lane = threadIdx.x & 63;
+  const int q = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (q >= ntasks) return;  // a whole wavefront; nothing below synchronizes
+  const DevTask t = S.tasks[off + q];
+  const int J = t.J, m = S.sm[J], k = S.sk[J];
+  const int nq = k <= 4 ? 4 : MB;
+  const int r = m - k;
+  const int r0 = min(r, 64 - nq - k);  // rows below inside the sweep
+  const bool diag = lane < k;
+  const bool below = lane >= nq && lane < nq + r0;
+  const bool unit = lane >= nq + r0 && lane < nq + r0 + k;
+  const int row = diag ? lane : (below ? k + lane - nq : 0);
+  const int e = unit ? lane - nq - r0 : ((lane >= k && lane < nq) ? lane : -1);
+  double* __restrict__ Lj = L + S.loff[J];
+  double x[MB];
+#pragma unroll
+  for (int c = 0; c < MB; ++c) {
+    const double v = Lj[(int64_t)min(c, k - 1) * m + row];
+    x[c] = ((diag || below) && c < k) ? v : (c == e ? 1.0 : 0.0);
+  }
+  if (nq == 4) potrf16<4>(x, lane, 0, status, (int64_t)S.sfirst[J]);
+  else potrf16<MB>(x, lane, 0, status, (int64_t)S.sfirst[J]);
+  if (diag || below) {
+#pragma unroll
+    for (int c = 0; c < MB; ++c)
+      if (c < k && c <= row) Lj[(int64_t)c * m + row] = x[c];
+  }
+  if (unit) {
+    double* __restrict__ Wd = winv + S.wbase[J];  // the one panel: K x K, column-major
+#pragma unroll
+    for (int c = 0; c < MB; ++c)
+      if (c < k) Wd[(int64_t)e * k + c] = c >= e ? x[c] : 0.0;
+  }
+  const int ub = nq + r0;  // lane of unit row 0: row u of L_JJ^{-T} in lane ub + u
+  for (int base = k + r0; base < m; base += 64) {
+    const int rr = base + lane;
+    const bool ok = rr < m;
+    const int rc = min(rr, m - 1);
+    double a[MB], o[MB];
+#pragma unroll
+    for (int c = 0; c < MB; ++c) {
+      a[c] = c < k ? Lj[(int64_t)min(c, k - 1) * m + rc] : 0.0;
+      o[c] = 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < MB; ++u) {
+      if (u >= k) break;
+#pragma unroll
+      for (int c = u; c < MB; ++c) o[c] = fma(a[u], readlane_d(x[c], ub + u), o[c]);
+    }
+    if (ok) {
+#pragma unroll
+      for (int c = 0; c < MB; ++c)
+        if (c < k) Lj[(int64_t)c * m + rr] = o[c];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // solves.  y is the permuted right-hand side block, n x nrhs, ld = n.
 // ---------------------------------------------------------------------------
@@ -2288,6 +2357,13 @@ hipError_t launch_factor_la(const DevSym& S, double* L, int64_t off, int32_t nfi
   if (prec == 2) k_panel_la<2><<<ntasks, 256, 0, st>>>(S, L, off, nfirst, te, status, winv);
   else if (prec == 1) k_panel_la<1><<<ntasks, 256, 0, st>>>(S, L, off, nfirst, te, status, winv);
   else k_panel_la<0><<<ntasks, 256, 0, st>>>(S, L, off, nfirst, te, status, winv);
+  return hipGetLastError();
+}
+
+hipError_t launch_medium(const DevSym& S, double* L, int64_t off, int32_t ntasks, unsigned long long* status,
+                         double* winv, hipStream_t st) {
+  if (ntasks <= 0) return hipSuccess;
+  k_medium<<<(ntasks + 3) / 4, 256, 0, st>>>(S, L, off, ntasks, status, winv);
   return hipGetLastError();
 }
 

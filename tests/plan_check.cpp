@@ -267,6 +267,12 @@ int main(int argc, char** argv) {
             if (ok && solved[e]) ok = fail("update of an entry that is already solved");
             got[e] += 1;
           }
+      } else if (kind == K_MEDIUM) {
+        // factor and panel solve of the whole one-panel supernode (its
+        // update comes from external update tiles)
+        if (!medium_supernode(k, m, nb)) ok = fail("one-wavefront factor task for a supernode that does not qualify");
+        for (int64_t c = 0; c < k && ok; ++c)
+          for (int64_t r = c; r < m && ok; ++r) ok = need_complete(idx(J, c, r), q) && solve_entry(idx(J, c, r), q);
       } else if (kind == K_UPD_INT || kind == K_UPD_EXT) {
         const bool ext = kind == K_UPD_EXT;
         const int64_t kb = ext ? 0 : int64_t(t.c) * nb, ke = ext ? k : std::min<int64_t>(k, kb + nb);
@@ -477,9 +483,11 @@ int main(int argc, char** argv) {
   for (const Launch& L : S.bwd_plan)
     if (L.kind == K_BWD)
       for (int32_t q = 0; q < L.ntasks; ++q) bsplit += S.tasks[L.off + q].c > 0;
-  int64_t nsmall = 0, nfwd2 = 0, nssolve = 0;
-  for (const Launch& L : S.factor_plan)
+  int64_t nsmall = 0, nfwd2 = 0, nssolve = 0, nmedium = 0;
+  for (const Launch& L : S.factor_plan) {
     if (L.kind == K_SMALL) nsmall += L.ntasks;
+    if (L.kind == K_MEDIUM) nmedium += L.ntasks;
+  }
   for (const Launch& L : S.fwd_plan)
     if (L.kind == K_FWD_SMALL) nssolve += L.ntasks;
   for (const Launch& L : S.fwd_plan)
@@ -496,10 +504,10 @@ int main(int argc, char** argv) {
       for (int32_t q = 0; q < L.nfirst; ++q) fused_diag += S.tasks[L.off + q].c >= 3;
   }
   std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld fwd2=%lld small=%lld small_solve=%lld fwd_bytes=%.0f "
-              "bwd_bytes=%.0f storage=%lld colors=%lld si_launches=%zu rlb_blocks=%lld rlb_tasks=%lld fused_diag=%lld fork_probes=%lld\n",
+              "bwd_bytes=%.0f storage=%lld colors=%lld si_launches=%zu rlb_blocks=%lld rlb_tasks=%lld fused_diag=%lld fork_probes=%lld medium=%lld\n",
               S.factor_plan.size(), S.fwd_plan.size(), S.bwd_plan.size(), (long long)bsplit, (long long)nfwd2,
               (long long)nsmall, (long long)nssolve, fwd_bytes, bwd_bytes, (long long)storage,
               (long long)S.max_colors, S.si_plan.size(), (long long)S.rlb_blocks, (long long)rlb_tasks,
-              (long long)fused_diag, (long long)fork_probes);
+              (long long)fused_diag, (long long)fork_probes, (long long)nmedium);
   return 0;
 }

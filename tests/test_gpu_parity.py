@@ -217,6 +217,18 @@ def test_small_supernode_limits(k, r):
     run_case(n, cp, ri, vv, None, B, 0, 0, 64)
 
 
+@pytest.mark.parametrize("k,r", [(1, 60), (4, 57), (16, 33), (16, 160), (7, 150), (12, 129), (16, 161)])
+def test_medium_supernodes(k, r):
+    """One-panel leaves of at most 16 columns too tall for the whole-step
+    one-wavefront task: factored one wavefront each (the rows below past
+    the sweep in 64-row chunks), their update by the external tiles."""
+    print(f"case medium leaves k={k} r={r}", flush=True)
+    rng = np.random.default_rng(4000 * k + r)
+    n, cp, ri, vv = gen.leaf_pair_spd(k, r, rng)
+    B = rng.standard_normal((n, 3))
+    run_case(n, cp, ri, vv, None, B, 0, 0, 64)
+
+
 @pytest.mark.parametrize("cfg,side,z,nrhs", [(4, 16, 8, 1), (4, 16, 8, 3), (4, 16, 8, 4), (4, 16, 8, 6),
                                              (0, None, 0, 5), (2, 14, 8, 8)])
 def test_small_solve_levels(cfg, side, z, nrhs):

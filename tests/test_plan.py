@@ -177,3 +177,18 @@ def test_rlb_schedule(checker, tmp_path, cfg, side, z, nb, pr):
         b0 = int(plain.split("rlb_blocks=")[1].split()[0])
         print(f"blocks without / with partition refinement: {b0} / {b1}")
         assert b1 <= b0
+
+
+# (leaf columns, rows of the parent, one-wavefront factor tasks expected):
+# one-panel leaves of at most 16 columns too tall for the whole-step
+# one-wavefront task, up to several 64-row chunks of rows below
+MEDIUM_SHAPES = [(1, 60, 2), (4, 57, 2), (16, 33, 2), (16, 160, 2), (7, 150, 2), (12, 129, 2), (16, 32, 0),
+                 (17, 40, 0), (16, 161, 0), (3, 333, 0)]
+
+
+@pytest.mark.parametrize("k,r,nmed", MEDIUM_SHAPES)
+def test_medium_supernodes(checker, tmp_path, k, r, nmed):
+    rng = np.random.default_rng(3000 * k + r)
+    n, cp, ri, _ = gen.leaf_pair_spd(k, r, rng)
+    out = _run(checker, tmp_path, n, cp, ri, None, 0, 0, 64)
+    assert int(out.split("medium=")[1].split()[0]) == nmed, out
