@@ -649,9 +649,9 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
     for (int64_t l = 0; l < S.nlevels; ++l) {
       // supernodes small enough for one wavefront: their whole step in one
       // launch; the panel rounds and tiled updates below take the others
-      // then the one-panel supernodes of at most 16 columns that are too
-      // tall for that: one wavefront each factors them, their update goes to
-      // the external update tiles with the others'
+      // then the short one-panel supernodes of at most 32 columns that are
+      // not: one wavefront each factors them, their update goes to the
+      // external update tiles with the others'
       std::vector<int32_t> lev, upd;
       open(S.factor_plan, K_SMALL, (int32_t)l, -1);
       for (int32_t J : bylev[l]) {
@@ -665,9 +665,15 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       for (int32_t J : upd) nmed += medium_supernode(K(J), M(J), nb);
       const bool med = nmed > 0 && (nmed == (int64_t)upd.size() || nmed >= kMediumMin);
       open(S.factor_plan, K_MEDIUM, (int32_t)l, -1);
+      for (int32_t J : upd)
+        if (med && medium_supernode(K(J), M(J), nb) && K(J) <= 16) S.tasks.push_back({J, 0, 0, 0});
+      S.factor_plan.back().nfirst = (int32_t)((int64_t)S.tasks.size() - S.factor_plan.back().off);
       for (int32_t J : upd) {
-        if (med && medium_supernode(K(J), M(J), nb)) S.tasks.push_back({J, 0, 0, 0});
-        else lev.push_back(J);
+        if (med && medium_supernode(K(J), M(J), nb)) {
+          if (K(J) > 16) S.tasks.push_back({J, 0, 0, 0});
+        } else {
+          lev.push_back(J);
+        }
       }
       close(S.factor_plan);
       int64_t maxp = 0;

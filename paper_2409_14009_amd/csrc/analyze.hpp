@@ -59,7 +59,7 @@ enum Kind : int32_t {
   K_FWD_SMALL = 15,  // forward solve of small one-panel supernodes, one wavefront each
   K_BWD_SMALL = 16,  // backward solve of the same
   K_UPD_RLB = 17,    // external update by block pairs (RLB)
-  K_MEDIUM = 18,     // a one-panel supernode of at most 16 columns too tall for K_SMALL:
+  K_MEDIUM = 18,     // a short one-panel supernode of at most 32 columns not done by K_SMALL:
                      // factor, inverse block and all rows below in one wavefront
 };
 
@@ -70,15 +70,16 @@ enum Kind : int32_t {
 inline bool small_supernode(int64_t k, int64_t m) { return k <= 16 && (k <= 4 ? 4 : 16) + m <= 64; }
 
 // Supernodes factored by one wavefront without their update (K_MEDIUM): at
-// most 16 columns (one panel), at most kMediumRows rows below, too tall for
+// most 32 columns (one panel), at most kMediumRows rows below, not done by
 // K_SMALL; the diagonal block, the inverse block and every row below are
 // done by the wavefront (the rows past its sweep 64 at a time, in
 // sequence: taller panels go to the row tiles, which run in parallel), the
-// update goes to the external update tiles.
+// update goes to the external update tiles.  A K_MEDIUM launch lists its
+// supernodes of at most 16 columns first (nfirst of them).
 constexpr int64_t kMediumRows = 160;
 constexpr int64_t kMediumMin = 128;  // fewer in a level that also has panel rounds: they join those
 inline bool medium_supernode(int64_t k, int64_t m, int64_t nb) {
-  return k <= 16 && k <= nb && m - k <= kMediumRows && !small_supernode(k, m);
+  return k <= 32 && k <= nb && m - k <= kMediumRows && !small_supernode(k, m);
 }
 
 // Supernodes solved by one wavefront (K_FWD_SMALL, K_BWD_SMALL): one panel

@@ -54,10 +54,11 @@ hipError_t launch_update(const DevSym& S, double* L, int32_t kind, int64_t off, 
 // update tiles (J, first local row, first local col, cb) of a column block
 // cb.. of L_RJ L_RJ^T written to U (column-major, leading dimension m_J - cb,
 // lower part; fp64), not scattered: the host-resident factorization
-// one-panel supernodes of at most 16 columns, one wavefront each: factor,
-// inverse block, all rows below (no update)
-hipError_t launch_medium(const DevSym& S, double* L, int64_t off, int32_t ntasks, unsigned long long* status,
-                         double* winv, hipStream_t st);
+// one-panel supernodes of at most 32 columns, one wavefront each: factor,
+// inverse block, all rows below (no update); tasks [0, nfirst) have at most
+// 16 columns, the rest 17 to 32
+hipError_t launch_medium(const DevSym& S, double* L, int64_t off, int32_t nfirst, int32_t ntasks,
+                         unsigned long long* status, double* winv, hipStream_t st);
 hipError_t launch_update_dense(const DevSym& S, double* L, int64_t off, int32_t ntasks, double* U, hipStream_t st);
 // tasks [0, nfirst): diagonal tasks; then ntrsm row tiles; the rest internal
 // update tiles

@@ -1174,71 +1174,94 @@ __global__ __launch_bounds__(256) void k_small(DevSym S, double* __restrict__ L,
   }
 }
 
-// One wavefront per supernode of at most 16 columns (one panel) that is too
-// tall for k_small (Sec. II: the diagonal block's Cholesky factor and the
-// panel solve, here without the update, which the external update tiles
-// do).  The sweep takes, as in k_small, the block padded to 4 or 16 columns,
-// the first rows below it and k unit rows: those come out as rows of
-// L_JJ^{-T} (stored as the inverse block W = L_JJ^{-1}).  The remaining rows
-// below follow 64 at a time, each row a times L_JJ^{-T} (a L_JJ^{-T} L_JJ^T =
-// a), the entries of L_JJ^{-T} broadcast from the unit lanes.
+// One wavefront per one-panel supernode of at most 16 (NB = 1) or 32
+// (NB = 2) columns that is too tall for k_small (Sec. II: the diagonal
+// block's Cholesky factor and the panel solve, here without the update,
+// which the external update tiles do).  The sweep takes, as in k_small, the
+// block padded to 4, 16 or 32 columns, the rows below that still fit and k
+// unit rows: those come out as rows of L_JJ^{-T} (stored as the inverse
+// block W = L_JJ^{-1}).  With two 16-column blocks the second is first
+// updated by the first (lane broadcasts), then swept.  The remaining rows
+// below follow 64 at a time, each row a times L_JJ^{-T} (a L_JJ^{-T} L_JJ^T
+// = a), the entries of L_JJ^{-T} broadcast from the unit lanes, in place
+// from the last column down (column c takes entries 0..c of the row).
+template <int NB>
 __global__ __launch_bounds__(256) void k_medium(DevSym S, double* __restrict__ L, int64_t off, int32_t ntasks,
                                                 unsigned long long* __restrict__ status,
                                                 double* __restrict__ winv) {
+  constexpr int NC = NB * MB;
   const int lane = threadIdx.x & 63;
   const int q = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
   if (q >= ntasks) return;  // a whole wavefront; nothing below synchronizes
   const DevTask t = S.tasks[off + q];
   const int J = t.J, m = S.sm[J], k = S.sk[J];
-  const int nq = k <= 4 ? 4 : MB;
+  const int nq = NB == 2 ? NC : (k <= 4 ? 4 : MB);
   const int r = m - k;
-  const int r0 = min(r, 64 - nq - k);  // rows below inside the sweep
+  const int r0 = max(0, min(r, 64 - nq - k));  // rows below inside the sweep
   const bool diag = lane < k;
   const bool below = lane >= nq && lane < nq + r0;
   const bool unit = lane >= nq + r0 && lane < nq + r0 + k;
   const int row = diag ? lane : (below ? k + lane - nq : 0);
   const int e = unit ? lane - nq - r0 : ((lane >= k && lane < nq) ? lane : -1);
+  const int64_t col0 = S.sfirst[J];
   double* __restrict__ Lj = L + S.loff[J];
-  double x[MB];
+  double x[NB][MB];
 #pragma unroll
-  for (int c = 0; c < MB; ++c) {
-    const double v = Lj[(int64_t)min(c, k - 1) * m + row];
-    x[c] = ((diag || below) && c < k) ? v : (c == e ? 1.0 : 0.0);
-  }
-  if (nq == 4) potrf16<4>(x, lane, 0, status, (int64_t)S.sfirst[J]);
-  else potrf16<MB>(x, lane, 0, status, (int64_t)S.sfirst[J]);
-  if (diag || below) {
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int cc = 0; cc < MB; ++cc) {
+      const int c = b * MB + cc;
+      const double v = Lj[(int64_t)min(c, k - 1) * m + row];
+      x[b][cc] = ((diag || below) && c < k) ? v : (c == e ? 1.0 : 0.0);
+    }
+  if (NB == 1 && nq == 4) potrf16<4>(x[0], lane, 0, status, col0);
+  else potrf16<MB>(x[0], lane, 0, status, col0);
+  if constexpr (NB == 2) {
 #pragma unroll
     for (int c = 0; c < MB; ++c)
-      if (c < k && c <= row) Lj[(int64_t)c * m + row] = x[c];
+#pragma unroll
+      for (int j = 0; j < MB; ++j) x[1][j] = fma(-x[0][c], readlane_d(x[0][c], MB + j), x[1][j]);
+    potrf16<MB>(x[1], lane, MB, status, col0 + MB);
+  }
+  if (diag || below) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int cc = 0; cc < MB; ++cc) {
+        const int c = b * MB + cc;
+        if (c < k && c <= row) Lj[(int64_t)c * m + row] = x[b][cc];
+      }
   }
   if (unit) {
     double* __restrict__ Wd = winv + S.wbase[J];  // the one panel: K x K, column-major
 #pragma unroll
-    for (int c = 0; c < MB; ++c)
-      if (c < k) Wd[(int64_t)e * k + c] = c >= e ? x[c] : 0.0;
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int cc = 0; cc < MB; ++cc) {
+        const int c = b * MB + cc;
+        if (c < k) Wd[(int64_t)e * k + c] = c >= e ? x[b][cc] : 0.0;
+      }
   }
-  const int ub = nq + r0;  // lane of unit row 0: row u of L_JJ^{-T} in lane ub + u
+  const int ub = nq + r0;  // lane of unit row 0: row u of L_JJ^{-T} in lane ub + u (u < k)
   for (int base = k + r0; base < m; base += 64) {
     const int rr = base + lane;
     const bool ok = rr < m;
     const int rc = min(rr, m - 1);
-    double a[MB], o[MB];
+    double a[NC];
 #pragma unroll
-    for (int c = 0; c < MB; ++c) {
-      a[c] = c < k ? Lj[(int64_t)min(c, k - 1) * m + rc] : 0.0;
-      o[c] = 0.0;
-    }
+    for (int c = 0; c < NC; ++c) a[c] = c < k ? Lj[(int64_t)min(c, k - 1) * m + rc] : 0.0;
 #pragma unroll
-    for (int u = 0; u < MB; ++u) {
-      if (u >= k) break;
+    for (int c = NC - 1; c >= 0; --c) {
+      if (c >= k) continue;
+      double o = 0.0;
 #pragma unroll
-      for (int c = u; c < MB; ++c) o[c] = fma(a[u], readlane_d(x[c], ub + u), o[c]);
+      for (int u = 0; u <= c; ++u) o = fma(a[u], readlane_d(x[c / MB][c % MB], ub + u), o);
+      a[c] = o;
     }
     if (ok) {
 #pragma unroll
-      for (int c = 0; c < MB; ++c)
-        if (c < k) Lj[(int64_t)c * m + rr] = o[c];
+      for (int c = 0; c < NC; ++c)
+        if (c < k) Lj[(int64_t)c * m + rr] = a[c];
     }
   }
 }
@@ -2360,10 +2383,11 @@ hipError_t launch_factor_la(const DevSym& S, double* L, int64_t off, int32_t nfi
   return hipGetLastError();
 }
 
-hipError_t launch_medium(const DevSym& S, double* L, int64_t off, int32_t ntasks, unsigned long long* status,
-                         double* winv, hipStream_t st) {
-  if (ntasks <= 0) return hipSuccess;
-  k_medium<<<(ntasks + 3) / 4, 256, 0, st>>>(S, L, off, ntasks, status, winv);
+hipError_t launch_medium(const DevSym& S, double* L, int64_t off, int32_t nfirst, int32_t ntasks,
+                         unsigned long long* status, double* winv, hipStream_t st) {
+  if (nfirst > 0) k_medium<1><<<(nfirst + 3) / 4, 256, 0, st>>>(S, L, off, nfirst, status, winv);
+  if (ntasks > nfirst)
+    k_medium<2><<<(ntasks - nfirst + 3) / 4, 256, 0, st>>>(S, L, off + nfirst, ntasks - nfirst, status, winv);
   return hipGetLastError();
 }
 

@@ -432,7 +432,7 @@ static spchol_status enqueue_factor(spchol_num_s* N, const double* vals, hipStre
       }));
     } else if (l.kind == K_MEDIUM) {
       HIP_TRY(timed_at(N, SPCHOL_KERNEL_FACTOR, l.level, 0, l.flops, l.bytes, st, [&] {
-        return launch_medium(D, N->L, l.off, l.ntasks, N->status, N->winv, st);
+        return launch_medium(D, N->L, l.off, l.nfirst, l.ntasks, N->status, N->winv, st);
       }));
     } else if (l.kind == K_FACTOR_LA) {
       HIP_TRY(timed_at(N, SPCHOL_KERNEL_FACTOR, l.level, 0, l.flops, l.bytes, st, [&] {

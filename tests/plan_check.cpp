@@ -271,6 +271,7 @@ int main(int argc, char** argv) {
         // factor and panel solve of the whole one-panel supernode (its
         // update comes from external update tiles)
         if (!medium_supernode(k, m, nb)) ok = fail("one-wavefront factor task for a supernode that does not qualify");
+        if ((q < L.nfirst) != (k <= 16)) ok = fail("one-wavefront factor tasks not listed 16-column ones first");
         for (int64_t c = 0; c < k && ok; ++c)
           for (int64_t r = c; r < m && ok; ++r) ok = need_complete(idx(J, c, r), q) && solve_entry(idx(J, c, r), q);
       } else if (kind == K_UPD_INT || kind == K_UPD_EXT) {

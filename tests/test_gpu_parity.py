@@ -217,11 +217,13 @@ def test_small_supernode_limits(k, r):
     run_case(n, cp, ri, vv, None, B, 0, 0, 64)
 
 
-@pytest.mark.parametrize("k,r", [(1, 60), (4, 57), (16, 33), (16, 160), (7, 150), (12, 129), (16, 161)])
+@pytest.mark.parametrize("k,r", [(1, 60), (4, 57), (16, 33), (16, 160), (7, 150), (12, 129), (16, 161), (17, 40),
+                                 (20, 5), (32, 0), (32, 100), (24, 160), (33, 50)])
 def test_medium_supernodes(k, r):
-    """One-panel leaves of at most 16 columns too tall for the whole-step
-    one-wavefront task: factored one wavefront each (the rows below past
-    the sweep in 64-row chunks), their update by the external tiles."""
+    """Short one-panel leaves of at most 32 columns not done by the
+    whole-step one-wavefront task: factored one wavefront each (the rows
+    below past the sweep in 64-row chunks), their update by the external
+    tiles; (16, 161) and (33, 50) just past the limits."""
     print(f"case medium leaves k={k} r={r}", flush=True)
     rng = np.random.default_rng(4000 * k + r)
     n, cp, ri, vv = gen.leaf_pair_spd(k, r, rng)

@@ -180,10 +180,11 @@ def test_rlb_schedule(checker, tmp_path, cfg, side, z, nb, pr):
 
 
 # (leaf columns, rows of the parent, one-wavefront factor tasks expected):
-# one-panel leaves of at most 16 columns too tall for the whole-step
+# short one-panel leaves of at most 32 columns not done by the whole-step
 # one-wavefront task, up to several 64-row chunks of rows below
-MEDIUM_SHAPES = [(1, 60, 2), (4, 57, 2), (16, 33, 2), (16, 160, 2), (7, 150, 2), (12, 129, 2), (16, 32, 0),
-                 (17, 40, 0), (16, 161, 0), (3, 333, 0)]
+# ((16, 32): the leaves are whole-step ones, the 32-column parent is not)
+MEDIUM_SHAPES = [(1, 60, 2), (4, 57, 2), (16, 33, 2), (16, 160, 2), (7, 150, 2), (12, 129, 2), (16, 32, 1),
+                 (17, 40, 2), (20, 5, 2), (32, 100, 2), (24, 161, 0), (33, 50, 0), (16, 161, 0), (3, 333, 0)]
 
 
 @pytest.mark.parametrize("k,r,nmed", MEDIUM_SHAPES)
