@@ -865,10 +865,15 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
         smalls[l].clear();
       }
     }
+    // (the supernodes with at most 64 rows below first: nfirst of them)
     auto small_launch = [&](std::vector<Launch>& plan, int32_t kind, int64_t l) {
       if (smalls[l].empty()) return;
       open(plan, kind, (int32_t)l, 0);
-      for (int32_t J : smalls[l]) S.tasks.push_back({J, 0, (int32_t)K(J), 1});
+      for (int32_t J : smalls[l])
+        if (M(J) - K(J) <= kTile) S.tasks.push_back({J, 0, (int32_t)K(J), 1});
+      plan.back().nfirst = (int32_t)((int64_t)S.tasks.size() - plan.back().off);
+      for (int32_t J : smalls[l])
+        if (M(J) - K(J) > kTile) S.tasks.push_back({J, 0, (int32_t)K(J), 1});
       close(plan);
     };
     for (int64_t l = 0; l < S.nlevels; ++l) {

@@ -99,7 +99,8 @@ struct Launch {
   double bytes = 0;  // algorithmic HBM bytes of the launch
   int64_t slot_base = 0;  // selected inversion: first entry of si_yoff for this round
   int32_t seg = 0;        // SI_Y: rows of B per task (64, 128 or kSiSeg)
-  int32_t nfirst = 0;     // FACTOR_LA: number of leading FACTOR tasks
+  int32_t nfirst = 0;     // FACTOR_LA: number of leading FACTOR tasks; MEDIUM: of those with at
+                          // most 16 columns; FWD_SMALL / BWD_SMALL: of those with at most 64 rows below
   int32_t ntrsm = 0;      // FACTOR_LA: number of TRSM tasks after them (the one-launch
                           // panel rounds; the rest are internal update tiles)
   int32_t side = 0;       // UPD_EXT of level l whose targets lie above level l+1: may run

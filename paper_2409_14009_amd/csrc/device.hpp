@@ -90,8 +90,12 @@ hipError_t launch_perm_gather(const DevSym& S, const double* B, int64_t ldb, int
                               hipStream_t st);
 hipError_t launch_perm_scatter(const DevSym& S, const double* y, int64_t nrhs, double* B, int64_t ldb,
                                hipStream_t st);
+// one solve launch of the plans; nfirst: for the small-supernode kinds, the
+// leading tasks with at most 64 rows below (a kernel without the second
+// row chunk), the rest with 65 to 128
 hipError_t launch_solve_step(const DevSym& S, const double* L, const double* winv, int32_t kind, int64_t off,
-                             int32_t ntasks, double* y, double* x, double* acc, int64_t nrhs, hipStream_t st);
+                             int32_t nfirst, int32_t ntasks, double* y, double* x, double* acc, int64_t nrhs,
+                             hipStream_t st);
 hipError_t launch_logdet(const DevSym& S, const double* L, double* partial, int32_t npartial,
                          double* out, hipStream_t st);
 int32_t logdet_partials(int64_t n);

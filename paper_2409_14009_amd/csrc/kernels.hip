@@ -1405,12 +1405,15 @@ struct SmallRows {
   double l0[kSmallSolveCols], l1[kSmallSolveCols];
 };
 
+// (TWO = false: at most 64 rows below, the second chunk left out altogether,
+// its registers too)
+template <bool TWO>
 __device__ __forceinline__ void small_rows(const DevSym& S, const double* __restrict__ Lj, int J, int m, int k,
                                            int lane, SmallRows& r) {
   const int nbl = m - k;
   const int32_t* __restrict__ R = S.rows + S.rptr[J];
   r.ok0 = lane < nbl;
-  r.ok1 = TILE + lane < nbl;
+  r.ok1 = TWO && TILE + lane < nbl;
   const int rl0 = nbl > 0 ? k + min(lane, nbl - 1) : 0;
   r.g0 = R[rl0];
 #pragma unroll
@@ -1420,7 +1423,7 @@ __device__ __forceinline__ void small_rows(const DevSym& S, const double* __rest
   r.g1 = 0;
 #pragma unroll
   for (int u = 0; u < kSmallSolveCols; ++u) r.l1[u] = 0.0;
-  if (nbl > TILE) {
+  if (TWO && nbl > TILE) {
     const int rl1 = k + TILE + min(lane, nbl - TILE - 1);
     r.g1 = R[rl1];
 #pragma unroll
@@ -1430,6 +1433,7 @@ __device__ __forceinline__ void small_rows(const DevSym& S, const double* __rest
 
 // Forward: z = W y_J, stored into x; y_R -= L_RJ z with atomics (the rows
 // below are ancestors', shared with other supernodes of the level).
+template <bool TWO>
 __global__ __launch_bounds__(256) void k_fwd_small(DevSym S, const double* __restrict__ L,
                                                    const double* __restrict__ winv, int64_t off, int32_t ntasks,
                                                    double* __restrict__ y, double* __restrict__ x, int64_t nrhs) {
@@ -1447,7 +1451,7 @@ __global__ __launch_bounds__(256) void k_fwd_small(DevSym S, const double* __res
 #pragma unroll
   for (int u = 0; u < kSmallSolveCols; ++u) wr[u] = W[min(u, k - 1) * k + il];
   SmallRows rw;
-  small_rows(S, Lj, J, m, k, lane, rw);
+  small_rows<TWO>(S, Lj, J, m, k, lane, rw);
   // right-hand sides four at a time: the group's entries of y_J are all
   // loaded before the first product (one memory round trip per group)
   for (int64_t cb = 0; cb < nrhs; cb += 4) {
@@ -1512,6 +1516,7 @@ __device__ __forceinline__ constexpr int col_sum_lane(int u) {
 
 // Backward: x_J = W^T (x_J - L_RJ^T x_R) (x_R final: ancestors are done in
 // earlier rounds).
+template <bool TWO>
 __global__ __launch_bounds__(256) void k_bwd_small(DevSym S, const double* __restrict__ L,
                                                    const double* __restrict__ winv, int64_t off, int32_t ntasks,
                                                    double* __restrict__ x, int64_t nrhs) {
@@ -1530,7 +1535,7 @@ __global__ __launch_bounds__(256) void k_bwd_small(DevSym S, const double* __res
 #pragma unroll
   for (int u = 0; u < kSmallSolveCols; ++u) wt[u] = W[il * k + min(u, k - 1)];
   SmallRows rw;
-  small_rows(S, Lj, J, m, k, lane, rw);
+  small_rows<TWO>(S, Lj, J, m, k, lane, rw);
   for (int64_t c = 0; c < nrhs; ++c) {
     const double xr0 = rw.ok0 ? x[rw.g0 + c * S.n] : 0.0;
     const double xr1 = rw.ok1 ? x[rw.g1 + c * S.n] : 0.0;
@@ -2451,13 +2456,19 @@ hipError_t launch_perm_scatter(const DevSym& S, const double* y, int64_t nrhs, d
 }
 
 hipError_t launch_solve_step(const DevSym& S, const double* L, const double* winv, int32_t kind, int64_t off,
-                             int32_t ntasks, double* y, double* x, double* acc, int64_t nrhs, hipStream_t st) {
+                             int32_t nfirst, int32_t ntasks, double* y, double* x, double* acc, int64_t nrhs,
+                             hipStream_t st) {
   if (ntasks <= 0) return hipSuccess;
+  const int32_t n2 = ntasks - nfirst;  // (small kernels: supernodes with 65..128 rows below)
   if (kind == 3) k_fwd<<<ntasks, 256, 0, st>>>(S, L, winv, off, y, x, nrhs);
   else if (kind == 14) k_fwd2<<<ntasks, 256, 0, st>>>(S, L, winv, off, y, x, nrhs);
-  else if (kind == 15) k_fwd_small<<<(ntasks + 3) / 4, 256, 0, st>>>(S, L, winv, off, ntasks, y, x, nrhs);
-  else if (kind == 16) k_bwd_small<<<(ntasks + 3) / 4, 256, 0, st>>>(S, L, winv, off, ntasks, x, nrhs);
-  else k_bwd<<<ntasks, 256, 0, st>>>(S, L, winv, off, x, acc, nrhs);
+  else if (kind == 15) {
+    if (nfirst > 0) k_fwd_small<false><<<(nfirst + 3) / 4, 256, 0, st>>>(S, L, winv, off, nfirst, y, x, nrhs);
+    if (n2 > 0) k_fwd_small<true><<<(n2 + 3) / 4, 256, 0, st>>>(S, L, winv, off + nfirst, n2, y, x, nrhs);
+  } else if (kind == 16) {
+    if (nfirst > 0) k_bwd_small<false><<<(nfirst + 3) / 4, 256, 0, st>>>(S, L, winv, off, nfirst, x, nrhs);
+    if (n2 > 0) k_bwd_small<true><<<(n2 + 3) / 4, 256, 0, st>>>(S, L, winv, off + nfirst, n2, x, nrhs);
+  } else k_bwd<<<ntasks, 256, 0, st>>>(S, L, winv, off, x, acc, nrhs);
   return hipGetLastError();
 }
 

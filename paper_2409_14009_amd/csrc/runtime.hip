@@ -493,7 +493,7 @@ static spchol_status enqueue_solve(spchol_num_s* num, double* wy, double* wx, do
       const double by = l.bytes;
       const bool fwd = l.kind == K_FWD || l.kind == K_FWD2 || l.kind == K_FWD_SMALL;
       return timed_at(num, fwd ? SPCHOL_KERNEL_FWD : SPCHOL_KERNEL_BWD, l.level, s == st ? 0 : 1, fl, by, s, [&] {
-        return launch_solve_step(D, num->L, num->winv, l.kind, l.off, l.ntasks, y, x, acc, nr, s);
+        return launch_solve_step(D, num->L, num->winv, l.kind, l.off, l.nfirst, l.ntasks, y, x, acc, nr, s);
       });
     };
     for (const Launch& l : S.fwd_plan) {

@@ -356,6 +356,7 @@ int main(int argc, char** argv) {
           // the whole supernode: z over its one panel, all rows below
           if (!small_solve_supernode(K(t.J), M(t.J), nb) || t.a != 0 || t.b != K(t.J) || t.c != 1)
             ok = fail("small forward task for a supernode that does not qualify");
+          if ((q < L.nfirst) != (M(t.J) - K(t.J) <= kTile)) ok = fail("small forward tasks not listed short ones first");
           const int64_t f0 = S.sptr[t.J];
           for (int64_t i = 0; i < K(t.J) && ok; ++i) {
             if (yg[f0 + i] != ye[f0 + i]) ok = fail("forward solve reads an incomplete right-hand side");
@@ -452,6 +453,7 @@ int main(int argc, char** argv) {
         if (L.kind == K_BWD_SMALL) {
           if (!small_solve_supernode(K(J), M(J), nb) || t.a != 0 || t.b != below || t.c != 1)
             ok = fail("small backward task for a supernode that does not qualify");
+          if ((q < L.nfirst) != (M(J) - K(J) <= kTile)) ok = fail("small backward tasks not listed short ones first");
           gather(t.b, M(J));
           all_gathered();
           finish();
