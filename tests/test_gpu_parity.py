@@ -110,10 +110,11 @@ def test_dense(n):
              0, 0, 64)
 
 
-@pytest.mark.parametrize("n,nb", [(150, 64), (150, 32), (300, 48)])
+@pytest.mark.parametrize("n,nb", [(150, 64), (150, 32), (300, 48), (333, 64), (400, 64)])
 def test_dense_odd_panels(n, nb):
     """One supernode whose panel count is odd, a ragged last panel, several
-    blocks of right-hand sides."""
+    blocks of right-hand sides; with 64-column panels and six or seven of
+    them, several one-launch panel rounds with trailing update tiles."""
     rng = np.random.default_rng(n + nb)
     G = rng.standard_normal((n, n))
     M = G @ G.T / n + np.eye(n)

@@ -83,7 +83,7 @@ def test_elasticity(checker, tmp_path):
     _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, 8, 16)
 
 
-@pytest.mark.parametrize("n,nb", [(150, 64), (150, 16), (65, 64), (1, 64)])
+@pytest.mark.parametrize("n,nb", [(150, 64), (150, 16), (65, 64), (1, 64), (400, 64)])
 def test_dense(checker, tmp_path, n, nb):
     cp = np.concatenate([[0], np.cumsum(np.arange(n, 0, -1))]).astype(np.int64)
     ri = np.concatenate([np.arange(j, n) for j in range(n)]).astype(np.int64)
