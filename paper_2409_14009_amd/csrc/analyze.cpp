@@ -1048,7 +1048,13 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
                             kind == K_FWD2 || kind == K_FWD_SMALL || kind == K_SI_Y || kind == K_SI_ZB;
           if (!adds) { out.push_back(L); continue; }
           Task* t0 = S.tasks.data() + L.off;
-          std::stable_sort(t0, t0 + L.ntasks, [&](const Task& a, const Task& b) { return key(a) < key(b); });
+          // (small forward solves: within a colour, the supernodes with at
+          // most 64 rows below first, nfirst of them per part)
+          const bool rows_first = kind == K_FWD_SMALL;
+          auto tall = [&](const Task& t) { return rows_first && M(t.J) - K(t.J) > kTile; };
+          std::stable_sort(t0, t0 + L.ntasks, [&](const Task& a, const Task& b) {
+            return key(a) != key(b) ? key(a) < key(b) : (!tall(a) && tall(b));
+          });
           int64_t parts = 0;
           for (int64_t q = 0; q < L.ntasks;) {
             int64_t e = q + 1;
@@ -1056,6 +1062,10 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
             Launch P = L;
             P.off = L.off + q;
             P.ntasks = (int32_t)(e - q);
+            if (rows_first) {
+              P.nfirst = 0;
+              for (int64_t u = q; u < e; ++u) P.nfirst += !tall(t0[u]);
+            }
             P.flops = P.bytes = 0;
             for (int64_t u = P.off; u < P.off + P.ntasks; ++u) {
               int32_t kd = kind;

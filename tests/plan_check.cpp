@@ -140,6 +140,11 @@ int main(int argc, char** argv) {
   };
 
   bool ok = true;
+  // a launch's leading-task count (the kernel variant that takes them) lies
+  // within the launch
+  for (const std::vector<Launch>* plan : {&S.factor_plan, &S.fwd_plan, &S.bwd_plan, &S.si_plan})
+    for (const Launch& L : *plan)
+      if (L.nfirst < 0 || L.nfirst > L.ntasks) ok = fail("a launch's leading-task count exceeds its tasks");
   // a launch marked `side` (external updates of level v) runs beside the
   // launches of level v + 1 and is joined before level v + 2: it is replayed
   // at that point, after everything it may overlap with
