@@ -1,7 +1,7 @@
 """Mixed precision (fp32 update products, fp64 diagonal Cholesky and
 solves) with iterative refinement against the fp64 matrix.
 
-Gate (the benchmark spec): normwise backward error <= 1e-12 after refinement, per
+Gate (the mixed-precision form's target): normwise backward error <= 1e-12 after refinement, per
 right-hand side.  The iterates themselves depend on rounding (parity
 unpinned); the refined solution is compared with the oracle's fp64
 solution at the accuracy the conditioning allows.

@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Gates (from the fp64 arithmetic and the benchmark spec's tolerances):
+Gates (from the fp64 arithmetic and the workloads' stated tolerances):
   * structure: bit-exact (tests/test_capi.py, CPU);
   * factor: relative residual ||C - L L^T||_F / ||C||_F <= 1e-12, and where
     the matrix is well conditioned (kappa <~ 1e4: the 2D configuration and the

@@ -2,7 +2,7 @@
 solve, against a dense inverse, torch dense autograd, the oracle's closed
 forms and central finite differences.
 
-Gate (the benchmark spec): gradients match to 1e-6 relative.
+Gate (the reverse-mode target): gradients match to 1e-6 relative.
 """
 import numpy as np
 import pytest
