@@ -571,8 +571,9 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
         }
         case K_UPD_INT:
         case K_UPD_EXT: {
-          const int64_t kb = kind == K_UPD_INT ? int64_t(t.c) * nb : 0;
-          const int64_t kk = kind == K_UPD_INT ? std::min<int64_t>(nb, k - kb) : k;
+          const bool range = kind == K_UPD_INT && (t.c & kPanelRange);
+          const int64_t kb = kind == K_UPD_INT ? int64_t(range ? (t.c & 0xffff) : t.c) * nb : 0;
+          const int64_t kk = kind == K_UPD_INT ? std::min<int64_t>(range ? ((t.c >> 16) & 0xff) * nb : nb, k - kb) : k;
           const int64_t colEnd = kind == K_UPD_INT ? k : m;
           const int64_t r1 = std::min<int64_t>(t.a + kTile, m), c1 = std::min<int64_t>(t.b + kTile, colEnd);
           const int64_t valid = lower_count(t.a, r1, t.b, c1);
@@ -717,6 +718,7 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       // A round's three sets touch disjoint entries and read only entries
       // the rounds before completed; round maxp holds the last row tiles.
       bool one_launch = fp_rounds && nb == kTile && maxp >= 2;
+      const int64_t win = kRoundWindow;
       for (int64_t p = 0; p < maxp && one_launch; ++p) one_launch = inl_of[p] != kTrsmRows;
       if (one_launch) {
         for (int64_t p = 0; p <= maxp; ++p) {
@@ -733,13 +735,27 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
                 S.tasks.push_back({J, (int32_t)(p - 1), (int32_t)r0, p - 1 >= 1 ? 1 : 0});
             }
           LL.ntrsm = (int32_t)((int64_t)S.tasks.size() - LL.off) - LL.nfirst;
+          // (with a window of D column blocks: panel p-2 goes to blocks p ..
+          // p + D - 1 only; block p + D enters the window and takes panels
+          // 0 .. p - 2 at once, in ranges of kRangePanels; blocks past it
+          // wait)
           if (p >= 2)
-            for (int32_t J : lev)
-              for (int64_t cb = p; cb < npan(J); ++cb) {
+            for (int32_t J : lev) {
+              const int64_t cend = win > 0 ? std::min<int64_t>(npan(J), p + win) : npan(J);
+              for (int64_t cb = p; cb < cend; ++cb) {
                 const int64_t c0 = cb * nb;
                 for (int64_t r0 = cb == p ? c0 + kpan(J, p) : c0; r0 < M(J); r0 += kTile)
                   S.tasks.push_back({J, (int32_t)r0, (int32_t)c0, (int32_t)(p - 2)});
               }
+              if (win > 0 && p + win < npan(J)) {
+                const int64_t c0 = (p + win) * nb;
+                for (int64_t s0 = 0; s0 <= p - 2; s0 += kRangePanels) {
+                  const int64_t ns = std::min<int64_t>(kRangePanels, p - 1 - s0);
+                  for (int64_t r0 = c0; r0 < M(J); r0 += kTile)
+                    S.tasks.push_back({J, (int32_t)r0, (int32_t)c0, (int32_t)(s0 | (ns << 16) | kPanelRange)});
+                }
+              }
+            }
           close(S.factor_plan);
         }
       }

@@ -814,6 +814,11 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
     kb = t.c * S.nb;
     ke = min(k, kb + S.nb);
     colEnd = k;
+  } else if constexpr (kind == 6) {
+    // panels (c & 0xffff) .. + ((c >> 16) & 0xff) - 1
+    kb = (t.c & 0xffff) * S.nb;
+    ke = min(k, kb + ((t.c >> 16) & 0xff) * S.nb);
+    colEnd = k;
   } else if constexpr (kind == 4) {
     // a block-pair tile: rows row0 .. rowEnd - 1, columns col0 .. colEnd - 1
     kb = 0;
@@ -971,6 +976,14 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
       const int cc = w + 4 * j, gc = col0 + cc;
       if (cc < cmax && gr < m && gr >= gc) Lj[(int64_t)gc * m + gr] = cold[j] - Cs[cc * CLD + lane];
     }
+  } else if constexpr (kind == 6) {
+    // (other tasks of the launch add into the same entries: the other
+    // panel ranges of the block)
+#pragma unroll
+    for (int j = 0; j < TILE / 4; ++j) {
+      const int cc = w + 4 * j, gc = col0 + cc;
+      if (cc < cmax && gr < m && gr >= gc) atomicAdd(Lj + (int64_t)gc * m + gr, -Cs[cc * CLD + lane]);
+    }
   } else if constexpr (kind == 5) {
     // the update matrix itself, not scattered: rows cb .. m - 1 of its
     // columns cb .. (a column block, cb = task field c) go to aux,
@@ -1066,6 +1079,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
   const DevTask t = S.tasks[off + blockIdx.x];
   if ((int)blockIdx.x < nfirst) panel_body(S, L, t, status, winv, smem);
   else if ((int)blockIdx.x < ntrsm_end) rows_body(S, L, t, winv, smem);
+  else if (t.c & kPanelRange) update_body<P, 6>(S, L, t, smem);
   else update_body<P, 1>(S, L, t, smem);
 }
 

@@ -281,7 +281,12 @@ int main(int argc, char** argv) {
           for (int64_t r = c; r < m && ok; ++r) ok = need_complete(idx(J, c, r), q) && solve_entry(idx(J, c, r), q);
       } else if (kind == K_UPD_INT || kind == K_UPD_EXT) {
         const bool ext = kind == K_UPD_EXT;
-        const int64_t kb = ext ? 0 : int64_t(t.c) * nb, ke = ext ? k : std::min<int64_t>(k, kb + nb);
+        // a tile over a range of panels (their adds atomic), or one panel
+        const bool range = !ext && (t.c & kPanelRange);
+        if (range && L.kind != K_FACTOR_LA) ok = fail("panel-range tile outside the one-launch panel rounds");
+        const int64_t np = range ? ((t.c >> 16) & 0xff) : 1;
+        const int64_t kb = ext ? 0 : int64_t(range ? (t.c & 0xffff) : t.c) * nb,
+                      ke = ext ? k : std::min<int64_t>(k, kb + np * nb);
         const int64_t colEnd = ext ? m : k;
         if (ext && t.b < k) ok = fail("external tile that starts inside the supernode's columns");
         const int64_t r1 = std::min<int64_t>(int64_t(t.a) + kTile, m), c1 = std::min<int64_t>(int64_t(t.b) + kTile, colEnd);
@@ -290,9 +295,9 @@ int main(int argc, char** argv) {
             for (int64_t s = kb; s < ke && ok; ++s) ok = need_solved(idx(J, s, r), q) && need_solved(idx(J, s, c), q);
             if (!ok) break;
             const int64_t e = ext ? target(J, c, r) : idx(J, c, r);
-            ok = on_write(acc, e, q, ext);
+            ok = on_write(acc, e, q, ext || range);
             if (ok && solved[e]) ok = fail("update of an entry that is already solved");
-            got[e] += 1;
+            got[e] += ext ? 1 : (int32_t)((ke - kb + nb - 1) / nb);
           }
       } else if (kind == K_UPD_RLB) {
         // one block pair tile: rows and columns consecutive indices of J,
@@ -505,17 +510,19 @@ int main(int argc, char** argv) {
   double fwd_bytes = 0, bwd_bytes = 0;
   for (const Launch& L : S.fwd_plan) fwd_bytes += L.bytes;
   for (const Launch& L : S.bwd_plan) bwd_bytes += L.bytes;
-  int64_t rlb_tasks = 0, fused_diag = 0;
+  int64_t rlb_tasks = 0, fused_diag = 0, range_tiles = 0;
   for (const Launch& L : S.factor_plan) {
     if (L.kind == K_UPD_RLB) rlb_tasks += L.ntasks;
-    if (L.kind == K_FACTOR_LA)
+    if (L.kind == K_FACTOR_LA) {
       for (int32_t q = 0; q < L.nfirst; ++q) fused_diag += S.tasks[L.off + q].c >= 3;
+      for (int32_t q = L.nfirst + L.ntrsm; q < L.ntasks; ++q) range_tiles += (S.tasks[L.off + q].c & kPanelRange) != 0;
+    }
   }
   std::printf("ok launches=%zu+%zu+%zu split_bwd=%lld fwd2=%lld small=%lld small_solve=%lld fwd_bytes=%.0f "
-              "bwd_bytes=%.0f storage=%lld colors=%lld si_launches=%zu rlb_blocks=%lld rlb_tasks=%lld fused_diag=%lld fork_probes=%lld medium=%lld\n",
+              "bwd_bytes=%.0f storage=%lld colors=%lld si_launches=%zu rlb_blocks=%lld rlb_tasks=%lld fused_diag=%lld fork_probes=%lld medium=%lld range_tiles=%lld\n",
               S.factor_plan.size(), S.fwd_plan.size(), S.bwd_plan.size(), (long long)bsplit, (long long)nfwd2,
               (long long)nsmall, (long long)nssolve, fwd_bytes, bwd_bytes, (long long)storage,
               (long long)S.max_colors, S.si_plan.size(), (long long)S.rlb_blocks, (long long)rlb_tasks,
-              (long long)fused_diag, (long long)fork_probes, (long long)nmedium);
+              (long long)fused_diag, (long long)fork_probes, (long long)nmedium, (long long)range_tiles);
   return 0;
 }

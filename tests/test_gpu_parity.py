@@ -110,11 +110,13 @@ def test_dense(n):
              0, 0, 64)
 
 
-@pytest.mark.parametrize("n,nb", [(150, 64), (150, 32), (300, 48), (333, 64), (400, 64)])
+@pytest.mark.parametrize("n,nb", [(150, 64), (150, 32), (300, 48), (333, 64), (400, 64), (1000, 64)])
 def test_dense_odd_panels(n, nb):
-    """One supernode whose panel count is odd, a ragged last panel, several
-    blocks of right-hand sides; with 64-column panels and six or seven of
-    them, several one-launch panel rounds with trailing update tiles."""
+    """One dense supernode (odd panel counts and a ragged last panel among
+    the cases), several blocks of right-hand sides; with 64-column panels and six, seven or 16
+    of them, several one-launch panel rounds with trailing update tiles
+    (at 16, column blocks entering the rounds' window with all their
+    finished panels at once)."""
     rng = np.random.default_rng(n + nb)
     G = rng.standard_normal((n, n))
     M = G @ G.T / n + np.eye(n)

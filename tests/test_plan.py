@@ -83,11 +83,15 @@ def test_elasticity(checker, tmp_path):
     _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, 8, 16)
 
 
-@pytest.mark.parametrize("n,nb", [(150, 64), (150, 16), (65, 64), (1, 64), (400, 64)])
+@pytest.mark.parametrize("n,nb", [(150, 64), (150, 16), (65, 64), (1, 64), (400, 64), (1200, 64)])
 def test_dense(checker, tmp_path, n, nb):
     cp = np.concatenate([[0], np.cumsum(np.arange(n, 0, -1))]).astype(np.int64)
     ri = np.concatenate([np.arange(j, n) for j in range(n)]).astype(np.int64)
-    _run(checker, tmp_path, n, cp, ri, None, 0, 0, nb)
+    out = _run(checker, tmp_path, n, cp, ri, None, 0, 0, nb)
+    if n >= 1200:
+        # 19 panels: the column blocks past the rounds' window take their
+        # finished panels in ranges when they enter it
+        assert int(out.split("range_tiles=")[1].split()[0]) > 0, out
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
