@@ -718,7 +718,9 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
       // A round's three sets touch disjoint entries and read only entries
       // the rounds before completed; round maxp holds the last row tiles.
       bool one_launch = fp_rounds && nb == kTile && maxp >= 2;
-      const int64_t win = kRoundWindow;
+      // (the deterministic schedule has no window: a block entering it would
+      // take several atomic ranges in one launch)
+      const int64_t win = S.deterministic ? 0 : kRoundWindow;
       for (int64_t p = 0; p < maxp && one_launch; ++p) one_launch = inl_of[p] != kTrsmRows;
       if (one_launch) {
         for (int64_t p = 0; p <= maxp; ++p) {

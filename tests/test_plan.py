@@ -92,6 +92,10 @@ def test_dense(checker, tmp_path, n, nb):
         # 19 panels: the column blocks past the rounds' window take their
         # finished panels in ranges when they enter it
         assert int(out.split("range_tiles=")[1].split()[0]) > 0, out
+        # the deterministic schedule has no window (one add per entry and
+        # launch)
+        out = _run(checker, tmp_path, n, cp, ri, None, 0, 0, nb, det=1)
+        assert int(out.split("range_tiles=")[1].split()[0]) == 0, out
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
