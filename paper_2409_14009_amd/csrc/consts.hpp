@@ -14,8 +14,8 @@ constexpr int kPanelRange = 1 << 30;
 constexpr int kRangePanels = 4;
 // The window: panel p - 2's update tiles in round p go to column blocks p ..
 // p + kRoundWindow - 1; the block after them enters (40^3 x 3, 111-panel
-// root: windows of 2 / 3 / 4 / 8 / 16 blocks 24.1 / 23.6 / 23.9 / 24.8 /
-// 25.1 ms against 25.7 ms without; ranges of 2 / 8 / 16 panels instead of 4:
+// root: windows of 2 / 3-4 / 8 / 16 blocks 24.1 / 23.8-23.9 / 24.8 / 25.1 ms
+// against 25.7 ms without; ranges of 2 / 8 / 16 panels instead of 4:
 // 24.1 / 24.7 / 28.3 ms).
 constexpr int kRoundWindow = 4;
 
