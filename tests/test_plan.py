@@ -78,6 +78,15 @@ def test_grid3d(checker, tmp_path, side, z, nb):
         assert int(out.split("small_solve=")[1].split()[0]) > 0, out
 
 
+def test_grid3d_root_past_the_window(checker, tmp_path):
+    """28^3: a 15-panel root separator, past the window of the one-launch
+    panel rounds, its column blocks taking their finished panels in
+    ranges when they enter it (several ranges per block)."""
+    p = gen.make_config(1, side=28)
+    out = _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, 8, 64)
+    assert int(out.split("range_tiles=")[1].split()[0]) > 0, out
+
+
 def test_elasticity(checker, tmp_path):
     p = gen.make_config(2, side=5)
     _run(checker, tmp_path, p.n, p.colptr, p.rowind, p.perm, 0, 8, 16)
