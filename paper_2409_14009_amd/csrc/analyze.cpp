@@ -743,13 +743,14 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowind, const int64
           // wait)
           if (p >= 2)
             for (int32_t J : lev) {
-              const int64_t cend = win > 0 ? std::min<int64_t>(npan(J), p + win) : npan(J);
+              const int64_t cend = win > 0 && npan(J) <= 0xffff ? std::min<int64_t>(npan(J), p + win) : npan(J);
               for (int64_t cb = p; cb < cend; ++cb) {
                 const int64_t c0 = cb * nb;
                 for (int64_t r0 = cb == p ? c0 + kpan(J, p) : c0; r0 < M(J); r0 += kTile)
                   S.tasks.push_back({J, (int32_t)r0, (int32_t)c0, (int32_t)(p - 2)});
               }
-              if (win > 0 && p + win < npan(J)) {
+              // (a range's first panel is held in 16 bits: no window past that)
+              if (win > 0 && p + win < npan(J) && npan(J) <= 0xffff) {
                 const int64_t c0 = (p + win) * nb;
                 for (int64_t s0 = 0; s0 <= p - 2; s0 += kRangePanels) {
                   const int64_t ns = std::min<int64_t>(kRangePanels, p - 1 - s0);
