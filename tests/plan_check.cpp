@@ -37,6 +37,8 @@ struct Access {
 
 int64_t g_launch = 0;
 std::string g_err;
+// per entry: side launches forked and not yet replayed that add into it
+std::vector<int32_t> g_pend;
 bool g_det = false;  // deterministic schedule: not even two atomic adds per entry and launch
 
 bool fail(const std::string& m) {
@@ -52,6 +54,7 @@ bool on_read(Access& A, int64_t e, int32_t task) {
 }
 
 bool on_write(Access& A, int64_t e, int32_t task, bool atomic) {
+  if (!atomic && g_pend[e] > 0) return fail("a write of an entry a launch on another stream adds into");
   if (A.rl[e] == g_launch && A.rt[e] != task) return fail("write of an entry another task of the launch reads");
   if (A.wl[e] == g_launch && A.wt[e] != task && !(atomic && A.wa[e] && !g_det))
     return fail(g_det ? "two adds into one entry in one launch of a deterministic schedule" : "two writers in one launch");
@@ -147,7 +150,9 @@ int main(int argc, char** argv) {
       if (L.nfirst < 0 || L.nfirst > L.ntasks) ok = fail("a launch's leading-task count exceeds its tasks");
   // a launch marked `side` (external updates of level v) runs beside the
   // launches of level v + 1 and is joined before level v + 2: it is replayed
-  // at that point, after everything it may overlap with
+  // at that point, after everything it may overlap with, and between fork
+  // and join no launch may write (other than by atomic adds) an entry it
+  // adds into.
   // The side stream forks before the near external launch of the same level
   // when that launch directly precedes it (both read the same finished
   // panels and write disjoint ancestors): a probe entry at the fork point
@@ -174,6 +179,24 @@ int main(int argc, char** argv) {
     order.push_back({&L, false});
   }
   for (const Launch* Lp : pending) order.push_back({Lp, false});
+  // every entry an external tile (or RLB block tile) of launch L adds into
+  auto side_targets = [&](const Launch& L, int32_t d) {
+    const int64_t msk = (int64_t(1) << 25) - 1;
+    for (int32_t q = 0; q < L.ntasks; ++q) {
+      const Task& t = S.tasks[L.off + q];
+      const int64_t m = M(t.J);
+      int64_t r0 = t.a, c0 = t.b, nr = kTile, nc = kTile;
+      if (L.kind == K_UPD_RLB) {
+        r0 = t.a & msk; nr = (int64_t(t.a) >> 25) + 1; c0 = t.b & msk; nc = (int64_t(t.b) >> 25) + 1;
+      }
+      for (int64_t c = c0; c < std::min<int64_t>(c0 + nc, m); ++c)
+        for (int64_t r = std::max(r0, c); r < std::min<int64_t>(r0 + nr, m); ++r) {
+          const int64_t e = target(t.J, c, r);
+          if (e >= 0) g_pend[e] += d;
+        }
+    }
+  };
+  g_pend.assign(storage, 0);
   int64_t fork_probes = 0;
   for (const auto& op : order) {
     const Launch& L = *op.first;
@@ -186,8 +209,10 @@ int main(int argc, char** argv) {
             if (!solved[idx(J, s, r)]) ok = fail("side stream forked before the panel it reads is solved");
       }
       if (!ok) break;
+      side_targets(L, 1);
       continue;
     }
+    if (L.side) side_targets(L, -1);
     ++g_launch;
     if (L.side && L.kind != K_UPD_EXT && L.kind != K_UPD_RLB) ok = fail("side launch that is not an external update");
     for (int32_t q = 0; q < L.ntasks && ok; ++q) {
