@@ -1,4 +1,4 @@
-"""Host-resident factorization on the GPU machine: supernodes at or above the
+"""Host-resident factorization with one MI355X: supernodes at or above the
 size threshold factored on the device (panel kernels on a copy of the one
 supernode), their update matrices computed on the device in column blocks
 that fit the device budget and added into the ancestors by the host; the
