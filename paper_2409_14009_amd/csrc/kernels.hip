@@ -774,6 +774,12 @@ template <> struct UpdPrec<1> {
 // bf16 operands, fp32 accumulation: one 16x16x16 MFMA per K chunk of 16;
 // staged row-major, four consecutive k of a row packed in 8 bytes
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+// two groups of four bf16 as the eight-value operand of the double-K MFMA
+__device__ __forceinline__ bf8 pair_bf8(s4 lo, s4 hi) {
+  struct Two { s4 lo, hi; };
+  return __builtin_bit_cast(bf8, Two{lo, hi});
+}
 template <> struct UpdPrec<2> {
   using T = s4;
   using Acc = f4;
@@ -898,16 +904,20 @@ __device__ __forceinline__ void update_body(const DevSym& S, double* __restrict_
       }
       __syncthreads();
       if (kk + UKC < ke) fetch(kk + UKC);
-      // k half h: lane (li, lk) holds A[row li][k = 16 h + 4 lk .. + 3],
-      // group 4 h + lk of its row; B likewise
-#pragma unroll
-      for (int h = 0; h < UKC / 16; ++h) {
-        const s4 a0 = As[(wr + li) * G2 + 4 * h + lk], a1 = As[(wr + 16 + li) * G2 + 4 * h + lk];
-        const s4 b0 = Bs[(wc + li) * G2 + 4 * h + lk], b1 = Bs[(wc + 16 + li) * G2 + 4 * h + lk];
-        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][1], 0, 0, 0);
+      // gfx950's double-K MFMA (16 x 16 x 32): lane (li, lk) gives eight
+      // values of row li, here groups lk and 4 + lk (k = 4 lk .. + 3 and
+      // 16 + 4 lk .. + 3); A and B take the same k from each lane, so the
+      // product sums all 32 k whichever order the unit assigns them
+      static_assert(UKC == 32, "one double-K MFMA per chunk");
+      {
+        const bf8 a0 = pair_bf8(As[(wr + li) * G2 + lk], As[(wr + li) * G2 + 4 + lk]);
+        const bf8 a1 = pair_bf8(As[(wr + 16 + li) * G2 + lk], As[(wr + 16 + li) * G2 + 4 + lk]);
+        const bf8 b0 = pair_bf8(Bs[(wc + li) * G2 + lk], Bs[(wc + li) * G2 + 4 + lk]);
+        const bf8 b1 = pair_bf8(Bs[(wc + 16 + li) * G2 + lk], Bs[(wc + 16 + li) * G2 + 4 + lk]);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
       }
       __syncthreads();
     }
